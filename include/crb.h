@@ -1,0 +1,188 @@
+/*
+ * crb.h -- C ABI of libcrb, an MI355X (gfx950) implementation of the per-iteration
+ * L.A.Cosmic cosmic-ray detection and cleaning pass that CRBLASTER distributes over
+ * subimages (K. J. Mighell, "CRBLASTER: A Parallel-Processing Computational
+ * Framework for Embarrassingly-Parallel Image-Analysis Algorithms", Section 5 for
+ * the algorithm and its parameters gain, read noise, sigfrac and objlim; Section 6
+ * for its use on subimages with overlapping borders).
+ *
+ * One iteration k on the image J_k with cumulative mask M_{k-1}:
+ *   L+  = 2x2 mean of the clipped (>= 0) 4-neighbour Laplacian of the 2x
+ *         block-replicated image;
+ *   N   = sqrt(gain * m5 + readnoise^2) / gain with m5 = med5(J) + sky
+ *         (m5 <= 0 is replaced by 1e-4);
+ *   S   = L+ / (2 N),  S' = S - med5(S);
+ *   F^  = max((med3(J) - med7(med3(J))) / N, 0.01);
+ *   A   = [S' > sigclip] and [S' / F^ > objlim];
+ *   G1  = dilate3x3(A) and [S' > sigclip];
+ *   G2  = dilate3x3(G1) and [S' > sigfrac * sigclip];
+ *   n_k = #(G2 and not M_{k-1});  M_k = M_{k-1} or G2;
+ *   J_{k+1}(p) = median of the unflagged J_k in the 5x5 window of p, for p in M_k
+ *         (even count: mean of the two middle values; no unflagged pixel: J_k(p)).
+ * Every stencil reads clamped ("nearest") indices; the paper leaves the outer
+ * pixels undefined (Section 6.1).  The loop runs up to niter iterations (the paper:
+ * typically 4) and, unless disabled, stops after the first iteration with n_k = 0,
+ * which is result-neutral because that iteration reproduces its input.
+ *
+ * Numerics: pixels are FP32.  Medians are exact selections.  L+, N, S, S', F^ and
+ * every threshold test are evaluated in IEEE binary64 (the paper's subimage data
+ * are doubles, Section 6.2), so the detection decisions for a given J_k do not
+ * depend on rounding order.  A replaced pixel with an even number of unflagged
+ * neighbours receives the binary64 mean of the two middle values rounded to FP32.
+ *
+ * Conventions for every entry point:
+ *   - image pointers are DEVICE pointers on the current HIP device, row-major,
+ *     contiguous, pitch == W; masks are uint8 0/1;
+ *   - the caller owns every buffer it passes; the library owns only internal
+ *     workspace (device memory it allocates and keeps per stream until
+ *     crb_release_workspace or process exit);
+ *   - calls are stream-ordered and asynchronous unless stated otherwise; the
+ *     returned status covers argument validation and launch errors only;
+ *   - on any status other than CRB_OK nothing has been enqueued, and
+ *     crb_last_error() returns a message for the calling thread;
+ *   - pixel values must be finite (unspecified output otherwise);
+ *   - out_clean may equal img (in-place cleaning); partial overlap is not allowed;
+ *   - calls are thread-safe; two calls on one stream from different threads are
+ *     serialised by the library.
+ */
+#ifndef CRB_H
+#define CRB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CRB_OK = 0,
+    CRB_EINVAL = -1,   /* invalid argument (null pointer, size < 1, parameter out of range) */
+    CRB_ENOMEM = -2,   /* device allocation failed                                          */
+    CRB_EDEVICE = -3,  /* HIP runtime or launch error                                       */
+    CRB_ETOOBIG = -4,  /* H * W exceeds 2^31 - 1 pixels                                     */
+    CRB_EBUSY = -5     /* serving: no admission possible now (retry later)                  */
+} crb_status;
+
+/* crb_frame.flags */
+#define CRB_FLAG_NO_EARLY_STOP 1   /* always run niter iterations */
+
+/* Options for crb_set_option. */
+#define CRB_OPT_EARLY_STOP 1       /* value 1 (default) or 0: early stop in crb_lacosmic */
+
+/*
+ * Clean one frame (the method above).
+ *   img        device, H*W FP32 input (read only unless out_clean == img)
+ *   H, W       >= 1, H*W <= 2^31-1
+ *   gain       electrons per ADU, > 0
+ *   readnoise  electrons, >= 0
+ *   sky        sky level already subtracted from img (ADU); enters the noise only
+ *   sigclip    detection limit (> 0), sigfrac in [0, 1], objlim > 0
+ *   niter      >= 0 (0 copies img and clears the mask)
+ *   out_clean  device, H*W FP32 cleaned image
+ *   out_mask   device, H*W uint8 cumulative mask
+ * Runs on the calling thread's stream (crb_set_stream).  All parameters must be
+ * finite.
+ */
+crb_status crb_lacosmic(const float *img, int32_t H, int32_t W, float gain, float readnoise,
+                        float sky, float sigclip, float sigfrac, float objlim, int32_t niter,
+                        float *out_clean, uint8_t *out_mask);
+
+/* One frame of a batch (host struct; pointers are device pointers). */
+typedef struct {
+    const float *img;     /* input  (device, H*W FP32)                           */
+    float *out_clean;     /* output (device, H*W FP32); may equal img            */
+    uint8_t *out_mask;    /* output (device, H*W uint8)                          */
+    int32_t H, W;
+    float gain, readnoise, sky, sigclip, sigfrac, objlim;
+    int32_t niter;
+    int32_t flags;        /* CRB_FLAG_*                                          */
+    int32_t iters_run;    /* output: iterations executed                        */
+    int32_t reserved;
+    int64_t n_flagged;    /* output: pixels in the final mask                   */
+} crb_frame;
+
+/*
+ * Clean n independent frames of any sizes in one batched pass (one launch per
+ * stage and iteration over a (frame, tile) work list).  Each frame's outputs are
+ * bit-identical to a crb_lacosmic call with the same parameters.  Synchronous:
+ * returns after the batch has completed on hip_stream (NULL: default stream) and
+ * has written iters_run and n_flagged into frames[].
+ */
+crb_status crb_lacosmic_batched(crb_frame *frames, int32_t n, void *hip_stream);
+
+/*
+ * Batch plans: the batched pass prepared once (work lists, descriptor table,
+ * workspace) and captured as a HIP graph, then replayed.  The frames' device
+ * pointers and sizes are fixed by the plan; the pixel contents may change between
+ * runs.  crb_plan_run is asynchronous on its stream; crb_plan_stats waits for the
+ * stream and fills iters_run / n_flagged of frames (n entries, same order).
+ */
+typedef struct crb_plan crb_plan;
+crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
+                           int32_t use_graph, crb_plan **out_plan);
+crb_status crb_plan_run(crb_plan *plan);
+crb_status crb_plan_stats(crb_plan *plan, crb_frame *frames, int32_t n);
+void crb_plan_destroy(crb_plan *plan);
+
+/* Per-thread stream used by crb_lacosmic (NULL: default stream). */
+crb_status crb_set_stream(void *hip_stream);
+/* Library-wide option (CRB_OPT_*). */
+crb_status crb_set_option(int32_t key, int64_t value);
+/* Message of the calling thread's last error ("" if none). */
+const char *crb_last_error(void);
+/* Device workspace a frame of H x W needs beyond its input and outputs (bytes). */
+size_t crb_workspace_bytes(int32_t H, int32_t W);
+/* Free the workspace cached for hip_stream (waits for the stream first). */
+crb_status crb_release_workspace(void *hip_stream);
+
+/*
+ * Serving: continuous (iteration-level) batching of frames that arrive over time.
+ * A server owns device memory up to hbm_budget bytes for admitted frames' state
+ * (image, mask and workspace) and runs rounds: each round performs one iteration
+ * for every admitted frame, so frames at different iterations share the GPU.
+ * Frames leave after niter iterations or an early stop; their results are copied
+ * to the caller's host buffers and a completion is reported.
+ *   crb_server_submit: host FP32 image (copied at once into pinned staging), host
+ *     outputs written at completion; returns CRB_EBUSY when the request can never
+ *     fit the budget.  Requests wait in FIFO order until slots and memory allow.
+ *   crb_server_poll: enqueue the next round when the previous one has finished,
+ *     admit waiting requests, retire finished frames; never blocks.  Writes up to
+ *     max_done completed request ids to done_ids and their latency (seconds from
+ *     submit to completion) to done_latency; returns the count in *n_done.
+ *   crb_server_pending: requests submitted and not yet retired.
+ */
+typedef struct crb_server crb_server;
+crb_status crb_server_create(size_t hbm_budget, int32_t max_slots, crb_server **out);
+crb_status crb_server_submit(crb_server *srv, const float *host_img, int32_t H, int32_t W,
+                             float gain, float readnoise, float sky, float sigclip,
+                             float sigfrac, float objlim, int32_t niter, float *host_clean,
+                             uint8_t *host_mask, int64_t *out_id);
+crb_status crb_server_poll(crb_server *srv, int64_t *done_ids, double *done_latency,
+                           int32_t max_done, int32_t *n_done);
+int32_t crb_server_pending(crb_server *srv);
+void crb_server_destroy(crb_server *srv);
+
+/* ---- entry points for parity tests ------------------------------------------ */
+
+/*
+ * Run exactly one iteration on a given (J_k, M_{k-1}) (device pointers): writes
+ * G2 (uint8, selected this iteration), M_k, J_{k+1} and n_k (device int64).
+ * params supplies H, W, gain, readnoise, sky, sigclip, sigfrac, objlim (its
+ * pointers are ignored).  Runs on the calling thread's stream.
+ */
+crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_frame *params,
+                             uint8_t *out_G2, uint8_t *out_M, float *out_J_next,
+                             int64_t *out_n_new);
+/* Detection stage only: code = A | [S' > sigclip] << 1 | [S' > sigfrac sigclip] << 2. */
+crb_status crb_debug_detect(const float *J, const crb_frame *params, uint8_t *out_codes);
+/* Clamped (2r+1)^2 median filter, r in {1, 2, 3}, by the kernels' networks. */
+crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out);
+/* Elementwise binary64 sqrt(x) and x / y on the device (rounding checks). */
+crb_status crb_debug_fp64(const double *x, const double *y, int32_t n, double *out_sqrt,
+                          double *out_div);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CRB_H */

@@ -1,0 +1,262 @@
+"""ctypes binding of libcrb (include/crb.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; PyTorch supplies device memory
+and streams.  Import fails loudly when libcrb.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrb.so")
+
+CRB_FLAG_NO_EARLY_STOP = 1
+CRB_OPT_EARLY_STOP = 1
+STATUS = {0: "CRB_OK", -1: "CRB_EINVAL", -2: "CRB_ENOMEM", -3: "CRB_EDEVICE",
+          -4: "CRB_ETOOBIG", -5: "CRB_EBUSY"}
+
+EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_plan_create", "crb_plan_run",
+           "crb_plan_stats", "crb_plan_destroy", "crb_set_stream", "crb_set_option",
+           "crb_last_error", "crb_workspace_bytes", "crb_release_workspace",
+           "crb_server_create", "crb_server_submit", "crb_server_poll", "crb_server_pending",
+           "crb_server_destroy", "crb_debug_iterate", "crb_debug_detect", "crb_debug_median",
+           "crb_debug_fp64"]
+
+
+class CrbError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Frame(ctypes.Structure):
+    """Mirror of ``crb_frame``."""
+    _fields_ = [("img", ctypes.c_void_p), ("out_clean", ctypes.c_void_p),
+                ("out_mask", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("gain", ctypes.c_float), ("readnoise", ctypes.c_float), ("sky", ctypes.c_float),
+                ("sigclip", ctypes.c_float), ("sigfrac", ctypes.c_float),
+                ("objlim", ctypes.c_float), ("niter", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("iters_run", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_flagged", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libcrb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libcrb.so not found at {LIB_PATH}: build it first "
+                           f"(python -m paper_1008_2192_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.crb_lacosmic.argtypes = [vp, i32, i32, f32, f32, f32, f32, f32, f32, i32, vp, vp]
+    L.crb_lacosmic_batched.argtypes = [ctypes.POINTER(Frame), i32, vp]
+    L.crb_plan_create.argtypes = [ctypes.POINTER(Frame), i32, vp, i32, ctypes.POINTER(vp)]
+    L.crb_plan_run.argtypes = [vp]
+    L.crb_plan_stats.argtypes = [vp, ctypes.POINTER(Frame), i32]
+    L.crb_plan_destroy.argtypes = [vp]
+    L.crb_plan_destroy.restype = None
+    L.crb_set_stream.argtypes = [vp]
+    L.crb_set_option.argtypes = [i32, i64]
+    L.crb_last_error.argtypes = []
+    L.crb_last_error.restype = ctypes.c_char_p
+    L.crb_workspace_bytes.argtypes = [i32, i32]
+    L.crb_workspace_bytes.restype = ctypes.c_size_t
+    L.crb_release_workspace.argtypes = [vp]
+    L.crb_server_create.argtypes = [ctypes.c_size_t, i32, ctypes.POINTER(vp)]
+    L.crb_server_submit.argtypes = [vp, vp, i32, i32, f32, f32, f32, f32, f32, f32, i32, vp, vp,
+                                    ctypes.POINTER(i64)]
+    L.crb_server_poll.argtypes = [vp, vp, vp, i32, ctypes.POINTER(i32)]
+    L.crb_server_pending.argtypes = [vp]
+    L.crb_server_pending.restype = i32
+    L.crb_server_destroy.argtypes = [vp]
+    L.crb_server_destroy.restype = None
+    L.crb_debug_iterate.argtypes = [vp, vp, ctypes.POINTER(Frame), vp, vp, vp, vp]
+    L.crb_debug_detect.argtypes = [vp, ctypes.POINTER(Frame), vp]
+    L.crb_debug_median.argtypes = [vp, i32, i32, i32, vp]
+    L.crb_debug_fp64.argtypes = [vp, vp, i32, vp, vp]
+    for name in ("crb_lacosmic", "crb_lacosmic_batched", "crb_plan_create", "crb_plan_run",
+                 "crb_plan_stats", "crb_set_stream", "crb_set_option", "crb_release_workspace",
+                 "crb_server_create", "crb_server_submit", "crb_server_poll",
+                 "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(fn: str, status: int) -> None:
+    if status != 0:
+        msg = lib().crb_last_error()
+        raise CrbError(fn, status, msg.decode() if msg else "")
+
+
+def _stream(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dev2d(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype or t.dim() != 2 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 2-D {dtype} tensor")
+    return t
+
+
+def set_stream(stream: Optional[torch.cuda.Stream] = None) -> None:
+    check("crb_set_stream", lib().crb_set_stream(ctypes.c_void_p(_stream(stream))))
+
+
+def lacosmic(img: torch.Tensor, gain: float, readnoise: float, sky: float = 0.0,
+             sigclip: float = 4.5, sigfrac: float = 0.3, objlim: float = 4.0, niter: int = 4,
+             out_clean: Optional[torch.Tensor] = None, out_mask: Optional[torch.Tensor] = None,
+             early_stop: bool = True, stream: Optional[torch.cuda.Stream] = None):
+    """crb_lacosmic on device tensors; returns (clean float32, mask uint8)."""
+    _dev2d(img, torch.float32, "img")
+    H, W = img.shape
+    if out_clean is None:
+        out_clean = torch.empty_like(img)
+    if out_mask is None:
+        out_mask = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    _dev2d(out_clean, torch.float32, "out_clean")
+    _dev2d(out_mask, torch.uint8, "out_mask")
+    L = lib()
+    set_stream(stream)
+    check("crb_set_option", L.crb_set_option(CRB_OPT_EARLY_STOP, 1 if early_stop else 0))
+    check("crb_lacosmic", L.crb_lacosmic(img.data_ptr(), H, W, gain, readnoise, sky, sigclip,
+                                         sigfrac, objlim, niter, out_clean.data_ptr(),
+                                         out_mask.data_ptr()))
+    return out_clean, out_mask
+
+
+def make_frames(items: Sequence[dict]) -> "ctypes.Array[Frame]":
+    """items: dicts with img, out_clean, out_mask tensors and the parameters."""
+    arr = (Frame * len(items))()
+    for i, it in enumerate(items):
+        img = _dev2d(it["img"], torch.float32, "img")
+        oc = _dev2d(it["out_clean"], torch.float32, "out_clean")
+        om = _dev2d(it["out_mask"], torch.uint8, "out_mask")
+        H, W = img.shape
+        arr[i] = Frame(img.data_ptr(), oc.data_ptr(), om.data_ptr(), H, W, it["gain"],
+                       it["readnoise"], it.get("sky", 0.0), it.get("sigclip", 4.5),
+                       it.get("sigfrac", 0.3), it.get("objlim", 4.0), it.get("niter", 4),
+                       CRB_FLAG_NO_EARLY_STOP if not it.get("early_stop", True) else 0, 0, 0, 0)
+    return arr
+
+
+def lacosmic_batched(items: Sequence[dict], stream: Optional[torch.cuda.Stream] = None
+                     ) -> List[dict]:
+    """crb_lacosmic_batched; returns per-frame dict(iters_run, n_flagged)."""
+    arr = make_frames(items)
+    check("crb_lacosmic_batched",
+          lib().crb_lacosmic_batched(arr, len(items), ctypes.c_void_p(_stream(stream))))
+    return [dict(iters_run=f.iters_run, n_flagged=f.n_flagged) for f in arr]
+
+
+class Plan:
+    """A graph-captured batch plan (crb_plan_*) on a stream of its own, ordered
+    after the caller's current stream at each run and before it afterwards."""
+
+    def __init__(self, items: Sequence[dict], use_graph: bool = True):
+        self.items = list(items)
+        self.frames = make_frames(self.items)
+        self.handle = ctypes.c_void_p()
+        self.stream = torch.cuda.Stream()
+        check("crb_plan_create", lib().crb_plan_create(
+            self.frames, len(self.items), ctypes.c_void_p(self.stream.cuda_stream),
+            1 if use_graph else 0, ctypes.byref(self.handle)))
+
+    def run(self) -> None:
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        check("crb_plan_run", lib().crb_plan_run(self.handle))
+        cur.wait_stream(self.stream)
+
+    def stats(self) -> List[dict]:
+        check("crb_plan_stats", lib().crb_plan_stats(self.handle, self.frames, len(self.items)))
+        return [dict(iters_run=f.iters_run, n_flagged=f.n_flagged) for f in self.frames]
+
+    def close(self) -> None:
+        if self.handle:
+            lib().crb_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _params_frame(H: int, W: int, gain, readnoise, sky=0.0, sigclip=4.5, sigfrac=0.3,
+                  objlim=4.0) -> Frame:
+    return Frame(None, None, None, H, W, gain, readnoise, sky, sigclip, sigfrac, objlim, 1, 0,
+                 0, 0, 0)
+
+
+def debug_iterate(J: torch.Tensor, M_prev: torch.Tensor, gain, readnoise, sky=0.0,
+                  sigclip=4.5, sigfrac=0.3, objlim=4.0,
+                  stream: Optional[torch.cuda.Stream] = None):
+    """One iteration on (J_k, M_{k-1}); returns (G2, M_k, J_{k+1}, n_k tensor)."""
+    _dev2d(J, torch.float32, "J")
+    _dev2d(M_prev, torch.uint8, "M_prev")
+    H, W = J.shape
+    G2 = torch.empty((H, W), dtype=torch.uint8, device=J.device)
+    M = torch.empty_like(G2)
+    Jn = torch.empty_like(J)
+    n = torch.zeros(1, dtype=torch.int64, device=J.device)
+    p = _params_frame(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim)
+    set_stream(stream)
+    check("crb_debug_iterate", lib().crb_debug_iterate(J.data_ptr(), M_prev.data_ptr(),
+                                                       ctypes.byref(p), G2.data_ptr(),
+                                                       M.data_ptr(), Jn.data_ptr(),
+                                                       n.data_ptr()))
+    return G2, M, Jn, n
+
+
+def debug_detect(J: torch.Tensor, gain, readnoise, sky=0.0, sigclip=4.5, sigfrac=0.3,
+                 objlim=4.0, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    _dev2d(J, torch.float32, "J")
+    H, W = J.shape
+    codes = torch.empty((H, W), dtype=torch.uint8, device=J.device)
+    p = _params_frame(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim)
+    set_stream(stream)
+    check("crb_debug_detect", lib().crb_debug_detect(J.data_ptr(), ctypes.byref(p),
+                                                     codes.data_ptr()))
+    return codes
+
+
+def debug_median(x: torch.Tensor, r: int, stream: Optional[torch.cuda.Stream] = None
+                 ) -> torch.Tensor:
+    _dev2d(x, torch.float32, "x")
+    out = torch.empty_like(x)
+    set_stream(stream)
+    check("crb_debug_median", lib().crb_debug_median(x.data_ptr(), x.shape[0], x.shape[1], r,
+                                                     out.data_ptr()))
+    return out
+
+
+def debug_fp64(x: torch.Tensor, y: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    if x.dtype != torch.float64 or y.dtype != torch.float64 or not x.is_cuda or not y.is_cuda:
+        raise ValueError("x, y must be float64 CUDA tensors")
+    x, y = x.contiguous(), y.contiguous()
+    if x.numel() != y.numel():
+        raise ValueError("x and y differ in size")
+    s = torch.empty_like(x)
+    d = torch.empty_like(x)
+    set_stream(stream)
+    check("crb_debug_fp64", lib().crb_debug_fp64(x.data_ptr(), y.data_ptr(), x.numel(),
+                                                 s.data_ptr(), d.data_ptr()))
+    return s, d
+
+
+def workspace_bytes(H: int, W: int) -> int:
+    return int(lib().crb_workspace_bytes(H, W))

@@ -1,0 +1,614 @@
+// C ABI of libcrb: argument validation, per-stream workspace, single-frame and
+// batched passes, graph-captured batch plans and the parity-test entry points.
+// The serving loop lives in server.hip.
+#include "api_internal.h"
+
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace crb {
+
+static thread_local std::string t_err;
+static thread_local hipStream_t t_stream = nullptr;
+static std::atomic<int> g_early_stop{1};
+
+crb_status fail(crb_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return st;
+}
+
+crb_status ok() {
+    t_err.clear();
+    return CRB_OK;
+}
+
+// bit-level test: robust under any floating-point compilation flags
+static bool finite32(float x) {
+    uint32_t u;
+    memcpy(&u, &x, sizeof(u));
+    return ((u >> 23) & 0xffu) != 0xffu;
+}
+
+crb_status check_frame_args(int32_t H, int32_t W, float gain, float readnoise, float sky,
+                            float sigclip, float sigfrac, float objlim, int32_t niter) {
+    if (H < 1 || W < 1)
+        return fail(CRB_EINVAL, "image size %d x %d: both must be >= 1", H, W);
+    if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX)
+        return fail(CRB_ETOOBIG, "image of %lld pixels exceeds 2^31-1", (long long)H * W);
+    if (!finite32(gain) || !finite32(readnoise) || !finite32(sky) || !finite32(sigclip) ||
+        !finite32(sigfrac) || !finite32(objlim))
+        return fail(CRB_EINVAL, "parameters must be finite");
+    if (!(gain > 0.0f))
+        return fail(CRB_EINVAL, "gain must be > 0 (got %g)", (double)gain);
+    if (!(readnoise >= 0.0f))
+        return fail(CRB_EINVAL, "readnoise must be >= 0 (got %g)", (double)readnoise);
+    if (!(sigclip > 0.0f))
+        return fail(CRB_EINVAL, "sigclip must be > 0 (got %g)", (double)sigclip);
+    if (!(sigfrac >= 0.0f && sigfrac <= 1.0f))
+        return fail(CRB_EINVAL, "sigfrac must lie in [0, 1] (got %g)", (double)sigfrac);
+    if (!(objlim > 0.0f))
+        return fail(CRB_EINVAL, "objlim must be > 0 (got %g)", (double)objlim);
+    if (niter < 0 || niter > kMaxIter)
+        return fail(CRB_EINVAL, "niter must lie in [0, %d] (got %d)", kMaxIter, niter);
+    return CRB_OK;
+}
+
+static bool ranges_overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+    return pa < pb + nb && pb < pa + na;
+}
+
+crb_status check_buffers(const float *img, const float *clean, const uint8_t *mask,
+                         size_t npix) {
+    if (!img || !clean || !mask)
+        return fail(CRB_EINVAL, "null image, output or mask pointer");
+    if (img != clean && ranges_overlap(img, npix * 4, clean, npix * 4))
+        return fail(CRB_EINVAL, "out_clean partially overlaps img");
+    if (ranges_overlap(mask, npix, img, npix * 4) || ranges_overlap(mask, npix, clean, npix * 4))
+        return fail(CRB_EINVAL, "out_mask overlaps an image buffer");
+    return CRB_OK;
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+FrameWs ws_layout(int32_t H, int32_t W) {
+    const size_t n = (size_t)H * (size_t)W;
+    FrameWs L;
+    L.codes = 0;
+    L.list = align_up(L.codes + n, 256);
+    L.nnew = align_up(L.list + 4 * n, 256);
+    L.listlen = align_up(L.nnew + 8 * (size_t)kMaxIter, 256);
+    L.total = align_up(L.listlen + 4 * (size_t)kMaxIter, 256);
+    return L;
+}
+
+DevFrame make_devframe(const float *img, float *J, uint8_t *mask, char *ws, const FrameWs &L,
+                       int32_t H, int32_t W, float gain, float readnoise, float sky,
+                       float sigclip, float sigfrac, float objlim, int32_t niter, int32_t flags) {
+    DevFrame f;
+    memset(&f, 0, sizeof(f));
+    f.img = img;
+    f.J = J;
+    f.mask = mask;
+    f.codes = reinterpret_cast<uint8_t *>(ws + L.codes);
+    f.g2 = nullptr;
+    f.list = reinterpret_cast<uint32_t *>(ws + L.list);
+    f.nnew = reinterpret_cast<unsigned long long *>(ws + L.nnew);
+    f.listlen = reinterpret_cast<unsigned int *>(ws + L.listlen);
+    f.H = H;
+    f.W = W;
+    f.gain = gain;
+    f.readnoise = readnoise;
+    f.sky = sky;
+    f.sigclip = sigclip;
+    f.sigfrac = sigfrac;
+    f.objlim = objlim;
+    f.niter = niter;
+    f.flags = flags;
+    f.k = 0;
+    return f;
+}
+
+int replace_grid(size_t npix) {
+    size_t g = npix / 4096;
+    if (g < 1)
+        g = 1;
+    if (g > 2048)
+        g = 2048;
+    return (int)g;
+}
+
+crb_status hip_status(hipError_t e, const char *what) {
+    if (e == hipSuccess)
+        return CRB_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(CRB_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(CRB_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// per-(device, stream) workspace
+// ---------------------------------------------------------------------------
+
+struct Workspace {
+    std::mutex mu;
+    char *buf = nullptr;
+    size_t cap = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+};
+
+static std::mutex g_ws_mu;
+static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
+
+static crb_status ws_get(hipStream_t s, Workspace **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_status(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_ws_mu);
+    auto key = std::make_pair(dev, s);
+    auto it = g_ws.find(key);
+    if (it == g_ws.end()) {
+        Workspace *w = new (std::nothrow) Workspace();
+        if (!w)
+            return fail(CRB_ENOMEM, "host allocation failed");
+        w->device = dev;
+        w->stream = s;
+        it = g_ws.emplace(key, w).first;
+    }
+    *out = it->second;
+    return CRB_OK;
+}
+
+// caller holds ws->mu
+static crb_status ws_reserve(Workspace *ws, size_t bytes) {
+    if (ws->cap >= bytes)
+        return CRB_OK;
+    if (ws->buf) {
+        hipError_t e = hipStreamSynchronize(ws->stream);
+        if (e != hipSuccess)
+            return hip_status(e, "hipStreamSynchronize");
+        (void)hipFree(ws->buf);
+        ws->buf = nullptr;
+        ws->cap = 0;
+    }
+    const size_t want = align_up(bytes, (size_t)1 << 20);
+    hipError_t e = hipMalloc((void **)&ws->buf, want);
+    if (e != hipSuccess) {
+        ws->buf = nullptr;
+        (void)hipGetLastError();
+        return fail(CRB_ENOMEM, "workspace of %zu bytes: %s", want, hipGetErrorString(e));
+    }
+    ws->cap = want;
+    return CRB_OK;
+}
+
+// enqueue niter iterations for one frame whose DevFrame is complete
+static crb_status enqueue_single(const DevFrame &f, bool zero_mask, hipStream_t s) {
+    const size_t npix = (size_t)f.H * (size_t)f.W;
+    hipError_t e = launch_init(nullptr, 1, f, npix, zero_mask, s);
+    for (int k = 1; e == hipSuccess && k <= f.niter; ++k) {
+        e = launch_detect(nullptr, nullptr, 0, f, k, s);
+        if (e == hipSuccess)
+            e = launch_grow(nullptr, nullptr, 0, f, k, s);
+        if (e == hipSuccess)
+            e = launch_replace(nullptr, 1, f, k, replace_grid(npix), s);
+    }
+    return hip_status(e, "kernel launch");
+}
+
+}  // namespace crb
+
+using namespace crb;
+
+extern "C" {
+
+crb_status crb_set_stream(void *hip_stream) {
+    t_stream = (hipStream_t)hip_stream;
+    return ok();
+}
+
+crb_status crb_set_option(int32_t key, int64_t value) {
+    if (key == CRB_OPT_EARLY_STOP) {
+        if (value != 0 && value != 1)
+            return fail(CRB_EINVAL, "CRB_OPT_EARLY_STOP takes 0 or 1");
+        g_early_stop.store((int)value);
+        return ok();
+    }
+    return fail(CRB_EINVAL, "unknown option %d", key);
+}
+
+const char *crb_last_error(void) { return t_err.c_str(); }
+
+size_t crb_workspace_bytes(int32_t H, int32_t W) {
+    if (H < 1 || W < 1)
+        return 0;
+    return ws_layout(H, W).total;
+}
+
+crb_status crb_release_workspace(void *hip_stream) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return fail(CRB_EDEVICE, "no HIP device");
+    Workspace *w = nullptr;
+    {
+        std::lock_guard<std::mutex> g(g_ws_mu);
+        auto it = g_ws.find(std::make_pair(dev, (hipStream_t)hip_stream));
+        if (it == g_ws.end())
+            return ok();
+        w = it->second;
+    }
+    std::lock_guard<std::mutex> g(w->mu);
+    if (w->buf) {
+        hipError_t e = hipStreamSynchronize(w->stream);
+        if (e != hipSuccess)
+            return hip_status(e, "hipStreamSynchronize");
+        (void)hipFree(w->buf);
+        w->buf = nullptr;
+        w->cap = 0;
+    }
+    return ok();
+}
+
+crb_status crb_lacosmic(const float *img, int32_t H, int32_t W, float gain, float readnoise,
+                        float sky, float sigclip, float sigfrac, float objlim, int32_t niter,
+                        float *out_clean, uint8_t *out_mask) {
+    crb_status st = check_frame_args(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim, niter);
+    if (st != CRB_OK)
+        return st;
+    const size_t npix = (size_t)H * (size_t)W;
+    if ((st = check_buffers(img, out_clean, out_mask, npix)) != CRB_OK)
+        return st;
+    hipStream_t s = t_stream;
+    Workspace *ws = nullptr;
+    if ((st = ws_get(s, &ws)) != CRB_OK)
+        return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    const FrameWs L = ws_layout(H, W);
+    if ((st = ws_reserve(ws, L.total)) != CRB_OK)
+        return st;
+    const int flags = g_early_stop.load() ? 0 : kNoEarlyStop;
+    DevFrame f = make_devframe(img, out_clean, out_mask, ws->buf, L, H, W, gain, readnoise, sky,
+                               sigclip, sigfrac, objlim, niter, flags);
+    if ((st = enqueue_single(f, true, s)) != CRB_OK)
+        return st;
+    return ok();
+}
+
+crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_frame *p,
+                             uint8_t *out_G2, uint8_t *out_M, float *out_J_next,
+                             int64_t *out_n_new) {
+    if (!p)
+        return fail(CRB_EINVAL, "null params");
+    crb_status st = check_frame_args(p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
+                                     p->sigfrac, p->objlim, 1);
+    if (st != CRB_OK)
+        return st;
+    const size_t npix = (size_t)p->H * (size_t)p->W;
+    if (!J || !M_prev || !out_G2 || !out_M || !out_J_next || !out_n_new)
+        return fail(CRB_EINVAL, "null pointer");
+    if (J == out_J_next)
+        return fail(CRB_EINVAL, "out_J_next must not alias J");
+    hipStream_t s = t_stream;
+    Workspace *ws = nullptr;
+    if ((st = ws_get(s, &ws)) != CRB_OK)
+        return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    const FrameWs L = ws_layout(p->H, p->W);
+    if ((st = ws_reserve(ws, L.total)) != CRB_OK)
+        return st;
+    DevFrame f = make_devframe(J, out_J_next, out_M, ws->buf, L, p->H, p->W, p->gain,
+                               p->readnoise, p->sky, p->sigclip, p->sigfrac, p->objlim, 1,
+                               kNoEarlyStop);
+    f.g2 = out_G2;
+    hipError_t e = hipMemcpyAsync(out_M, M_prev, npix, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess)
+        return hip_status(e, "hipMemcpyAsync");
+    if ((st = enqueue_single(f, false, s)) != CRB_OK)
+        return st;
+    e = hipMemcpyAsync(out_n_new, f.nnew, sizeof(int64_t), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess)
+        return hip_status(e, "hipMemcpyAsync");
+    return ok();
+}
+
+crb_status crb_debug_detect(const float *J, const crb_frame *p, uint8_t *out_codes) {
+    if (!p || !J || !out_codes)
+        return fail(CRB_EINVAL, "null pointer");
+    crb_status st = check_frame_args(p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
+                                     p->sigfrac, p->objlim, 1);
+    if (st != CRB_OK)
+        return st;
+    DevFrame f = make_devframe(J, const_cast<float *>(J), nullptr, nullptr, ws_layout(1, 1),
+                               p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
+                               p->sigfrac, p->objlim, 1, kNoEarlyStop);
+    f.codes = out_codes;
+    f.nnew = nullptr;
+    f.listlen = nullptr;
+    f.list = nullptr;
+    return hip_status(launch_detect(nullptr, nullptr, 0, f, 1, t_stream), "kernel launch") ==
+                   CRB_OK
+               ? ok()
+               : CRB_EDEVICE;
+}
+
+crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out) {
+    if (!in || !out)
+        return fail(CRB_EINVAL, "null pointer");
+    if (H < 1 || W < 1 || (int64_t)H * W > (int64_t)INT32_MAX)
+        return fail(CRB_EINVAL, "bad size %d x %d", H, W);
+    if (r < 1 || r > 3)
+        return fail(CRB_EINVAL, "radius must be 1, 2 or 3");
+    if (ranges_overlap(in, (size_t)H * W * 4, out, (size_t)H * W * 4))
+        return fail(CRB_EINVAL, "in and out overlap");
+    crb_status st = hip_status(launch_debug_median(in, H, W, r, out, t_stream), "kernel launch");
+    return st == CRB_OK ? ok() : st;
+}
+
+crb_status crb_debug_fp64(const double *x, const double *y, int32_t n, double *out_sqrt,
+                          double *out_div) {
+    if (!x || !y || !out_sqrt || !out_div || n < 0)
+        return fail(CRB_EINVAL, "bad arguments");
+    if (n == 0)
+        return ok();
+    crb_status st =
+        hip_status(launch_debug_fp64(x, y, n, out_sqrt, out_div, t_stream), "kernel launch");
+    return st == CRB_OK ? ok() : st;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batch plans
+// ---------------------------------------------------------------------------
+
+struct crb_plan {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int n = 0;
+    int kmax = 0;
+    size_t max_pix = 0;
+    char *dmem = nullptr;
+    DevFrame *d_frames = nullptr;
+    TileRef *d_tdet = nullptr;
+    int ntdet = 0;
+    TileRef *d_tgrow = nullptr;
+    int ntgrow = 0;
+    long long *d_stats = nullptr;
+    int rgrid = 1;
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace crb {
+
+static crb_status plan_enqueue(crb_plan *p) {
+    hipStream_t s = p->stream;
+    DevFrame none;
+    memset(&none, 0, sizeof(none));
+    hipError_t e = launch_init(p->d_frames, p->n, none, p->max_pix, true, s);
+    for (int k = 1; e == hipSuccess && k <= p->kmax; ++k) {
+        e = launch_detect(p->d_frames, p->d_tdet, p->ntdet, none, k, s);
+        if (e == hipSuccess)
+            e = launch_grow(p->d_frames, p->d_tgrow, p->ntgrow, none, k, s);
+        if (e == hipSuccess)
+            e = launch_replace(p->d_frames, p->n, none, k, p->rgrid, s);
+    }
+    if (e == hipSuccess)
+        e = launch_stats(p->d_frames, p->n, p->d_stats, s);
+    return hip_status(e, "kernel launch");
+}
+
+static void plan_free(crb_plan *p) {
+    if (!p)
+        return;
+    if (p->exec)
+        (void)hipGraphExecDestroy(p->exec);
+    if (p->graph)
+        (void)hipGraphDestroy(p->graph);
+    if (p->dmem) {
+        (void)hipStreamSynchronize(p->stream);
+        (void)hipFree(p->dmem);
+    }
+    if (p->own_stream && p->stream)
+        (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+
+}  // namespace crb
+
+extern "C" {
+
+crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
+                           int32_t use_graph, crb_plan **out_plan) {
+    if (!out_plan)
+        return fail(CRB_EINVAL, "null out_plan");
+    *out_plan = nullptr;
+    if (!frames || n < 1)
+        return fail(CRB_EINVAL, "need at least one frame");
+    crb_status st;
+    std::vector<FrameWs> lay(n);
+    std::vector<size_t> off(n);
+    size_t total = 0, max_pix = 0;
+    int kmax = 0;
+    size_t ntdet = 0, ntgrow = 0;
+    for (int i = 0; i < n; ++i) {
+        const crb_frame &f = frames[i];
+        st = check_frame_args(f.H, f.W, f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac,
+                              f.objlim, f.niter);
+        if (st != CRB_OK)
+            return fail(st, "frame %d: %s", i, crb_last_error());
+        const size_t npix = (size_t)f.H * (size_t)f.W;
+        if ((st = check_buffers(f.img, f.out_clean, f.out_mask, npix)) != CRB_OK)
+            return fail(st, "frame %d: %s", i, crb_last_error());
+        lay[i] = ws_layout(f.H, f.W);
+        off[i] = total;
+        total += lay[i].total;
+        max_pix = npix > max_pix ? npix : max_pix;
+        kmax = f.niter > kmax ? f.niter : kmax;
+        ntdet += (size_t)((f.H + kDetectTY - 1) / kDetectTY) * ((f.W + kDetectTX - 1) / kDetectTX);
+        ntgrow += (size_t)((f.H + kGrowTY - 1) / kGrowTY) * ((f.W + kGrowTX - 1) / kGrowTX);
+    }
+    if (ntdet > (size_t)INT32_MAX || ntgrow > (size_t)INT32_MAX)
+        return fail(CRB_ETOOBIG, "batch too large");
+    // also guard against buffers shared between frames
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) {
+            const size_t ni = (size_t)frames[i].H * frames[i].W, nj = (size_t)frames[j].H * frames[j].W;
+            if (ranges_overlap(frames[i].out_clean, ni * 4, frames[j].out_clean, nj * 4) ||
+                ranges_overlap(frames[i].out_mask, ni, frames[j].out_mask, nj) ||
+                ranges_overlap(frames[i].out_clean, ni * 4, frames[j].img, nj * 4) ||
+                ranges_overlap(frames[j].out_clean, nj * 4, frames[i].img, ni * 4))
+                return fail(CRB_EINVAL, "frames %d and %d share output memory", i, j);
+        }
+    const size_t o_frames = total;
+    const size_t o_tdet = o_frames + ((n * sizeof(DevFrame) + 255) / 256) * 256;
+    const size_t o_tgrow = o_tdet + ((ntdet * sizeof(TileRef) + 255) / 256) * 256;
+    const size_t o_stats = o_tgrow + ((ntgrow * sizeof(TileRef) + 255) / 256) * 256;
+    const size_t bytes = o_stats + ((2 * n * sizeof(long long) + 255) / 256) * 256;
+
+    crb_plan *p = new (std::nothrow) crb_plan();
+    if (!p)
+        return fail(CRB_ENOMEM, "host allocation failed");
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        return hip_status(e, "hipGetDevice");
+    }
+    p->stream = (hipStream_t)hip_stream;
+    if (!p->stream && use_graph) {
+        e = hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete p;
+            return hip_status(e, "hipStreamCreate");
+        }
+        p->own_stream = true;
+    }
+    e = hipMalloc((void **)&p->dmem, bytes);
+    if (e != hipSuccess) {
+        p->dmem = nullptr;
+        plan_free(p);
+        (void)hipGetLastError();
+        return fail(CRB_ENOMEM, "batch workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+    }
+    p->n = n;
+    p->kmax = kmax;
+    p->max_pix = max_pix;
+    p->d_frames = reinterpret_cast<DevFrame *>(p->dmem + o_frames);
+    p->d_tdet = reinterpret_cast<TileRef *>(p->dmem + o_tdet);
+    p->d_tgrow = reinterpret_cast<TileRef *>(p->dmem + o_tgrow);
+    p->d_stats = reinterpret_cast<long long *>(p->dmem + o_stats);
+    p->ntdet = (int)ntdet;
+    p->ntgrow = (int)ntgrow;
+
+    std::vector<DevFrame> hf(n);
+    std::vector<TileRef> td, tg;
+    td.reserve(ntdet);
+    tg.reserve(ntgrow);
+    for (int i = 0; i < n; ++i) {
+        const crb_frame &f = frames[i];
+        hf[i] = make_devframe(f.img, f.out_clean, f.out_mask, p->dmem + off[i], lay[i], f.H, f.W,
+                              f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac, f.objlim,
+                              f.niter, f.flags & CRB_FLAG_NO_EARLY_STOP ? kNoEarlyStop : 0);
+        for (int y = 0; y < f.H; y += kDetectTY)
+            for (int x = 0; x < f.W; x += kDetectTX)
+                td.push_back(TileRef{i, y, x, 0});
+        for (int y = 0; y < f.H; y += kGrowTY)
+            for (int x = 0; x < f.W; x += kGrowTX)
+                tg.push_back(TileRef{i, y, x, 0});
+    }
+    p->rgrid = replace_grid(max_pix);
+    e = hipMemcpy(p->d_frames, hf.data(), n * sizeof(DevFrame), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_tdet, td.data(), td.size() * sizeof(TileRef), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_tgrow, tg.data(), tg.size() * sizeof(TileRef), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_status(e, "hipMemcpy");
+    }
+    if (use_graph) {
+        e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            plan_free(p);
+            return hip_status(e, "hipStreamBeginCapture");
+        }
+        st = plan_enqueue(p);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->stream, &g);
+        if (st != CRB_OK || e != hipSuccess) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            plan_free(p);
+            return st != CRB_OK ? st : hip_status(e, "hipStreamEndCapture");
+        }
+        p->graph = g;
+        e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            plan_free(p);
+            return hip_status(e, "hipGraphInstantiate");
+        }
+        p->use_graph = true;
+    }
+    *out_plan = p;
+    return ok();
+}
+
+crb_status crb_plan_run(crb_plan *p) {
+    if (!p)
+        return fail(CRB_EINVAL, "null plan");
+    if (p->use_graph)
+        return hip_status(hipGraphLaunch(p->exec, p->stream), "hipGraphLaunch") == CRB_OK
+                   ? ok()
+                   : CRB_EDEVICE;
+    crb_status st = plan_enqueue(p);
+    return st == CRB_OK ? ok() : st;
+}
+
+crb_status crb_plan_stats(crb_plan *p, crb_frame *frames, int32_t n) {
+    if (!p || !frames || n != p->n)
+        return fail(CRB_EINVAL, "plan/frames mismatch");
+    std::vector<long long> st(2 * (size_t)n);
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(st.data(), p->d_stats, st.size() * sizeof(long long), hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_status(e, "stats copy");
+    for (int i = 0; i < n; ++i) {
+        frames[i].iters_run = (int32_t)st[2 * i];
+        frames[i].n_flagged = (int64_t)st[2 * i + 1];
+    }
+    return ok();
+}
+
+void crb_plan_destroy(crb_plan *p) { plan_free(p); }
+
+crb_status crb_lacosmic_batched(crb_frame *frames, int32_t n, void *hip_stream) {
+    crb_plan *p = nullptr;
+    crb_status st = crb_plan_create(frames, n, hip_stream, 0, &p);
+    if (st != CRB_OK)
+        return st;
+    st = crb_plan_run(p);
+    if (st == CRB_OK)
+        st = crb_plan_stats(p, frames, n);
+    plan_free(p);
+    return st == CRB_OK ? ok() : st;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Device-side frame descriptor and kernel launchers of libcrb (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace crb {
+
+// Upper bound on iterations per frame (sizes the per-frame counters).
+constexpr int kMaxIter = 1024;
+// Detection tile (outputs per block) and grow tile.
+constexpr int kDetectTY = 32;
+constexpr int kDetectTX = 64;
+constexpr int kGrowTY = 16;
+constexpr int kGrowTX = 64;
+constexpr int kThreads = 256;
+
+// Early-stop control bit in DevFrame::flags (same value as CRB_FLAG_NO_EARLY_STOP).
+constexpr int kNoEarlyStop = 1;
+
+// Everything a kernel needs to know about one frame.  All pointers are device
+// pointers; J is the image being cleaned in place (out_clean).
+struct DevFrame {
+    const float *img;             // input frame (copied into J by the init kernel)
+    float *J;                     // working / output image, H x W
+    uint8_t *mask;                // cumulative mask, H x W (0/1)
+    uint8_t *codes;               // detection codes, H x W (workspace)
+    uint8_t *g2;                  // optional: selection of this iteration (debug), or null
+    uint32_t *list;               // indices of flagged pixels, H x W capacity (workspace)
+    unsigned long long *nnew;     // n_k per iteration [kMaxIter] (workspace)
+    unsigned int *listlen;        // list length per iteration [kMaxIter] (workspace)
+    int H, W;
+    float gain, readnoise, sky, sigclip, sigfrac, objlim;
+    int niter;
+    int flags;
+    int k;                        // current iteration when a kernel is launched with k = 0
+    int pad;
+};
+
+struct TileRef {                  // one (frame, tile origin) work item
+    int frame, y0, x0, pad;
+};
+
+// Copies img into J (when they differ), optionally clears the mask, clears counters.
+hipError_t launch_init(const DevFrame *d_frames, int nframes, const DevFrame &single,
+                       size_t max_pixels, bool zero_mask, hipStream_t s);
+// Detection (codes) for one frame (d_tiles == null: grid over `single`) or a work list.
+hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
+                         const DevFrame &single, int k, hipStream_t s);
+// Two-stage grow, new-flag count, cumulative mask, flagged list.
+hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
+                       const DevFrame &single, int k, hipStream_t s);
+// Masked-median replacement of every pixel on the flagged list.
+hipError_t launch_replace(const DevFrame *d_frames, int nframes, const DevFrame &single, int k,
+                          int grid, hipStream_t s);
+// Per-frame (iters_run, n_flagged) into d_stats[2 * i].
+hipError_t launch_stats(const DevFrame *d_frames, int nframes, long long *d_stats,
+                        hipStream_t s);
+
+hipError_t launch_debug_median(const float *in, int H, int W, int r, float *out, hipStream_t s);
+hipError_t launch_debug_fp64(const double *x, const double *y, int n, double *out_sqrt,
+                             double *out_div, hipStream_t s);
+
+}  // namespace crb

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars: masks and counts bit-exact; the cleaned image within 1e-5 relative (FP32
+output against the binary64 oracle; the kernels' replacements are exact FP32
+selections or the correctly rounded mean of two).  Decision statistics are
+binary64 on both sides, so for a given input J_k the detection is identical; the
+teacher-forced test feeds both sides the same FP32 J_k each iteration.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_1008_2192_amd import _lib, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def f32(x):
+    return float(np.float32(x))
+
+
+def fparams(f):
+    """The FP32 parameter values the GPU receives, for the binary64 oracle."""
+    return dict(gain=f32(f.gain), readnoise=f32(f.readnoise), sky=f32(f.sky),
+                sigclip=f32(f.sigclip), sigfrac=f32(f.sigfrac), objlim=f32(f.objlim))
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def small_frames():
+    """Frames spanning several detection tiles with ragged tails, plus tiny ones."""
+    out = [synth.c1()]
+    c2 = synth.c2()
+    c2.img = np.ascontiguousarray(c2.img[:230, :301])
+    out.append(c2)
+    for (H, W, seed) in [(33, 97, 31), (1, 40, 32), (40, 1, 33), (5, 5, 34), (70, 130, 35),
+                         (2, 3, 36), (1, 1, 37), (97, 65, 38)]:
+        out.append(synth.c1_density_frame(H, W, seed, 1.0, 5.0))
+    return out
+
+
+def test_fp64_sqrt_and_division_correctly_rounded():
+    rng = np.random.default_rng(0)
+    x = 10.0 ** rng.uniform(-6, 9, 200000)
+    y = 10.0 ** rng.uniform(-4, 6, 200000)
+    s, d = _lib.debug_fp64(torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(s.cpu().numpy(), np.sqrt(x))
+    np.testing.assert_array_equal(d.cpu().numpy(), x / y)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3])
+def test_median_networks_match_oracle(r):
+    rng = np.random.default_rng(r)
+    shapes = [(1, 1), (1, 9), (9, 1), (3, 5), (37, 53), (64, 64), (130, 67)]
+    for (H, W) in shapes:
+        for kind in ("ties", "cont"):
+            if kind == "ties":
+                x = rng.integers(0, 5, (H, W)).astype(np.float32)
+            else:
+                x = rng.normal(100, 10, (H, W)).astype(np.float32)
+            g = _lib.debug_median(torch.from_numpy(x).to(DEV), r)
+            torch.cuda.synchronize()
+            exp = ref.median_filter(x.astype(np.float64), r).astype(np.float32)
+            np.testing.assert_array_equal(g.cpu().numpy(), exp, err_msg=f"{H}x{W} {kind}")
+
+
+def test_detection_codes_match_oracle():
+    for f in small_frames():
+        p = fparams(f)
+        tr = ref.iterate(f.img, np.zeros(f.img.shape, np.uint8), trace=True, **p)
+        exp = (tr["first"] | ((tr["sprime"] > p["sigclip"]) << 1) |
+               ((tr["sprime"] > p["sigfrac"] * p["sigclip"]) << 2)).astype(np.uint8)
+        codes = _lib.debug_detect(torch.from_numpy(f.img).to(DEV), **p)
+        torch.cuda.synchronize()
+        got = codes.cpu().numpy()
+        log(f"detect {f.img.shape}: {int((got != exp).sum())} code mismatches, "
+            f"{int((exp & 1).sum())} first-selected")
+        np.testing.assert_array_equal(got, exp, err_msg=str(f.img.shape))
+
+
+def test_iterations_teacher_forced():
+    """Each iteration from the same FP32 J_k and M_{k-1} on both sides."""
+    for f in small_frames()[:3] + small_frames()[6:]:
+        p = fparams(f)
+        J = f.img.astype(np.float32)
+        M = np.zeros(J.shape, np.uint8)
+        for k in range(1, 5):
+            exp = ref.iterate(J.astype(np.float64), M, **p)
+            G2, Mk, Jn, n = _lib.debug_iterate(torch.from_numpy(J).to(DEV),
+                                               torch.from_numpy(M).to(DEV), **p)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(G2.cpu().numpy(), exp["G2"])
+            np.testing.assert_array_equal(Mk.cpu().numpy(), exp["M"])
+            assert int(n.item()) == exp["n"]
+            np.testing.assert_array_equal(Jn.cpu().numpy(), exp["Jnext"].astype(np.float32))
+            log(f"iterate {J.shape} k={k}: n={exp['n']} ok")
+            J = exp["Jnext"].astype(np.float32)
+            M = exp["M"]
+
+
+def compare_end_to_end(f, clean, mask, r):
+    gm = mask.cpu().numpy()
+    gc = clean.cpu().numpy().astype(np.float64)
+    nmis = int((gm != r["mask"]).sum())
+    rel = np.abs(gc - r["clean"]) / np.maximum(np.abs(r["clean"]), np.finfo(np.float64).tiny)
+    log(f"end-to-end {f.img.shape}: flagged {int(gm.sum())}, mask mismatches {nmis}, "
+        f"max rel diff {rel.max():.3g}")
+    assert nmis == 0
+    assert rel.max() <= 1e-5
+    assert (gc[r["clean"] == 0] == 0).all()
+
+
+@pytest.mark.parametrize("early_stop", [True, False])
+def test_end_to_end_small(early_stop):
+    for f in small_frames():
+        img = torch.from_numpy(f.img).to(DEV)
+        clean, mask = _lib.lacosmic(img, niter=4, early_stop=early_stop, **fparams(f))
+        torch.cuda.synchronize()
+        r = ref.lacosmic(f.img, niter=4, early_stop=early_stop, **fparams(f))
+        compare_end_to_end(f, clean, mask, r)
+
+
+def test_niter_zero_constant_and_in_place():
+    f = synth.c1()
+    img = torch.from_numpy(f.img).to(DEV)
+    clean, mask = _lib.lacosmic(img, niter=0, **fparams(f))
+    torch.cuda.synchronize()
+    assert torch.equal(clean, img) and int(mask.sum()) == 0
+    for v in (24.3, 137.0):
+        c = torch.full((50, 70), v, dtype=torch.float32, device=DEV)
+        cl, m = _lib.lacosmic(c, 7.0, 5.0, sigfrac=0.3, objlim=4.0, niter=4)
+        torch.cuda.synchronize()
+        assert torch.equal(cl, c) and int(m.sum()) == 0
+    work = img.clone()
+    cl, m = _lib.lacosmic(work, out_clean=work, niter=4, **fparams(f))
+    cl2, m2 = _lib.lacosmic(img, niter=4, **fparams(f))
+    torch.cuda.synchronize()
+    assert torch.equal(cl, cl2) and torch.equal(m, m2)
+
+
+def make_items(frames, early_stop=True):
+    items = []
+    for f in frames:
+        img = torch.from_numpy(f.img).to(DEV)
+        items.append(dict(img=img, out_clean=torch.empty_like(img),
+                          out_mask=torch.empty(img.shape, dtype=torch.uint8, device=DEV),
+                          niter=f.niter, early_stop=early_stop, **fparams(f)))
+    return items
+
+
+def test_batched_matches_solo_and_oracle_counts():
+    frames = small_frames()
+    frames[2].gain, frames[2].readnoise = 3.25, 6.5
+    frames[4].niter = 2
+    items = make_items(frames)
+    stats = _lib.lacosmic_batched(items)
+    for f, it, st in zip(frames, items, stats):
+        c, m = _lib.lacosmic(it["img"], niter=f.niter, **fparams(f))
+        torch.cuda.synchronize()
+        assert torch.equal(c, it["out_clean"]) and torch.equal(m, it["out_mask"])
+        r = ref.lacosmic(f.img, niter=f.niter, **fparams(f))
+        assert st["iters_run"] == r["iters"], (st, r["iters"])
+        assert st["n_flagged"] == int(r["mask"].sum())
+
+
+def test_plan_graph_replays_match_solo():
+    frames = small_frames()[:4]
+    items = make_items(frames, early_stop=False)
+    plan = _lib.Plan(items, use_graph=True)
+    for rep in range(3):
+        for it in items:
+            it["out_clean"].fill_(-1.0)
+            it["out_mask"].fill_(7)
+        plan.run()
+        stats = plan.stats()
+        _ = torch.randn(1000, device=DEV).sum().item()       # eager work between replays
+        for f, it, st in zip(frames, items, stats):
+            c, m = _lib.lacosmic(it["img"], niter=4, early_stop=False, **fparams(f))
+            torch.cuda.synchronize()
+            assert torch.equal(c, it["out_clean"]), rep
+            assert torch.equal(m, it["out_mask"]), rep
+            assert st["iters_run"] == 4
+    plan.close()
+
+
+def sampled_windows(H, W, rng, n=6, size=16):
+    pts = [(0, 0), (H - size, W - size), (0, W - size), (H - size, 0)]
+    while len(pts) < n:
+        pts.append((int(rng.integers(0, H - size)), int(rng.integers(0, W - size))))
+    return pts
+
+
+def check_sampled(f, clean, mask, niter, size=16):
+    """Oracle on crops with a halo of 8 px per iteration: the crop interior is exact."""
+    rng = np.random.default_rng(f.seed)
+    H, W = f.img.shape
+    halo = 8 * niter
+    gm = mask.cpu().numpy()
+    gc = clean.cpu().numpy()
+    for (y, x) in sampled_windows(H, W, rng, size=size):
+        a0, a1 = max(0, y - halo), min(H, y + size + halo)
+        b0, b1 = max(0, x - halo), min(W, x + size + halo)
+        r = ref.lacosmic(np.ascontiguousarray(f.img[a0:a1, b0:b1]), niter=niter,
+                         early_stop=False, **fparams(f))
+        em = r["mask"][y - a0:y - a0 + size, x - b0:x - b0 + size]
+        ec = r["clean"][y - a0:y - a0 + size, x - b0:x - b0 + size]
+        np.testing.assert_array_equal(gm[y:y + size, x:x + size], em, err_msg=str((y, x)))
+        np.testing.assert_allclose(gc[y:y + size, x:x + size].astype(np.float64), ec, rtol=1e-5,
+                                   atol=0, err_msg=str((y, x)))
+
+
+def test_full_size_4096_sampled():
+    f = synth.c3()
+    img = torch.from_numpy(f.img).to(DEV)
+    clean, mask = _lib.lacosmic(img, niter=4, early_stop=False, **fparams(f))
+    torch.cuda.synchronize()
+    log(f"c3 4096x4096: flagged {int(mask.sum())} ({int(f.hits.sum())} hit pixels)")
+    check_sampled(f, clean, mask, 4)
+
+
+def test_mixed_batch_sampled():
+    frames = [synth.c1_density_frame(800, 800, 4000, 3.5, 4.25),
+              synth.c1_density_frame(2048, 4096, 4032, 6.75, 7.5),
+              synth.c1_density_frame(1024, 1024, 4016, 1.25, 3.0)]
+    items = make_items(frames, early_stop=False)
+    plan = _lib.Plan(items, use_graph=True)
+    plan.run()
+    plan.stats()
+    for f, it in zip(frames, items):
+        check_sampled(f, it["out_clean"], it["out_mask"], 4)
+    plan.close()
