@@ -1,0 +1,231 @@
+"""Benchmark: Mpix/s per L.A.Cosmic iteration on the mixed-size batch, batched vs per-frame.
+
+A step is one pass of the whole hot path over the batch: niter = 4 iterations
+(detection, grow/count, replacement) for all 64 frames of the mixed-size workload
+(16 x 800x800, 16 x 1024x1024, 16 x 2048x4096, 16 x 4096x2048; per-frame gain and
+read noise), with every iteration forced so that the work is fixed.  Frames are
+device-resident before the timed region starts.  The timed region runs the batch
+plan with a pair of HIP events around every launch (on the plan's stream), which
+gives the detection kernel's average duration for the roofline; the same plan
+replayed as a captured HIP graph and the per-frame path (one crb_lacosmic call per
+frame) are timed after it.  rank 0 prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4|c3|c2|c1]
+                  [--no-cpu-baseline] [--no-per-frame] [--calib-copy]
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpix/s per L.A.Cosmic iteration (batched vs per-frame); p99 frame latency"
+UNIT = "Mpix/s per iteration"
+
+
+def _gen(args):
+    name, i = args
+    from paper_1008_2192_amd import synth
+    if name == "c4":
+        sizes = synth.C4_SIZES
+        H, W = sizes[i // 16]
+        seed = 4000 + i
+        prng = np.random.Generator(np.random.PCG64(seed + 10_000_000))
+        g = float(np.float32(prng.uniform(1.0, 8.0)))
+        rn = float(np.float32(prng.uniform(3.0, 8.0)))
+        return synth.c1_density_frame(H, W, seed, g, rn, name=f"c4[{i}]-{H}x{W}")
+    return getattr(synth, name)()
+
+
+def make_workload(name: str, workers: int):
+    if name == "c4":
+        jobs = [("c4", i) for i in range(64)]
+        with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(_gen, jobs))
+    return [_gen((name, 0))]
+
+
+def describe(name, frames):
+    px = sum(f.img.size for f in frames)
+    if name == "c4":
+        return {"workload": "mixed-size batch: 64 FP32 frames, 16 each of 800x800, 1024x1024, "
+                            "2048x4096, 4096x2048 (HxW), per-frame gain U(1,8), read noise "
+                            "U(3,8), 30 stars and 50 cosmic-ray hits per 65536 px; sigclip 4.5, "
+                            "sigfrac 0.3, objlim 4, niter 4 (forced)",
+                "frames": len(frames), "pixels": px, "niter": 4}
+    f = frames[0]
+    return {"workload": f"{f.name}: single FP32 frame {f.img.shape[0]}x{f.img.shape[1]}, "
+                        f"gain {f.gain}, read noise {f.readnoise}, niter 4 (forced)",
+            "frames": 1, "pixels": px, "niter": 4}
+
+
+def cpu_baseline(frames_for_cpu):
+    """The FP64 oracle as it stands, single-threaded, on a bounded sample."""
+    from oracle import ref
+    t0 = time.perf_counter()
+    px_iter = 0
+    for f in frames_for_cpu:
+        ref.lacosmic(f.img, f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac, f.objlim, 4,
+                     early_stop=False)
+        px_iter += f.img.size * 4
+    dt = time.perf_counter() - t0
+    return {"value": round(px_iter / dt / 1e6, 4), "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{len(frames_for_cpu)} frame(s) of "
+                      f"{'+'.join(f'{f.img.shape[0]}x{f.img.shape[1]}' for f in frames_for_cpu)}"
+                      f" px, 4 forced iterations, {dt:.1f} s on one host thread (nproc "
+                      f"{os.cpu_count()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-frame", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--workers", type=int, default=8)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (frames shard across GPUs by "
+              "whole frames; no multi-GPU path is built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1008_2192_amd import _lib, roofline
+
+    _lib.lib()                     # fail loudly if the HIP library is missing
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    t0 = time.perf_counter()
+    frames = make_workload(args.workload, args.workers)
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] generated {len(frames)} frame(s) in {gen_s:.1f} s", file=sys.stderr,
+          flush=True)
+    items = []
+    for f in frames:
+        img = torch.from_numpy(f.img).to(dev)
+        items.append(dict(img=img, out_clean=torch.empty_like(img),
+                          out_mask=torch.empty(img.shape, dtype=torch.uint8, device=dev),
+                          gain=f.gain, readnoise=f.readnoise, sky=f.sky, sigclip=f.sigclip,
+                          sigfrac=f.sigfrac, objlim=f.objlim, niter=4, early_stop=False))
+    torch.cuda.synchronize()
+    total_px = sum(f.img.size for f in frames)
+    px_iter = total_px * 4
+
+    # ---- timed region: batch plan, events around every launch ----------------
+    plan = _lib.Plan(items, use_graph=False)
+    for _ in range(args.warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ktimes = plan.kernel_times()
+    stats = plan.stats()
+    plan.set_timing(False)
+    plan.close()
+    ms_per_step = dt / args.steps * 1e3
+    value = px_iter / (dt / args.steps) / 1e6
+    print(f"[bench] batched: {ms_per_step:.2f} ms/step, {value:.0f} Mpix/s per iteration; "
+          f"kernel ms: " + ", ".join(f"{k} {v[0] / max(v[1], 1):.3f}x{v[1]}"
+                                     for k, v in ktimes.items()), file=sys.stderr, flush=True)
+
+    det_ms, det_n = ktimes["detect"]
+    det_avg_s = det_ms / det_n / 1e3
+    ops = roofline.detect_ops_per_pixel()
+    achieved = ops["total"] * total_px / det_avg_s        # lane-ops per second
+    roof = {"bound": "alu", "kernel": "k_detect (detection: med3/med5/med7 networks, L+, N, "
+                                      "S, S', F^, thresholds)",
+            "achieved": round(achieved / 1e12, 3), "peak": round(roofline.ALU_PEAK / 1e12, 3),
+            "unit": "Tlane-op/s", "frac": round(achieved / roofline.ALU_PEAK, 4),
+            "traffic": None, "ops_per_pixel": round(ops["total"], 2),
+            "pixels_per_launch": total_px, "avg_launch_ms": round(det_avg_s * 1e3, 4),
+            "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64", "data": "synthetic",
+           "config": describe(args.workload, frames), "roofline": roof}
+    out["flagged_pixels"] = int(sum(s["n_flagged"] for s in stats))
+
+    # ---- same plan replayed as a captured graph -------------------------------
+    if not args.no_graph:
+        gplan = _lib.Plan(items, use_graph=True)
+        for _ in range(args.warmup):
+            gplan.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gplan.run()
+        torch.cuda.synchronize()
+        gdt = time.perf_counter() - t0
+        gplan.close()
+        out["graph"] = {"value": round(px_iter / (gdt / args.steps) / 1e6, 1),
+                        "ms_per_step": round(gdt / args.steps * 1e3, 3)}
+        print(f"[bench] graph replay: {gdt / args.steps * 1e3:.2f} ms/step", file=sys.stderr,
+              flush=True)
+
+    # ---- per-frame path: one crb_lacosmic call per frame ----------------------
+    if not args.no_per_frame:
+        def per_frame_step():
+            for it in items:
+                _lib.lacosmic(it["img"], it["gain"], it["readnoise"], it["sky"], it["sigclip"],
+                              it["sigfrac"], it["objlim"], 4, out_clean=it["out_clean"],
+                              out_mask=it["out_mask"], early_stop=False)
+        for _ in range(args.warmup):
+            per_frame_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            per_frame_step()
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        pf = px_iter / (pdt / args.steps) / 1e6
+        out["per_frame"] = {"value": round(pf, 1), "ms_per_step": round(pdt / args.steps * 1e3, 3),
+                            "batched_speedup": round(value / pf, 3)}
+        if "graph" in out:
+            out["per_frame"]["graph_speedup"] = round(out["graph"]["value"] / pf, 3)
+        print(f"[bench] per-frame: {pdt / args.steps * 1e3:.2f} ms/step", file=sys.stderr,
+              flush=True)
+
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * src.numel() * 4
+
+    if not args.no_cpu_baseline:
+        sample = [f for f in frames if f.img.shape == (800, 800)][:2] or frames[:1]
+        if args.workload == "c3":
+            from paper_1008_2192_amd import synth
+            sample = [synth.c3(size=512)]
+        out["cpu_baseline"] = cpu_baseline(sample)
+        print(f"[bench] cpu baseline: {out['cpu_baseline']}", file=sys.stderr, flush=True)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -124,6 +124,13 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
 crb_status crb_plan_run(crb_plan *plan);
 crb_status crb_plan_stats(crb_plan *plan, crb_frame *frames, int32_t n);
 void crb_plan_destroy(crb_plan *plan);
+/* Per-launch timing of a plan created without a graph: when enabled, every launch
+ * of crb_plan_run is bracketed by a pair of HIP events on the plan's stream.
+ * crb_plan_kernel_times waits for the recorded work and returns, per kernel class
+ * (0 init, 1 detection, 2 grow/count, 3 replacement), the summed milliseconds and
+ * the number of launches since timing was enabled (ms[4], launches[4]). */
+crb_status crb_plan_set_timing(crb_plan *plan, int32_t enable);
+crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
 
 /* Per-thread stream used by crb_lacosmic (NULL: default stream). */
 crb_status crb_set_stream(void *hip_stream);

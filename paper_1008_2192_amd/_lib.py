@@ -20,7 +20,7 @@ STATUS = {0: "CRB_OK", -1: "CRB_EINVAL", -2: "CRB_ENOMEM", -3: "CRB_EDEVICE",
           -4: "CRB_ETOOBIG", -5: "CRB_EBUSY"}
 
 EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_plan_create", "crb_plan_run",
-           "crb_plan_stats", "crb_plan_destroy", "crb_set_stream", "crb_set_option",
+           "crb_plan_stats", "crb_plan_destroy", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option",
            "crb_last_error", "crb_workspace_bytes", "crb_release_workspace",
            "crb_server_create", "crb_server_submit", "crb_server_poll", "crb_server_pending",
            "crb_server_destroy", "crb_debug_iterate", "crb_debug_detect", "crb_debug_median",
@@ -64,6 +64,9 @@ def lib():
     L.crb_plan_stats.argtypes = [vp, ctypes.POINTER(Frame), i32]
     L.crb_plan_destroy.argtypes = [vp]
     L.crb_plan_destroy.restype = None
+    L.crb_plan_set_timing.argtypes = [vp, i32]
+    L.crb_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(i64)]
     L.crb_set_stream.argtypes = [vp]
     L.crb_set_option.argtypes = [i32, i64]
     L.crb_last_error.argtypes = []
@@ -84,7 +87,7 @@ def lib():
     L.crb_debug_median.argtypes = [vp, i32, i32, i32, vp]
     L.crb_debug_fp64.argtypes = [vp, vp, i32, vp, vp]
     for name in ("crb_lacosmic", "crb_lacosmic_batched", "crb_plan_create", "crb_plan_run",
-                 "crb_plan_stats", "crb_set_stream", "crb_set_option", "crb_release_workspace",
+                 "crb_plan_stats", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option", "crb_release_workspace",
                  "crb_server_create", "crb_server_submit", "crb_server_poll",
                  "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64"):
         getattr(L, name).restype = ctypes.c_int
@@ -183,6 +186,18 @@ class Plan:
     def stats(self) -> List[dict]:
         check("crb_plan_stats", lib().crb_plan_stats(self.handle, self.frames, len(self.items)))
         return [dict(iters_run=f.iters_run, n_flagged=f.n_flagged) for f in self.frames]
+
+    def set_timing(self, enable: bool) -> None:
+        check("crb_plan_set_timing", lib().crb_plan_set_timing(self.handle, 1 if enable else 0))
+
+    KINDS = ("init", "detect", "grow", "replace")
+
+    def kernel_times(self) -> dict:
+        """{kind: (total ms, launches)} since timing was enabled."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        check("crb_plan_kernel_times", lib().crb_plan_kernel_times(self.handle, ms, n))
+        return {k: (ms[i], int(n[i])) for i, k in enumerate(self.KINDS)}
 
     def close(self) -> None:
         if self.handle:

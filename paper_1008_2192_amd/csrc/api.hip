@@ -394,21 +394,62 @@ struct crb_plan {
     bool use_graph = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // eager timing: an event pair around every launch, summed per kernel class
+    bool timing = false;
+    std::vector<hipEvent_t> events;     // pool, 2 per recorded launch
+    std::vector<int> ev_kind;           // kernel class of each recorded pair
+    size_t ev_used = 0;                 // pairs recorded since the last query
+    double acc_ms[crb::kNumKernelKinds] = {0};
+    long long acc_n[crb::kNumKernelKinds] = {0};
 };
 
 namespace crb {
+
+// records the start event of a timed launch (no-op unless timing)
+static hipError_t tmark_begin(crb_plan *p, int kind) {
+    if (!p->timing)
+        return hipSuccess;
+    if (2 * (p->ev_used + 1) > p->events.size()) {
+        for (int i = 0; i < 2; ++i) {
+            hipEvent_t ev;
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess)
+                return e;
+            p->events.push_back(ev);
+        }
+        p->ev_kind.push_back(0);
+    }
+    p->ev_kind[p->ev_used] = kind;
+    return hipEventRecord(p->events[2 * p->ev_used], p->stream);
+}
+
+static hipError_t tmark_end(crb_plan *p) {
+    if (!p->timing)
+        return hipSuccess;
+    hipError_t e = hipEventRecord(p->events[2 * p->ev_used + 1], p->stream);
+    ++p->ev_used;
+    return e;
+}
 
 static crb_status plan_enqueue(crb_plan *p) {
     hipStream_t s = p->stream;
     DevFrame none;
     memset(&none, 0, sizeof(none));
-    hipError_t e = launch_init(p->d_frames, p->n, none, p->max_pix, true, s);
+    hipError_t e = tmark_begin(p, kKindInit);
+    if (e == hipSuccess)
+        e = launch_init(p->d_frames, p->n, none, p->max_pix, true, s);
+    if (e == hipSuccess)
+        e = tmark_end(p);
     for (int k = 1; e == hipSuccess && k <= p->kmax; ++k) {
-        e = launch_detect(p->d_frames, p->d_tdet, p->ntdet, none, k, s);
-        if (e == hipSuccess)
-            e = launch_grow(p->d_frames, p->d_tgrow, p->ntgrow, none, k, s);
-        if (e == hipSuccess)
-            e = launch_replace(p->d_frames, p->n, none, k, p->rgrid, s);
+        if ((e = tmark_begin(p, kKindDetect)) == hipSuccess &&
+            (e = launch_detect(p->d_frames, p->d_tdet, p->ntdet, none, k, s)) == hipSuccess &&
+            (e = tmark_end(p)) == hipSuccess &&
+            (e = tmark_begin(p, kKindGrow)) == hipSuccess &&
+            (e = launch_grow(p->d_frames, p->d_tgrow, p->ntgrow, none, k, s)) == hipSuccess &&
+            (e = tmark_end(p)) == hipSuccess &&
+            (e = tmark_begin(p, kKindReplace)) == hipSuccess &&
+            (e = launch_replace(p->d_frames, p->n, none, k, p->rgrid, s)) == hipSuccess)
+            e = tmark_end(p);
     }
     if (e == hipSuccess)
         e = launch_stats(p->d_frames, p->n, p->d_stats, s);
@@ -426,6 +467,8 @@ static void plan_free(crb_plan *p) {
         (void)hipStreamSynchronize(p->stream);
         (void)hipFree(p->dmem);
     }
+    for (hipEvent_t ev : p->events)
+        (void)hipEventDestroy(ev);
     if (p->own_stream && p->stream)
         (void)hipStreamDestroy(p->stream);
     delete p;
@@ -598,6 +641,44 @@ crb_status crb_plan_stats(crb_plan *p, crb_frame *frames, int32_t n) {
 }
 
 void crb_plan_destroy(crb_plan *p) { plan_free(p); }
+
+crb_status crb_plan_set_timing(crb_plan *p, int32_t enable) {
+    if (!p)
+        return fail(CRB_EINVAL, "null plan");
+    if (enable && p->use_graph)
+        return fail(CRB_EINVAL, "per-launch timing needs a plan without a graph");
+    p->timing = enable != 0;
+    p->ev_used = 0;
+    for (int i = 0; i < kNumKernelKinds; ++i) {
+        p->acc_ms[i] = 0.0;
+        p->acc_n[i] = 0;
+    }
+    return ok();
+}
+
+crb_status crb_plan_kernel_times(crb_plan *p, double *ms, int64_t *launches) {
+    if (!p || !ms || !launches)
+        return fail(CRB_EINVAL, "null argument");
+    if (p->ev_used) {
+        hipError_t e = hipEventSynchronize(p->events[2 * p->ev_used - 1]);
+        if (e != hipSuccess)
+            return hip_status(e, "hipEventSynchronize");
+        for (size_t i = 0; i < p->ev_used; ++i) {
+            float t = 0.0f;
+            e = hipEventElapsedTime(&t, p->events[2 * i], p->events[2 * i + 1]);
+            if (e != hipSuccess)
+                return hip_status(e, "hipEventElapsedTime");
+            p->acc_ms[p->ev_kind[i]] += (double)t;
+            p->acc_n[p->ev_kind[i]] += 1;
+        }
+        p->ev_used = 0;
+    }
+    for (int i = 0; i < kNumKernelKinds; ++i) {
+        ms[i] = p->acc_ms[i];
+        launches[i] = p->acc_n[i];
+    }
+    return ok();
+}
 
 crb_status crb_lacosmic_batched(crb_frame *frames, int32_t n, void *hip_stream) {
     crb_plan *p = nullptr;

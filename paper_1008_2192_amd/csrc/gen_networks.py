@@ -347,6 +347,30 @@ def _ref(net: Net, x: int) -> str:
     return f"v[{x}]" if x < net.n_in else f"t{x}"
 
 
+def dfs_order(net: Net, outs: Sequence[int]) -> List[int]:
+    """Op indices in depth-first post-order from the outputs: each value is computed
+    just before its first use, which keeps fewer values live at a time."""
+    order, seen = [], set()
+    for o in outs:
+        stack = [(o, False)]
+        while stack:
+            v, done = stack.pop()
+            if v < net.n_in or v in seen:
+                continue
+            if done:
+                seen.add(v)
+                order.append(v - net.n_in)
+                continue
+            stack.append((v, True))
+            _, a, b = net.ops[v - net.n_in]
+            stack.append((b, False))
+            stack.append((a, False))
+    return order
+
+
+EMIT_ORDER = os.environ.get("CRB_NET_ORDER", "seq")
+
+
 def emit_tile_function(name: str, tm: TileMedian) -> str:
     net = tm.net
     outs = [tm.outputs[(i, j)] for i in range(tm.ty) for j in range(tm.tx)]
@@ -358,9 +382,10 @@ def emit_tile_function(name: str, tm: TileMedian) -> str:
              f"template <typename T>",
              f"__device__ __forceinline__ void {name}(const T (&v)[{tm.ph * tm.pw}], "
              f"T (&o)[{tm.ty * tm.tx}]) {{"]
-    for i, (kind, a, b) in enumerate(net.ops):
-        if not live[i]:
-            continue
+    order = dfs_order(net, outs) if EMIT_ORDER == "dfs" else [i for i in range(len(net.ops))
+                                                                if live[i]]
+    for i in order:
+        kind, a, b = net.ops[i]
         fn = "vmin" if kind == "min" else "vmax"
         lines.append(f"  const T t{net.n_in + i} = {fn}({_ref(net, a)}, {_ref(net, b)});")
     for idx, o in enumerate(outs):
@@ -383,8 +408,7 @@ def emit_sort_function(name: str, n: int) -> str:
 
 
 # tile shapes used by the kernels: (function name, k, ty, tx)
-TILES = [("med5_t2x4", 5, 2, 4), ("med7_t2x4", 7, 2, 4), ("med5_t1x1", 5, 1, 1),
-         ("med7_t1x1", 7, 1, 1)]
+TILES = [("med5_t2x5", 5, 2, 5), ("med5_t2x4", 5, 2, 4), ("med7_t2x4", 7, 2, 4)]
 
 
 def generate(path: str, verify: bool = True) -> None:

@@ -9,12 +9,17 @@ namespace crb {
 
 // Upper bound on iterations per frame (sizes the per-frame counters).
 constexpr int kMaxIter = 1024;
-// Detection tile (outputs per block) and grow tile.
+// Detection tile (outputs per block) and grow tile (outputs per wave: 62 words of
+// 4 pixels by kGrowTY rows).
 constexpr int kDetectTY = 32;
 constexpr int kDetectTX = 64;
-constexpr int kGrowTY = 16;
-constexpr int kGrowTX = 64;
+constexpr int kGrowTY = 32;
+constexpr int kGrowTX = 248;
 constexpr int kThreads = 256;
+
+// Kernel classes for per-launch timing (crb_plan_kernel_times order).
+constexpr int kKindInit = 0, kKindDetect = 1, kKindGrow = 2, kKindReplace = 3;
+constexpr int kNumKernelKinds = 4;
 
 // Early-stop control bit in DevFrame::flags (same value as CRB_FLAG_NO_EARLY_STOP).
 constexpr int kNoEarlyStop = 1;

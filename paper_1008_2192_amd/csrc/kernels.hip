@@ -37,21 +37,22 @@ __device__ __forceinline__ float med3f(float a, float b, float c) {
 __device__ __forceinline__ float min3f(float a, float b, float c) { return fminf(fminf(a, b), c); }
 __device__ __forceinline__ float max3f(float a, float b, float c) { return fmaxf(fmaxf(a, b), c); }
 
-// 3x3 medians of a run of 8 horizontally adjacent outputs from three rows of 10
+// 3x3 medians of a run of N horizontally adjacent outputs from three rows of N+2
 // inputs.  Each column of three is sorted once (shared by up to three windows);
 // the median of a 3x3 window with sorted columns is the median of
 // (max of the column minima, median of the column medians, min of the column maxima).
-__device__ __forceinline__ void med3_run8(const float (&a)[10], const float (&b)[10],
-                                          const float (&c)[10], float (&o)[8]) {
-    float lo[10], mi[10], hi[10];
+template <int N>
+__device__ __forceinline__ void med3_run(const float (&a)[N + 2], const float (&b)[N + 2],
+                                         const float (&c)[N + 2], float (&o)[N]) {
+    float lo[N + 2], mi[N + 2], hi[N + 2];
 #pragma unroll
-    for (int j = 0; j < 10; ++j) {
+    for (int j = 0; j < N + 2; ++j) {
         lo[j] = min3f(a[j], b[j], c[j]);
         mi[j] = med3f(a[j], b[j], c[j]);
         hi[j] = max3f(a[j], b[j], c[j]);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int j = 0; j < N; ++j)
         o[j] = med3f(max3f(lo[j], lo[j + 1], lo[j + 2]), med3f(mi[j], mi[j + 1], mi[j + 2]),
                      min3f(hi[j], hi[j + 1], hi[j + 2]));
 }
@@ -87,24 +88,31 @@ __device__ __forceinline__ double lplus(double c, double u, double d, double l, 
 // detection
 // ---------------------------------------------------------------------------
 
+// Work shapes inside a detection block: med3 in runs of kRun3 outputs, med5(J) with
+// L+, N, S in 2 x 5 thread tiles, med7 and med5(S) in 2 x 4 thread tiles.  For the
+// 32 x 64 tile each stage needs one pass of the 256 threads.
+constexpr int kRun3 = 14;
+
 template <int TY, int TX>
 struct DetectLayout {
     static constexpr int JH = TY + 8, JW = TX + 8;              // J, apron 4
     static constexpr int MH = TY + 6, MW = TX + 6;              // med3(J), apron 3
     static constexpr int MWP = (MW + 3) & ~3;                   // 16-byte rows
     static constexpr int SH = TY + 4, SW = TX + 4;              // S (binary64), apron 2
+    static_assert(JH * JW >= TY * TX, "med7 results reuse the J buffer");
 };
 
 template <int TY, int TX>
-__global__ __launch_bounds__(kThreads) void k_detect(const DevFrame *__restrict__ frames,
-                                                     const TileRef *__restrict__ tiles,
-                                                     DevFrame single, int kiter) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
+              DevFrame single, int kiter) {
     using L = DetectLayout<TY, TX>;
     static_assert(TY % 2 == 0 && TX % 4 == 0, "detection tile must hold 2x4 thread tiles");
-    __shared__ float sJ[L::JH * L::JW];
+    __shared__ __align__(16) float sJ[L::JH * L::JW];      // J, later med7(med3)
     __shared__ __align__(16) float sM3[L::MH * L::MWP];
     __shared__ __align__(16) double sS[L::SH * L::SW];
-    __shared__ double sN[TY * TX];
+    __shared__ float sM5[TY * TX];                          // med5(J) at the outputs
+    float *const sM7 = sJ;
 
     DevFrame f;
     int y0, x0;
@@ -131,57 +139,57 @@ __global__ __launch_bounds__(kThreads) void k_detect(const DevFrame *__restrict_
     }
     __syncthreads();
 
-    // med3(J) over [y0-3, y0+TY+3) x [x0-3, x0+TX+3): runs of 8 per thread
+    // med3(J) over [y0-3, y0+TY+3) x [x0-3, x0+TX+3)
     {
-        constexpr int NRX = (L::MW + 7) / 8;
+        constexpr int NRX = (L::MW + kRun3 - 1) / kRun3;
         for (int t = tid; t < L::MH * NRX; t += kThreads) {
             const int r = t / NRX;
-            const int cx = min((t - r * NRX) * 8, L::MW - 8);
-            float a[10], b[10], c[10], o[8];
+            const int cx = min((t - r * NRX) * kRun3, L::MW - kRun3);
+            float a[kRun3 + 2], b[kRun3 + 2], c[kRun3 + 2], o[kRun3];
 #pragma unroll
-            for (int j = 0; j < 10; ++j) {
+            for (int j = 0; j < kRun3 + 2; ++j) {
                 a[j] = sJ[r * L::JW + cx + j];
                 b[j] = sJ[(r + 1) * L::JW + cx + j];
                 c[j] = sJ[(r + 2) * L::JW + cx + j];
             }
-            med3_run8(a, b, c, o);
+            med3_run<kRun3>(a, b, c, o);
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
+            for (int j = 0; j < kRun3; ++j)
                 sM3[r * L::MWP + cx + j] = o[j];
         }
     }
 
-    // med5(J), L+, N and S over [y0-2, y0+TY+2) x [x0-2, x0+TX+2): 2x4 thread tiles
+    // med5(J), L+, N and S over [y0-2, y0+TY+2) x [x0-2, x0+TX+2)
     {
-        constexpr int NTY = (L::SH + 1) / 2, NTX = (L::SW + 3) / 4;
-        constexpr int PW = 8;
+        constexpr int TTY = 2, TTX = 5, PW = TTX + 4;
+        constexpr int NTY = (L::SH + TTY - 1) / TTY, NTX = (L::SW + TTX - 1) / TTX;
         const double gain = f.gain, sky = f.sky, rn = f.readnoise;
         const double rn2 = rn * rn;
         for (int t = tid; t < NTY * NTX; t += kThreads) {
             const int ty = t / NTX;
-            const int r = min(ty * 2, L::SH - 2);
-            const int c = min((t - ty * NTX) * 4, L::SW - 4);
-            float v[6 * PW], m5[8];
+            const int r = min(ty * TTY, L::SH - TTY);
+            const int c = min((t - ty * NTX) * TTX, L::SW - TTX);
+            float v[(TTY + 4) * PW], m5[TTY * TTX];
 #pragma unroll
-            for (int i = 0; i < 6; ++i)
+            for (int i = 0; i < TTY + 4; ++i)
 #pragma unroll
                 for (int j = 0; j < PW; ++j)
                     v[i * PW + j] = sJ[(r + i) * L::JW + c + j];
-            med5_t2x4(v, m5);
+            med5_t2x5(v, m5);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < TTY; ++i) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+                for (int j = 0; j < TTX; ++j) {
                     const int pc = (i + 2) * PW + (j + 2);
                     const double lp = lplus(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1]);
-                    double m = (double)m5[i * 4 + j] + sky;
+                    double m = (double)m5[i * TTX + j] + sky;
                     if (m <= 0.0)
                         m = 1e-4;
                     const double N = sqrt(gain * m + rn2) / gain;
                     sS[(r + i) * L::SW + c + j] = lp / (2.0 * N);
                     const int cy = r + i - 2, cxx = c + j - 2;
                     if (cy >= 0 && cy < TY && cxx >= 0 && cxx < TX)
-                        sN[cy * TX + cxx] = N;
+                        sM5[cy * TX + cxx] = m5[i * TTX + j];
                 }
             }
         }
@@ -207,42 +215,49 @@ __global__ __launch_bounds__(kThreads) void k_detect(const DevFrame *__restrict_
         __syncthreads();
     }
 
-    // med7(med3), med5(S), S', F^ and the threshold bits for the TY x TX outputs
+    constexpr int NTX3 = TX / 4;
+    // med7(med3) for the TY x TX outputs, into the (now unused) J buffer
+    for (int t = tid; t < (TY / 2) * NTX3; t += kThreads) {
+        const int ty = t / NTX3;
+        const int r = ty * 2, c = (t - ty * NTX3) * 4;
+        float v[8 * 10], m7[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float4 q0 = *reinterpret_cast<const float4 *>(&sM3[(r + i) * L::MWP + c]);
+            const float4 q1 = *reinterpret_cast<const float4 *>(&sM3[(r + i) * L::MWP + c + 4]);
+            const float2 q2 = *reinterpret_cast<const float2 *>(&sM3[(r + i) * L::MWP + c + 8]);
+            v[i * 10 + 0] = q0.x; v[i * 10 + 1] = q0.y; v[i * 10 + 2] = q0.z; v[i * 10 + 3] = q0.w;
+            v[i * 10 + 4] = q1.x; v[i * 10 + 5] = q1.y; v[i * 10 + 6] = q1.z; v[i * 10 + 7] = q1.w;
+            v[i * 10 + 8] = q2.x; v[i * 10 + 9] = q2.y;
+        }
+        med7_t2x4(v, m7);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            *reinterpret_cast<float4 *>(&sM7[(r + i) * TX + c]) =
+                make_float4(m7[i * 4], m7[i * 4 + 1], m7[i * 4 + 2], m7[i * 4 + 3]);
+    }
+    __syncthreads();
+
+    // med5(S), S', F^ and the threshold bits
     {
-        constexpr int NTX = TX / 4;
         const double sigclip = f.sigclip, objlim = f.objlim;
         const double lowlim = (double)f.sigfrac * (double)f.sigclip;
+        const double gain = f.gain, sky = f.sky, rn = f.readnoise;
+        const double rn2 = rn * rn;
         uint8_t *__restrict__ codes = f.codes;
-        for (int t = tid; t < (TY / 2) * NTX; t += kThreads) {
-            const int ty = t / NTX;
-            const int r = ty * 2, c = (t - ty * NTX) * 4;
-            float m7[8];
-            {
-                float v[8 * 10];
+        for (int t = tid; t < (TY / 2) * NTX3; t += kThreads) {
+            const int ty = t / NTX3;
+            const int r = ty * 2, c = (t - ty * NTX3) * 4;
+            double v[6 * 8], ms[8];
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const float4 q0 = *reinterpret_cast<const float4 *>(&sM3[(r + i) * L::MWP + c]);
-                    const float4 q1 = *reinterpret_cast<const float4 *>(&sM3[(r + i) * L::MWP + c + 4]);
-                    const float2 q2 = *reinterpret_cast<const float2 *>(&sM3[(r + i) * L::MWP + c + 8]);
-                    v[i * 10 + 0] = q0.x; v[i * 10 + 1] = q0.y; v[i * 10 + 2] = q0.z; v[i * 10 + 3] = q0.w;
-                    v[i * 10 + 4] = q1.x; v[i * 10 + 5] = q1.y; v[i * 10 + 6] = q1.z; v[i * 10 + 7] = q1.w;
-                    v[i * 10 + 8] = q2.x; v[i * 10 + 9] = q2.y;
+            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                for (int j = 0; j < 8; j += 2) {
+                    const double2 q = *reinterpret_cast<const double2 *>(&sS[(r + i) * L::SW + c + j]);
+                    v[i * 8 + j] = q.x;
+                    v[i * 8 + j + 1] = q.y;
                 }
-                med7_t2x4(v, m7);
-            }
-            double ms[8];
-            {
-                double v[6 * 8];
-#pragma unroll
-                for (int i = 0; i < 6; ++i)
-#pragma unroll
-                    for (int j = 0; j < 8; j += 2) {
-                        const double2 q = *reinterpret_cast<const double2 *>(&sS[(r + i) * L::SW + c + j]);
-                        v[i * 8 + j] = q.x;
-                        v[i * 8 + j + 1] = q.y;
-                    }
-                med5_t2x4(v, ms);
-            }
+            med5_t2x4(v, ms);
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int gy = y0 + r + i;
@@ -251,15 +266,23 @@ __global__ __launch_bounds__(kThreads) void k_detect(const DevFrame *__restrict_
                     const int gx = x0 + c + j;
                     if (gy < H && gx < W) {
                         const double S = sS[(r + i + 2) * L::SW + c + j + 2];
-                        const double N = sN[(r + i) * TX + c + j];
-                        const double m3 = sM3[(r + i + 3) * L::MWP + c + j + 3];
                         const double sp = S - ms[i * 4 + j];
-                        double fh = (m3 - (double)m7[i * 4 + j]) / N;
-                        if (fh < 0.01)
-                            fh = 0.01;
                         const bool hi = sp > sigclip;
-                        const bool first = hi && (sp / fh > objlim);
                         const bool lo = sp > lowlim;
+                        bool first = false;
+                        if (hi) {   // the contrast test matters only where S' > sigclip
+                            // N as in the S stage, from the stored med5(J)
+                            double m = (double)sM5[(r + i) * TX + c + j] + sky;
+                            if (m <= 0.0)
+                                m = 1e-4;
+                            const double N = sqrt(gain * m + rn2) / gain;
+                            const double m3 = sM3[(r + i + 3) * L::MWP + c + j + 3];
+                            const double m7 = sM7[(r + i) * TX + c + j];
+                            double fh = (m3 - m7) / N;
+                            if (fh < 0.01)
+                                fh = 0.01;
+                            first = sp / fh > objlim;
+                        }
                         codes[(size_t)gy * W + gx] =
                             (uint8_t)((first ? 1 : 0) | (hi ? 2 : 0) | (lo ? 4 : 0));
                     }
@@ -272,109 +295,160 @@ __global__ __launch_bounds__(kThreads) void k_detect(const DevFrame *__restrict_
 // ---------------------------------------------------------------------------
 // grow + count + cumulative mask + flagged list
 // ---------------------------------------------------------------------------
+//
+// Word-parallel: a lane holds the codes of 4 horizontally adjacent pixels in one
+// dword (bytes 0..3 = pixels x..x+3), so a 3-wide dilation is two byte shifts plus
+// the edge bytes of the neighbouring lanes.  A wave covers 62 words (248 pixels) of
+// a strip of kGrowRows rows; lanes 0 and 63 hold the words just outside the strip,
+// whose inner edge bytes the dilation needs.  Rows stream through a delay line:
+// codes of row y give the horizontal dilation of the first selection at y, then
+// G1 at y-1 (vertical OR of three rows, gated by S' > sigclip), then G2 at y-2
+// (gated by S' > sigfrac*sigclip).  No LDS and no block barrier.
+
+constexpr uint32_t kByteLsb = 0x01010101u;
+
+__device__ __forceinline__ uint32_t shfl_prev(uint32_t v) {   // value of lane-1
+    return (uint32_t)__shfl_up((int)v, 1);
+}
+__device__ __forceinline__ uint32_t shfl_next(uint32_t v) {   // value of lane+1
+    return (uint32_t)__shfl_down((int)v, 1);
+}
+// 3-wide horizontal OR of byte flags (one flag in bit 0 of each byte)
+__device__ __forceinline__ uint32_t hdilate(uint32_t v) {
+    return v | (v << 8) | (v >> 8) | (shfl_prev(v) >> 24) | (shfl_next(v) << 24);
+}
+
+// four bytes of row y starting at pixel x (x multiple of 4); bytes outside the image read 0
+__device__ __forceinline__ uint32_t load_word(const uint8_t *__restrict__ p, int y, int x, int H,
+                                              int W, bool aligned) {
+    if (y < 0 || y >= H || x + 4 <= 0 || x >= W)
+        return 0u;
+    const uint8_t *row = p + (size_t)y * W;
+    if (aligned && x >= 0)
+        return *reinterpret_cast<const uint32_t *>(row + x);
+    uint32_t v = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (x + b >= 0 && x + b < W)
+            v |= (uint32_t)row[x + b] << (8 * b);
+    return v;
+}
+
+__device__ __forceinline__ void store_word(uint8_t *__restrict__ p, int y, int x, int W,
+                                           bool aligned, uint32_t v) {
+    uint8_t *row = p + (size_t)y * W;
+    if (aligned) {
+        *reinterpret_cast<uint32_t *>(row + x) = v;
+        return;
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if (x + b < W)
+            row[x + b] = (uint8_t)(v >> (8 * b));
+}
+
+__device__ __forceinline__ unsigned int wave_sum(unsigned int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1)
+        v += (unsigned int)__shfl_xor((int)v, o);
+    return v;
+}
 
 __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ frames,
                                                    const TileRef *__restrict__ tiles,
-                                                   DevFrame single, int kiter) {
-    constexpr int CW = kGrowTX + 4, CH = kGrowTY + 4;   // codes, apron 2
-    constexpr int GW = kGrowTX + 2, GH = kGrowTY + 2;   // G1, apron 1
-    constexpr int NW = kThreads / 64;                   // waves
-    constexpr int NP = kGrowTY / NW;                    // rows per wave
-    __shared__ uint8_t sC[CH * CW];
-    __shared__ uint8_t sG1[GH * GW];
-    __shared__ unsigned int sCntNew[NW * NP], sCntM[NW * NP], sOff[NW * NP];
-    __shared__ unsigned int sBase;
-
+                                                   DevFrame single, int kiter, int ntiles) {
+    const int lane = threadIdx.x & 63;
+    const int wt = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);   // wave tile index
+    if (wt >= ntiles)
+        return;
     DevFrame f;
     int y0, x0;
     if (tiles) {
-        const TileRef t = tiles[blockIdx.x];
+        const TileRef t = tiles[wt];
         f = frames[t.frame];
         y0 = t.y0;
         x0 = t.x0;
     } else {
         f = single;
-        y0 = blockIdx.y * kGrowTY;
-        x0 = blockIdx.x * kGrowTX;
+        const int ntx = (f.W + kGrowTX - 1) / kGrowTX;
+        y0 = (wt / ntx) * kGrowTY;
+        x0 = (wt % ntx) * kGrowTX;
     }
     const int k = kiter ? kiter : f.k;
     if (frame_skips(f, k))
         return;
-    const int H = f.H, W = f.W, tid = threadIdx.x;
+    const int H = f.H, W = f.W;
+    const bool aligned = (W & 3) == 0;
+    const int px = x0 - 4 + 4 * lane;                 // first pixel of this lane's word
+    const bool owner = lane >= 1 && lane <= kGrowTX / 4 && px < W;
 
-    for (int i = tid; i < CH * CW; i += kThreads) {
-        const int r = i / CW, c = i - r * CW;
-        const int gy = y0 - 2 + r, gx = x0 - 2 + c;
-        sC[i] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? f.codes[(size_t)gy * W + gx] : 0;
-    }
-    __syncthreads();
-    // G1 = dilate(first) and [S' > sigclip]; cells outside the image stay 0
-    for (int i = tid; i < GH * GW; i += kThreads) {
-        const int r = i / GW, c = i - r * GW;
-        uint8_t any = 0;
+    uint32_t hA0 = 0, hA1 = 0;        // dilated first selection, rows y-2, y-1
+    uint32_t hi1 = 0;                 // [S' > sigclip] at row y-1
+    uint32_t lo1 = 0, lo2 = 0;        // [S' > low] at rows y-1, y-2
+    uint32_t hG0 = 0, hG1 = 0;        // dilated G1 at rows y-3, y-2
+    uint32_t mrow[kGrowTY];
+    unsigned int nnew = 0, nm = 0;
 #pragma unroll
-        for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-            for (int dc = 0; dc < 3; ++dc)
-                any |= sC[(r + dr) * CW + c + dc];
-        sG1[i] = (uint8_t)((any & 1) & (sC[(r + 1) * CW + c + 1] >> 1));
-    }
-    __syncthreads();
-
-    const int lane = tid & 63, w = tid >> 6;
-    const int gx = x0 + lane;
-    unsigned long long balM[NP];
-    bool mine[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        const int row = w * NP + p;
-        const int gy = y0 + row;
-        const bool in = gy < H && gx < W;
-        bool g2 = false, mprev = false;
-        if (in) {
-            uint8_t any = 0;
-#pragma unroll
-            for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-                for (int dc = 0; dc < 3; ++dc)
-                    any |= sG1[(row + dr) * GW + lane + dc];
-            g2 = any && ((sC[(row + 2) * CW + lane + 2] >> 2) & 1);
-            const size_t q = (size_t)gy * W + gx;
-            mprev = f.mask[q] != 0;
-            if (g2 && !mprev)
-                f.mask[q] = 1;
-            if (f.g2)
-                f.g2[q] = g2 ? 1 : 0;
+    for (int t = 0; t < kGrowTY + 4; ++t) {
+        const int y = y0 - 2 + t;
+        const uint32_t c = load_word(f.codes, y, px, H, W, aligned);
+        const uint32_t hA2 = hdilate(c & kByteLsb);
+        const uint32_t hi2 = (c >> 1) & kByteLsb;
+        const uint32_t lo0 = (c >> 2) & kByteLsb;
+        // G1 at row y-1 (zero outside the image: its codes read as 0)
+        const uint32_t g1 = (hA0 | hA1 | hA2) & hi1;
+        const uint32_t hG2 = hdilate(g1);
+        // G2 at row y-2
+        if (t >= 4) {
+            const int r = t - 4;                     // output row y0 + r == y - 2
+            const uint32_t g2 = (hG0 | hG1 | hG2) & lo2;
+            uint32_t m = 0;
+            if (owner && y - 2 < H) {
+                const uint32_t mp = load_word(f.mask, y - 2, px, H, W, aligned);
+                const uint32_t nw = g2 & ~mp;
+                m = mp | g2;
+                if (nw)
+                    store_word(f.mask, y - 2, px, W, aligned, m);
+                if (f.g2)
+                    store_word(f.g2, y - 2, px, W, aligned, g2);
+                nnew += (unsigned int)__popc(nw);
+                nm += (unsigned int)__popc(m);
+            }
+            mrow[r] = m;
         }
-        const bool nw = g2 && !mprev;
-        mine[p] = in && (g2 || mprev);
-        const unsigned long long bn = __ballot(nw);
-        balM[p] = __ballot(mine[p]);
-        if (lane == 0) {
-            sCntNew[w * NP + p] = (unsigned int)__popcll(bn);
-            sCntM[w * NP + p] = (unsigned int)__popcll(balM[p]);
-        }
+        hA0 = hA1; hA1 = hA2;
+        lo2 = lo1; lo1 = lo0;
+        hi1 = hi2;
+        hG0 = hG1; hG1 = hG2;
     }
-    __syncthreads();
-    if (tid == 0) {
-        unsigned int tn = 0, tm = 0;
-        for (int i = 0; i < NW * NP; ++i) {
-            tn += sCntNew[i];
-            sOff[i] = tm;
-            tm += sCntM[i];
-        }
+    // one atomic per wave for the count and one for the list space
+    const unsigned int tn = wave_sum(nnew);
+    unsigned int incl = nm;                          // inclusive prefix over lanes
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned int v = (unsigned int)__shfl_up((int)incl, o);
+        if (lane >= o)
+            incl += v;
+    }
+    const unsigned int total = (unsigned int)__shfl((int)incl, 63);
+    unsigned int base = 0;
+    if (lane == 0) {
         if (tn)
             atomicAdd(&f.nnew[k - 1], (unsigned long long)tn);
-        sBase = tm ? atomicAdd(&f.listlen[k - 1], tm) : 0u;
+        if (total)
+            base = atomicAdd(&f.listlen[k - 1], total);
     }
-    __syncthreads();
-    const unsigned long long below = (1ull << lane) - 1ull;
+    base = (unsigned int)__shfl((int)base, 0);
+    if (!total)
+        return;
+    unsigned int off = base + incl - nm;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        if (mine[p]) {
-            const int gy = y0 + w * NP + p;
-            const unsigned int off = sBase + sOff[w * NP + p] + (unsigned int)__popcll(balM[p] & below);
-            f.list[off] = (uint32_t)gy * (uint32_t)W + (uint32_t)gx;
+    for (int r = 0; r < kGrowTY; ++r) {
+        uint32_t m = mrow[r];
+        while (m) {
+            const int b = __ffs(m) - 1;              // bit 8*j marks pixel j
+            f.list[off++] = (uint32_t)(y0 + r) * (uint32_t)W + (uint32_t)(px + (b >> 3));
+            m &= m - 1;
         }
     }
 }
@@ -480,7 +554,7 @@ __global__ void k_stats(const DevFrame *__restrict__ frames, int nframes,
 template <int R>
 __global__ __launch_bounds__(kThreads) void k_debug_median(const float *__restrict__ in, int H,
                                                            int W, float *__restrict__ out) {
-    constexpr int TY = (R == 1) ? 1 : 2, TX = (R == 1) ? 8 : 4;
+    constexpr int TY = (R == 1) ? 1 : 2, TX = (R == 1) ? kRun3 : (R == 2 ? 5 : 4);
     constexpr int PH = TY + 2 * R, PW = TX + 2 * R;
     const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY;
     const int t = blockIdx.x * kThreads + threadIdx.x;
@@ -494,16 +568,16 @@ __global__ __launch_bounds__(kThreads) void k_debug_median(const float *__restri
         for (int j = 0; j < PW; ++j)
             v[i * PW + j] = in[(size_t)clampi(y0 - R + i, H) * W + clampi(x0 - R + j, W)];
     if constexpr (R == 1) {
-        float a[10], b[10], c[10];
+        float a[kRun3 + 2], b[kRun3 + 2], c[kRun3 + 2];
 #pragma unroll
-        for (int j = 0; j < 10; ++j) {
+        for (int j = 0; j < kRun3 + 2; ++j) {
             a[j] = v[j];
             b[j] = v[PW + j];
             c[j] = v[2 * PW + j];
         }
-        med3_run8(a, b, c, o);
+        med3_run<kRun3>(a, b, c, o);
     } else if constexpr (R == 2) {
-        med5_t2x4(v, o);
+        med5_t2x5(v, o);
     } else {
         med7_t2x4(v, o);
     }
@@ -557,14 +631,12 @@ hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int n
 
 hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
                        const DevFrame &single, int k, hipStream_t s) {
-    if (d_tiles) {
-        if (ntiles <= 0)
-            return hipSuccess;
-        k_grow<<<ntiles, kThreads, 0, s>>>(d_frames, d_tiles, single, k);
-    } else {
-        dim3 grid((single.W + kGrowTX - 1) / kGrowTX, (single.H + kGrowTY - 1) / kGrowTY);
-        k_grow<<<grid, kThreads, 0, s>>>(nullptr, nullptr, single, k);
-    }
+    if (!d_tiles)
+        ntiles = ((single.W + kGrowTX - 1) / kGrowTX) * ((single.H + kGrowTY - 1) / kGrowTY);
+    if (ntiles <= 0)
+        return hipSuccess;
+    constexpr int wpb = kThreads / 64;
+    k_grow<<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(d_frames, d_tiles, single, k, ntiles);
     return hipGetLastError();
 }
 
@@ -581,7 +653,7 @@ hipError_t launch_stats(const DevFrame *d_frames, int nframes, long long *d_stat
 }
 
 hipError_t launch_debug_median(const float *in, int H, int W, int r, float *out, hipStream_t s) {
-    const int ty = (r == 1) ? 1 : 2, tx = (r == 1) ? 8 : 4;
+    const int ty = (r == 1) ? 1 : 2, tx = (r == 1) ? kRun3 : (r == 2 ? 5 : 4);
     const size_t n = (size_t)((H + ty - 1) / ty) * (size_t)((W + tx - 1) / tx);
     const unsigned int grid = (unsigned int)((n + kThreads - 1) / kThreads);
     if (r == 1)
