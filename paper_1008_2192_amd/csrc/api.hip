@@ -198,15 +198,15 @@ static crb_status ws_reserve(Workspace *ws, size_t bytes) {
 }
 
 // enqueue niter iterations for one frame whose DevFrame is complete
-static crb_status enqueue_single(const DevFrame &f, bool zero_mask, hipStream_t s) {
+static crb_status enqueue_single(const DevFrame &f, hipStream_t s) {
     const size_t npix = (size_t)f.H * (size_t)f.W;
-    hipError_t e = launch_init(nullptr, 1, f, npix, zero_mask, s);
+    hipError_t e = launch_init(nullptr, 1, f, npix, s);
     for (int k = 1; e == hipSuccess && k <= f.niter; ++k) {
         e = launch_detect(nullptr, nullptr, 0, f, k, s);
         if (e == hipSuccess)
             e = launch_grow(nullptr, nullptr, 0, f, k, s);
         if (e == hipSuccess)
-            e = launch_replace(nullptr, 1, f, k, replace_grid(npix), s);
+            e = launch_replace(nullptr, 1, nullptr, f, k, replace_grid(npix), s);
     }
     return hip_status(e, "kernel launch");
 }
@@ -281,10 +281,10 @@ crb_status crb_lacosmic(const float *img, int32_t H, int32_t W, float gain, floa
     const FrameWs L = ws_layout(H, W);
     if ((st = ws_reserve(ws, L.total)) != CRB_OK)
         return st;
-    const int flags = g_early_stop.load() ? 0 : kNoEarlyStop;
+    const int flags = (g_early_stop.load() ? 0 : kNoEarlyStop) | kFreshMask;
     DevFrame f = make_devframe(img, out_clean, out_mask, ws->buf, L, H, W, gain, readnoise, sky,
                                sigclip, sigfrac, objlim, niter, flags);
-    if ((st = enqueue_single(f, true, s)) != CRB_OK)
+    if ((st = enqueue_single(f, s)) != CRB_OK)
         return st;
     return ok();
 }
@@ -318,7 +318,7 @@ crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_fr
     hipError_t e = hipMemcpyAsync(out_M, M_prev, npix, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess)
         return hip_status(e, "hipMemcpyAsync");
-    if ((st = enqueue_single(f, false, s)) != CRB_OK)
+    if ((st = enqueue_single(f, s)) != CRB_OK)
         return st;
     e = hipMemcpyAsync(out_n_new, f.nnew, sizeof(int64_t), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess)
@@ -390,6 +390,7 @@ struct crb_plan {
     TileRef *d_tgrow = nullptr;
     int ntgrow = 0;
     long long *d_stats = nullptr;
+    unsigned int *d_prefix = nullptr;   // flat offsets of the frames' flagged lists
     int rgrid = 1;
     bool use_graph = false;
     hipGraph_t graph = nullptr;
@@ -437,7 +438,7 @@ static crb_status plan_enqueue(crb_plan *p) {
     memset(&none, 0, sizeof(none));
     hipError_t e = tmark_begin(p, kKindInit);
     if (e == hipSuccess)
-        e = launch_init(p->d_frames, p->n, none, p->max_pix, true, s);
+        e = launch_init(p->d_frames, p->n, none, p->max_pix, s);
     if (e == hipSuccess)
         e = tmark_end(p);
     for (int k = 1; e == hipSuccess && k <= p->kmax; ++k) {
@@ -448,7 +449,8 @@ static crb_status plan_enqueue(crb_plan *p) {
             (e = launch_grow(p->d_frames, p->d_tgrow, p->ntgrow, none, k, s)) == hipSuccess &&
             (e = tmark_end(p)) == hipSuccess &&
             (e = tmark_begin(p, kKindReplace)) == hipSuccess &&
-            (e = launch_replace(p->d_frames, p->n, none, k, p->rgrid, s)) == hipSuccess)
+            (e = launch_list_prefix(p->d_frames, p->n, k, p->d_prefix, s)) == hipSuccess &&
+            (e = launch_replace(p->d_frames, p->n, p->d_prefix, none, k, p->rgrid, s)) == hipSuccess)
             e = tmark_end(p);
     }
     if (e == hipSuccess)
@@ -488,7 +490,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     crb_status st;
     std::vector<FrameWs> lay(n);
     std::vector<size_t> off(n);
-    size_t total = 0, max_pix = 0;
+    size_t total = 0, max_pix = 0, all_pix = 0;
     int kmax = 0;
     size_t ntdet = 0, ntgrow = 0;
     for (int i = 0; i < n; ++i) {
@@ -504,6 +506,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
         off[i] = total;
         total += lay[i].total;
         max_pix = npix > max_pix ? npix : max_pix;
+        all_pix += npix;
         kmax = f.niter > kmax ? f.niter : kmax;
         ntdet += (size_t)((f.H + kDetectTY - 1) / kDetectTY) * ((f.W + kDetectTX - 1) / kDetectTX);
         ntgrow += (size_t)((f.H + kGrowTY - 1) / kGrowTY) * ((f.W + kGrowTX - 1) / kGrowTX);
@@ -524,7 +527,8 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     const size_t o_tdet = o_frames + ((n * sizeof(DevFrame) + 255) / 256) * 256;
     const size_t o_tgrow = o_tdet + ((ntdet * sizeof(TileRef) + 255) / 256) * 256;
     const size_t o_stats = o_tgrow + ((ntgrow * sizeof(TileRef) + 255) / 256) * 256;
-    const size_t bytes = o_stats + ((2 * n * sizeof(long long) + 255) / 256) * 256;
+    const size_t o_prefix = o_stats + ((2 * n * sizeof(long long) + 255) / 256) * 256;
+    const size_t bytes = o_prefix + (((n + 1) * sizeof(unsigned int) + 255) / 256) * 256;
 
     crb_plan *p = new (std::nothrow) crb_plan();
     if (!p)
@@ -557,6 +561,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     p->d_tdet = reinterpret_cast<TileRef *>(p->dmem + o_tdet);
     p->d_tgrow = reinterpret_cast<TileRef *>(p->dmem + o_tgrow);
     p->d_stats = reinterpret_cast<long long *>(p->dmem + o_stats);
+    p->d_prefix = reinterpret_cast<unsigned int *>(p->dmem + o_prefix);
     p->ntdet = (int)ntdet;
     p->ntgrow = (int)ntgrow;
 
@@ -568,7 +573,8 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
         const crb_frame &f = frames[i];
         hf[i] = make_devframe(f.img, f.out_clean, f.out_mask, p->dmem + off[i], lay[i], f.H, f.W,
                               f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac, f.objlim,
-                              f.niter, f.flags & CRB_FLAG_NO_EARLY_STOP ? kNoEarlyStop : 0);
+                              f.niter,
+                              (f.flags & CRB_FLAG_NO_EARLY_STOP ? kNoEarlyStop : 0) | kFreshMask);
         for (int y = 0; y < f.H; y += kDetectTY)
             for (int x = 0; x < f.W; x += kDetectTX)
                 td.push_back(TileRef{i, y, x, 0});
@@ -576,7 +582,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
             for (int x = 0; x < f.W; x += kGrowTX)
                 tg.push_back(TileRef{i, y, x, 0});
     }
-    p->rgrid = replace_grid(max_pix);
+    p->rgrid = replace_grid(all_pix);
     e = hipMemcpy(p->d_frames, hf.data(), n * sizeof(DevFrame), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(p->d_tdet, td.data(), td.size() * sizeof(TileRef), hipMemcpyHostToDevice);

@@ -21,8 +21,10 @@ constexpr int kThreads = 256;
 constexpr int kKindInit = 0, kKindDetect = 1, kKindGrow = 2, kKindReplace = 3;
 constexpr int kNumKernelKinds = 4;
 
-// Early-stop control bit in DevFrame::flags (same value as CRB_FLAG_NO_EARLY_STOP).
+// DevFrame::flags bits.  kNoEarlyStop has the value of CRB_FLAG_NO_EARLY_STOP;
+// kFreshMask: the mask is uninitialised before iteration 1, which then writes all of it.
 constexpr int kNoEarlyStop = 1;
+constexpr int kFreshMask = 1 << 8;
 
 // Everything a kernel needs to know about one frame.  All pointers are device
 // pointers; J is the image being cleaned in place (out_clean).
@@ -47,21 +49,33 @@ struct TileRef {                  // one (frame, tile origin) work item
     int frame, y0, x0, pad;
 };
 
-// Copies img into J (when they differ), optionally clears the mask, clears counters.
+// Clears the counters; for frames with niter == 0 also copies img into J and clears
+// the mask (otherwise iteration 1 does both: detection copies img into J, the grow
+// writes the whole mask when kFreshMask is set).
 hipError_t launch_init(const DevFrame *d_frames, int nframes, const DevFrame &single,
-                       size_t max_pixels, bool zero_mask, hipStream_t s);
+                       size_t max_pixels, hipStream_t s);
 // Detection (codes) for one frame (d_tiles == null: grid over `single`) or a work list.
 hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
                          const DevFrame &single, int k, hipStream_t s);
 // Two-stage grow, new-flag count, cumulative mask, flagged list.
 hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
                        const DevFrame &single, int k, hipStream_t s);
-// Masked-median replacement of every pixel on the flagged list.
-hipError_t launch_replace(const DevFrame *d_frames, int nframes, const DevFrame &single, int k,
-                          int grid, hipStream_t s);
+// Offsets of each frame's flagged list in one flat index space (batched path):
+// d_prefix[i] = sum of the list lengths of frames before i; d_prefix[n] = total.
+hipError_t launch_list_prefix(const DevFrame *d_frames, int nframes, int k,
+                              unsigned int *d_prefix, hipStream_t s);
+// Masked-median replacement of every pixel on the flagged lists (d_prefix from
+// launch_list_prefix for a batch; null for `single`).
+hipError_t launch_replace(const DevFrame *d_frames, int nframes, const unsigned int *d_prefix,
+                          const DevFrame &single, int k, int grid, hipStream_t s);
 // Per-frame (iters_run, n_flagged) into d_stats[2 * i].
 hipError_t launch_stats(const DevFrame *d_frames, int nframes, long long *d_stats,
                         hipStream_t s);
+
+// Serving rounds: per frame, n_k of the iteration f.k just run and the running total
+// of flagged pixels, into d_stats[2 * i] and d_stats[2 * i + 1].
+hipError_t launch_round_stats(const DevFrame *d_frames, int nframes, long long *d_stats,
+                              hipStream_t s);
 
 hipError_t launch_debug_median(const float *in, int H, int W, int r, float *out, hipStream_t s);
 hipError_t launch_debug_fp64(const double *x, const double *y, int n, double *out_sqrt,

@@ -130,7 +130,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     if (frame_skips(f, k))
         return;
     const int H = f.H, W = f.W, tid = threadIdx.x;
-    const float *__restrict__ J = f.J;
+    // iteration 1 reads the input frame and initialises J with the tile's own pixels
+    const float *__restrict__ J = (k == 1) ? f.img : f.J;
 
     // J over [y0-4, y0+TY+4) x [x0-4, x0+TX+4), clamped reads
     for (int i = tid; i < L::JH * L::JW; i += kThreads) {
@@ -138,6 +139,13 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         sJ[i] = J[(size_t)clampi(y0 - 4 + r, H) * W + clampi(x0 - 4 + c, W)];
     }
     __syncthreads();
+    if (k == 1 && f.img != f.J) {
+        for (int i = tid; i < TY * TX; i += kThreads) {
+            const int r = i / TX, c = i - r * TX;
+            if (y0 + r < H && x0 + c < W)
+                f.J[(size_t)(y0 + r) * W + x0 + c] = sJ[(r + 4) * L::JW + c + 4];
+        }
+    }
 
     // med3(J) over [y0-3, y0+TY+3) x [x0-3, x0+TX+3)
     {
@@ -379,6 +387,7 @@ __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ 
         return;
     const int H = f.H, W = f.W;
     const bool aligned = (W & 3) == 0;
+    const bool fresh = k == 1 && (f.flags & kFreshMask);   // mask not yet initialised
     const int px = x0 - 4 + 4 * lane;                 // first pixel of this lane's word
     const bool owner = lane >= 1 && lane <= kGrowTX / 4 && px < W;
 
@@ -404,10 +413,10 @@ __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ 
             const uint32_t g2 = (hG0 | hG1 | hG2) & lo2;
             uint32_t m = 0;
             if (owner && y - 2 < H) {
-                const uint32_t mp = load_word(f.mask, y - 2, px, H, W, aligned);
+                const uint32_t mp = fresh ? 0u : load_word(f.mask, y - 2, px, H, W, aligned);
                 const uint32_t nw = g2 & ~mp;
                 m = mp | g2;
-                if (nw)
+                if (nw || fresh)
                     store_word(f.mask, y - 2, px, W, aligned, m);
                 if (f.g2)
                     store_word(f.g2, y - 2, px, W, aligned, g2);
@@ -488,18 +497,68 @@ __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p) {
     f.J[p] = (ia == ib) ? a : (float)(((double)a + (double)b) * 0.5);
 }
 
+__global__ __launch_bounds__(kThreads) void k_list_prefix(const DevFrame *__restrict__ frames,
+                                                          int nframes, int kiter,
+                                                          unsigned int *__restrict__ prefix) {
+    __shared__ unsigned int sPart[kThreads];
+    __shared__ unsigned int sCarry;
+    if (threadIdx.x == 0)
+        sCarry = 0;
+    __syncthreads();
+    for (int base = 0; base < nframes; base += kThreads) {
+        const int i = base + threadIdx.x;
+        unsigned int len = 0;
+        if (i < nframes) {
+            const DevFrame &f = frames[i];
+            const int k = kiter ? kiter : f.k;
+            len = frame_skips(f, k) ? 0u : f.listlen[k - 1];
+        }
+        sPart[threadIdx.x] = len;
+        __syncthreads();
+        for (int o = 1; o < kThreads; o <<= 1) {      // inclusive scan
+            const unsigned int v = threadIdx.x >= o ? sPart[threadIdx.x - o] : 0u;
+            __syncthreads();
+            sPart[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (i < nframes)
+            prefix[i] = sCarry + sPart[threadIdx.x] - len;
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1)
+            sCarry += sPart[kThreads - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        prefix[nframes] = sCarry;
+}
+
 __global__ __launch_bounds__(kThreads) void k_replace(const DevFrame *__restrict__ frames,
-                                                      int nframes, DevFrame single, int kiter) {
-    const int nf = frames ? nframes : 1;
-    for (int fi = 0; fi < nf; ++fi) {
-        const DevFrame f = frames ? frames[fi] : single;
-        const int k = kiter ? kiter : f.k;
-        if (frame_skips(f, k))
-            continue;
-        const unsigned int n = f.listlen[k - 1];
-        for (unsigned int i = blockIdx.x * kThreads + threadIdx.x; i < n;
-             i += gridDim.x * kThreads)
-            replace_one(f, f.list[i]);
+                                                      int nframes,
+                                                      const unsigned int *__restrict__ prefix,
+                                                      DevFrame single, int kiter) {
+    const unsigned int stride = gridDim.x * kThreads;
+    unsigned int i = blockIdx.x * kThreads + threadIdx.x;
+    if (!frames) {
+        const int k = kiter ? kiter : single.k;
+        if (frame_skips(single, k))
+            return;
+        const unsigned int n = single.listlen[k - 1];
+        for (; i < n; i += stride)
+            replace_one(single, single.list[i]);
+        return;
+    }
+    const unsigned int total = prefix[nframes];
+    for (; i < total; i += stride) {
+        int lo = 0, hi = nframes - 1;                  // last frame with prefix <= i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const DevFrame &f = frames[lo];
+        replace_one(f, f.list[i - prefix[lo]]);
     }
 }
 
@@ -508,20 +567,22 @@ __global__ __launch_bounds__(kThreads) void k_replace(const DevFrame *__restrict
 // ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kThreads) void k_init(const DevFrame *__restrict__ frames,
-                                                   int nframes, DevFrame single, int zero_mask) {
+                                                   int nframes, DevFrame single) {
     const int nf = frames ? nframes : 1;
     const size_t gid = (size_t)blockIdx.x * kThreads + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * kThreads;
     for (int fi = 0; fi < nf; ++fi) {
         const DevFrame f = frames ? frames[fi] : single;
-        const size_t n = (size_t)f.H * (size_t)f.W;
-        if (f.img != f.J)
-            for (size_t i = gid; i < n; i += stride)
-                f.J[i] = f.img[i];
-        if (zero_mask)
-            for (size_t i = gid; i < n; i += stride)
+        if (f.niter == 0) {
+            const size_t n = (size_t)f.H * (size_t)f.W;
+            for (size_t i = gid; i < n; i += stride) {
+                if (f.img != f.J)
+                    f.J[i] = f.img[i];
                 f.mask[i] = 0;
-        if (gid < (size_t)kMaxIter) {
+            }
+        }
+        // counters restart at a frame's first iteration (f.k is 0 outside serving)
+        if (f.nnew && f.k <= 1 && gid < (size_t)kMaxIter) {
             f.nnew[gid] = 0ull;
             f.listlen[gid] = 0u;
         }
@@ -544,6 +605,19 @@ __global__ void k_stats(const DevFrame *__restrict__ frames, int nframes,
             break;
     }
     stats[2 * i] = iters;
+    stats[2 * i + 1] = total;
+}
+
+__global__ void k_round_stats(const DevFrame *__restrict__ frames, int nframes,
+                              long long *__restrict__ stats) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nframes)
+        return;
+    const DevFrame f = frames[i];
+    long long total = 0;
+    for (int k = 1; k <= f.k; ++k)
+        total += (long long)f.nnew[k - 1];
+    stats[2 * i] = (long long)f.nnew[f.k - 1];
     stats[2 * i + 1] = total;
 }
 
@@ -610,9 +684,15 @@ static unsigned int grid_for(size_t items, unsigned int cap) {
 }
 
 hipError_t launch_init(const DevFrame *d_frames, int nframes, const DevFrame &single,
-                       size_t max_pixels, bool zero_mask, hipStream_t s) {
+                       size_t max_pixels, hipStream_t s) {
     const unsigned int grid = grid_for(max_pixels > (size_t)kMaxIter ? max_pixels : kMaxIter, 4096);
-    k_init<<<grid, kThreads, 0, s>>>(d_frames, nframes, single, zero_mask ? 1 : 0);
+    k_init<<<grid, kThreads, 0, s>>>(d_frames, nframes, single);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_prefix(const DevFrame *d_frames, int nframes, int k,
+                              unsigned int *d_prefix, hipStream_t s) {
+    k_list_prefix<<<1, kThreads, 0, s>>>(d_frames, nframes, k, d_prefix);
     return hipGetLastError();
 }
 
@@ -640,15 +720,21 @@ hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int nti
     return hipGetLastError();
 }
 
-hipError_t launch_replace(const DevFrame *d_frames, int nframes, const DevFrame &single, int k,
-                          int grid, hipStream_t s) {
-    k_replace<<<grid < 1 ? 1 : grid, kThreads, 0, s>>>(d_frames, nframes, single, k);
+hipError_t launch_replace(const DevFrame *d_frames, int nframes, const unsigned int *d_prefix,
+                          const DevFrame &single, int k, int grid, hipStream_t s) {
+    k_replace<<<grid < 1 ? 1 : grid, kThreads, 0, s>>>(d_frames, nframes, d_prefix, single, k);
     return hipGetLastError();
 }
 
 hipError_t launch_stats(const DevFrame *d_frames, int nframes, long long *d_stats,
                         hipStream_t s) {
     k_stats<<<(nframes + 63) / 64, 64, 0, s>>>(d_frames, nframes, d_stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_round_stats(const DevFrame *d_frames, int nframes, long long *d_stats,
+                              hipStream_t s) {
+    k_round_stats<<<(nframes + 63) / 64, 64, 0, s>>>(d_frames, nframes, d_stats);
     return hipGetLastError();
 }
 
