@@ -67,6 +67,56 @@ def describe(name, frames):
             "frames": 1, "pixels": px, "niter": 4}
 
 
+def _pool_frame(args):
+    """A frame in electrons (gain 1, read noise 5.5 e-)."""
+    from paper_1008_2192_amd import synth
+    si, j = args
+    H, W = synth.C4_SIZES[si]
+    return synth.c1_density_frame(H, W, 5000 + 4 * si + j, 1.0, 5.5).img
+
+
+def serving_leg(rate, seconds, workers, budget=64 << 30):
+    """Requests arrive as a Poisson process; sizes drawn uniformly from the four
+    batch sizes, each with its own gain and read noise.  Pixel content comes from a
+    pool of 4 frames per size generated in electrons (the request's seed picks one)
+    and divided by the request's gain, which keeps generation time bounded while the
+    noise level matches the request's parameters.  Served twice on the same trace:
+    continuous batching (64 slots) and one frame at a time (1 slot)."""
+    from paper_1008_2192_amd import serving, synth
+    reqs = synth.c5_stream(rate=rate, duration=seconds)
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        pool = list(ex.map(_pool_frame, [(si, j) for si in range(4) for j in range(4)]))
+    sizes = list(synth.C4_SIZES)
+    frames, params = [], []
+    for r in reqs:
+        si = sizes.index((r.H, r.W))
+        frames.append((pool[4 * si + (r.seed % 4)] / np.float32(r.gain)).astype(np.float32))
+        params.append(dict(gain=r.gain, readnoise=r.readnoise, niter=4))
+    arrivals = [r.t_arrival for r in reqs]
+    out = {"trace": f"Poisson arrivals at {rate:g} frames/s over {seconds:g} s "
+                    f"({len(reqs)} requests), sizes uniform over 800x800, 1024x1024, "
+                    f"2048x4096, 4096x2048, per-request gain U(1,8) and read noise U(3,8), "
+                    f"niter 4 with early stop, HBM budget {budget >> 30} GiB; latency from "
+                    f"submit (host buffer) to result in host memory"}
+    for name, slots in (("continuous", 64), ("sequential", 1)):
+        srv = serving.Server(budget, max_slots=slots)
+        srv.submit(pool[0], 1.0, 5.0)               # warm-up request
+        srv.drain()
+        res = serving.replay(srv, arrivals, frames, params)
+        srv.close()
+        out[name] = res.summary()
+        print(f"[bench] serving {name}: {out[name]}", file=sys.stderr, flush=True)
+    # saturation: the whole trace arrives at once
+    for name, slots in (("burst_continuous", 64), ("burst_sequential", 1)):
+        srv = serving.Server(budget, max_slots=slots)
+        n = min(len(frames), 128)
+        res = serving.replay(srv, [0.0] * n, frames[:n], params[:n])
+        srv.close()
+        out[name] = res.summary()
+        print(f"[bench] serving {name}: {out[name]}", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(frames_for_cpu):
     """The FP64 oracle as it stands, single-threaded, on a bounded sample."""
     from oracle import ref
@@ -96,6 +146,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the Poisson request trace (0 skips serving)")
+    ap.add_argument("--serve-rate", type=float, default=40.0)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -215,6 +268,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * src.numel() * 4
+
+    if args.serve_seconds > 0 and args.workload == "c4":
+        del items
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(args.serve_rate, args.serve_seconds, args.workers)
 
     if not args.no_cpu_baseline:
         sample = [f for f in frames if f.img.shape == (800, 800)][:2] or frames[:1]

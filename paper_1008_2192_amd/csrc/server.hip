@@ -331,6 +331,9 @@ static crb_status finish_round(crb_server *s) {
         r->state = kDraining;
         s->draining.push_back(r);
     }
+    // frames admitted while the round ran were appended after its members
+    for (size_t i = s->round_members.size(); i < s->active.size(); ++i)
+        still.push_back(s->active[i]);
     s->active.swap(still);
     s->round_members.clear();
     s->round_busy = false;

@@ -82,3 +82,15 @@ def test_batched_rejects_bad_frames(L):
     arr[1].out_clean = arr[0].out_clean            # two frames writing one buffer
     assert L.crb_lacosmic_batched(arr, 2, None) == -1
     assert L.crb_lacosmic_batched(arr, 0, None) == -1
+
+
+def test_server_argument_validation(L):
+    out = ctypes.c_void_p()
+    assert L.crb_server_create(0, 4, ctypes.byref(out)) == -1
+    assert L.crb_server_create(1 << 30, 0, ctypes.byref(out)) == -1
+    rid = ctypes.c_int64()
+    assert L.crb_server_submit(None, ctypes.c_void_p(16), 4, 4, 1.0, 5.0, 0.0, 4.5, 0.3, 4.0, 4,
+                               ctypes.c_void_p(32), ctypes.c_void_p(48), ctypes.byref(rid)) == -1
+    n = ctypes.c_int32()
+    assert L.crb_server_poll(None, None, None, 0, ctypes.byref(n)) == -1
+    assert L.crb_server_pending(None) == 0
