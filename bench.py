@@ -67,6 +67,35 @@ def describe(name, frames):
             "frames": 1, "pixels": px, "niter": 4}
 
 
+KERNEL_SOURCES = ("csrc/kernels.hip", "csrc/kernels.h", "csrc/medtile.inc")
+COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_detect_batch64_counters.md")
+
+
+def profiled_traffic():
+    """HBM bytes per detection launch from the committed counter summary, if it was
+    taken on the current kernel sources (else None)."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1008_2192_amd", rel), "rb") as f:
+            h.update(f.read())
+    try:
+        text = open(COUNTERS_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if ":" in line and not line.startswith(("|", "#", "`")):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip().split()[0] if v.strip() else ""
+    if vals.get("kernel_source_sha256") != h.hexdigest():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def _pool_frame(args):
     """A frame in electrons (gain 1, read noise 5.5 e-)."""
     from paper_1008_2192_amd import synth
@@ -209,7 +238,8 @@ def main():
                                       "S, S', F^, thresholds)",
             "achieved": round(achieved / 1e12, 3), "peak": round(roofline.ALU_PEAK / 1e12, 3),
             "unit": "Tlane-op/s", "frac": round(achieved / roofline.ALU_PEAK, 4),
-            "traffic": None, "ops_per_pixel": round(ops["total"], 2),
+            "traffic": profiled_traffic() if args.workload == "c4" else None,
+            "ops_per_pixel": round(ops["total"], 2),
             "pixels_per_launch": total_px, "avg_launch_ms": round(det_avg_s * 1e3, 4),
             "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}}
 
