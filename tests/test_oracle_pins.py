@@ -39,8 +39,12 @@ def clamp(i, n):
 
 def noise_level(s, gain, rn, sky=0.0):
     """N for a flat region of level s ADU: sqrt(g (s + sky) + rn^2) / g (electron
-    Poisson variance plus read noise, expressed in ADU)."""
-    return math.sqrt(gain * (s + sky) + rn * rn) / gain
+    Poisson variance plus read noise, expressed in ADU); a non-positive level is
+    replaced by 1e-4 ADU, which keeps N defined on sky-subtracted data."""
+    level = s + sky
+    if level <= 0:
+        level = 1e-4
+    return math.sqrt(gain * level + rn * rn) / gain
 
 
 # ---------------------------------------------------------------------------
@@ -174,7 +178,8 @@ def test_ramp_not_flagged_and_sprime_zero():
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("gain,rn,s,sky", [(7.0, 5.0, 50.0, 0.0), (1.0, 5.0, 100.0, 0.0),
-                                           (1.5, 4.0, 200.0, 30.0)])
+                                           (1.5, 4.0, 200.0, 30.0), (2.0, 0.5, 0.0, 0.0),
+                                           (1.0, 3.0, -20.0, 5.0)])
 def test_single_pixel_hit_threshold(gain, rn, s, sky):
     """L+(p0) = 2A (each of the four sub-pixel terms is 2A), zero elsewhere; med5(S)
     = 0 so S' = S = 2A / (2 N0) = A / N0; F = 0 so the contrast is A/N0 / 0.01.
@@ -198,6 +203,22 @@ def test_single_pixel_hit_threshold(gain, rn, s, sky):
             assert tr["Jnext"][p0] == s
         r = ref.lacosmic(img.astype(np.float32), gain, rn, sky=sky, niter=4, early_stop=False)
         assert list(r["counts"]) == [expect, 0, 0, 0]
+        # with early stop the run ends after the first iteration that selects nothing new
+        r = ref.lacosmic(img.astype(np.float32), gain, rn, sky=sky, niter=4, early_stop=True)
+        assert r["iters"] == 1 + expect and list(r["counts"]) == [expect, 0][:1 + expect]
+
+
+def test_threshold_is_strict():
+    """A statistic equal to its threshold is not selected.  Exact case: gain 1, read
+    noise 0 and a flat level 16 give N0 = 4 exactly; a hit of 18 gives L+ = 36 and
+    S' = 36 / 8 = 4.5 = sigclip in binary64 without rounding."""
+    img = np.full((13, 13), 16.0)
+    for A, expect in [(18.0, 0), (18.0 + 2.0 ** -20, 1)]:
+        img[6, 6] = 16.0 + A
+        tr = ref.iterate(img, np.zeros(img.shape, np.uint8), 1.0, 0.0, trace=True)
+        assert tr["noise"][6, 6] == 4.0
+        assert (tr["sprime"][6, 6] == 4.5) == (A == 18.0)
+        assert tr["first"][6, 6] == expect and tr["G2"].sum() == expect
 
 
 # ---------------------------------------------------------------------------
