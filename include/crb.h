@@ -132,6 +132,24 @@ void crb_plan_destroy(crb_plan *plan);
 crb_status crb_plan_set_timing(crb_plan *plan, int32_t enable);
 crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
 
+/*
+ * The paper's partitioned run (Section 6.2): the frame is split into ny x nx
+ * rectangles of nearly equal area (row and column bounds floor(H*i/ny),
+ * floor(W*j/nx)), each extended by `border` pixels beyond every edge it shares with
+ * another rectangle (clamped to the frame), and each extended subimage is cleaned as
+ * an independent frame (its own clamped edges, niter iterations, early stop on)
+ * in one batched pass; only the interiors are written to out_clean / out_mask.
+ * With border >= 8 * niter the result equals crb_lacosmic's (an iteration's
+ * dependency radius is 8 pixels); smaller borders show the subimage edge effects
+ * the paper's 6-pixel border trades against overlap.  Synchronous on the calling
+ * thread's stream; allocates temporary device memory for the subimages.
+ *   ny, nx >= 1 with ny <= H and nx <= W; border >= 0; other arguments as crb_lacosmic.
+ */
+crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int32_t W, float gain,
+                                    float readnoise, float sky, float sigclip, float sigfrac,
+                                    float objlim, int32_t niter, int32_t ny, int32_t nx,
+                                    int32_t border, float *out_clean, uint8_t *out_mask);
+
 /* Per-thread stream used by crb_lacosmic (NULL: default stream). */
 crb_status crb_set_stream(void *hip_stream);
 /* Library-wide option (CRB_OPT_*). */

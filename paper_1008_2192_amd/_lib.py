@@ -19,7 +19,7 @@ CRB_OPT_EARLY_STOP = 1
 STATUS = {0: "CRB_OK", -1: "CRB_EINVAL", -2: "CRB_ENOMEM", -3: "CRB_EDEVICE",
           -4: "CRB_ETOOBIG", -5: "CRB_EBUSY"}
 
-EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_plan_create", "crb_plan_run",
+EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned", "crb_plan_create", "crb_plan_run",
            "crb_plan_stats", "crb_plan_destroy", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option",
            "crb_last_error", "crb_workspace_bytes", "crb_release_workspace",
            "crb_server_create", "crb_server_submit", "crb_server_poll", "crb_server_pending",
@@ -59,6 +59,8 @@ def lib():
     vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     L.crb_lacosmic.argtypes = [vp, i32, i32, f32, f32, f32, f32, f32, f32, i32, vp, vp]
     L.crb_lacosmic_batched.argtypes = [ctypes.POINTER(Frame), i32, vp]
+    L.crb_lacosmic_partitioned.argtypes = [vp, i32, i32, f32, f32, f32, f32, f32, f32, i32,
+                                           i32, i32, i32, vp, vp]
     L.crb_plan_create.argtypes = [ctypes.POINTER(Frame), i32, vp, i32, ctypes.POINTER(vp)]
     L.crb_plan_run.argtypes = [vp]
     L.crb_plan_stats.argtypes = [vp, ctypes.POINTER(Frame), i32]
@@ -86,7 +88,8 @@ def lib():
     L.crb_debug_detect.argtypes = [vp, ctypes.POINTER(Frame), vp]
     L.crb_debug_median.argtypes = [vp, i32, i32, i32, vp]
     L.crb_debug_fp64.argtypes = [vp, vp, i32, vp, vp]
-    for name in ("crb_lacosmic", "crb_lacosmic_batched", "crb_plan_create", "crb_plan_run",
+    for name in ("crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned",
+                 "crb_plan_create", "crb_plan_run",
                  "crb_plan_stats", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option", "crb_release_workspace",
                  "crb_server_create", "crb_server_submit", "crb_server_poll",
                  "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64"):
@@ -137,6 +140,22 @@ def lacosmic(img: torch.Tensor, gain: float, readnoise: float, sky: float = 0.0,
     check("crb_lacosmic", L.crb_lacosmic(img.data_ptr(), H, W, gain, readnoise, sky, sigclip,
                                          sigfrac, objlim, niter, out_clean.data_ptr(),
                                          out_mask.data_ptr()))
+    return out_clean, out_mask
+
+
+def lacosmic_partitioned(img: torch.Tensor, gain: float, readnoise: float, ny: int, nx: int,
+                         border: int, sky: float = 0.0, sigclip: float = 4.5,
+                         sigfrac: float = 0.3, objlim: float = 4.0, niter: int = 4,
+                         stream: Optional[torch.cuda.Stream] = None):
+    """crb_lacosmic_partitioned: independent subimages with a border, stitched."""
+    _dev2d(img, torch.float32, "img")
+    H, W = img.shape
+    out_clean = torch.empty_like(img)
+    out_mask = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    set_stream(stream)
+    check("crb_lacosmic_partitioned", lib().crb_lacosmic_partitioned(
+        img.data_ptr(), H, W, gain, readnoise, sky, sigclip, sigfrac, objlim, niter, ny, nx,
+        border, out_clean.data_ptr(), out_mask.data_ptr()))
     return out_clean, out_mask
 
 

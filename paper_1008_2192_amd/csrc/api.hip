@@ -699,3 +699,99 @@ crb_status crb_lacosmic_batched(crb_frame *frames, int32_t n, void *hip_stream) 
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// partitioned run (the paper's subimages with a border)
+// ---------------------------------------------------------------------------
+
+extern "C" crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int32_t W, float gain,
+                                               float readnoise, float sky, float sigclip,
+                                               float sigfrac, float objlim, int32_t niter,
+                                               int32_t ny, int32_t nx, int32_t border,
+                                               float *out_clean, uint8_t *out_mask) {
+    crb_status st = check_frame_args(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim, niter);
+    if (st != CRB_OK)
+        return st;
+    const size_t npix = (size_t)H * (size_t)W;
+    if ((st = check_buffers(img, out_clean, out_mask, npix)) != CRB_OK)
+        return st;
+    if (ny < 1 || nx < 1 || ny > H || nx > W || border < 0)
+        return fail(CRB_EINVAL, "partition %d x %d with border %d does not fit %d x %d", ny, nx,
+                    border, H, W);
+    hipStream_t s = t_stream;
+    const int nsub = ny * nx;
+    std::vector<SubRect> subs(nsub);
+    std::vector<size_t> off(nsub);
+    size_t total = 0, max_sub = 0;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+    for (int i = 0; i < ny; ++i) {
+        for (int j = 0; j < nx; ++j) {
+            SubRect &r = subs[i * nx + j];
+            r.y0 = (int)((int64_t)H * i / ny);
+            r.y1 = (int)((int64_t)H * (i + 1) / ny);
+            r.x0 = (int)((int64_t)W * j / nx);
+            r.x1 = (int)((int64_t)W * (j + 1) / nx);
+            r.a0 = r.y0 - border > 0 ? r.y0 - border : 0;
+            r.b0 = r.x0 - border > 0 ? r.x0 - border : 0;
+            r.h = (r.y1 + border < H ? r.y1 + border : H) - r.a0;
+            r.w = (r.x1 + border < W ? r.x1 + border : W) - r.b0;
+            const size_t n = (size_t)r.h * r.w;
+            off[i * nx + j] = total;
+            total += 2 * al(4 * n) + al(n);
+            max_sub = n > max_sub ? n : max_sub;
+        }
+    }
+    const size_t o_tab = total;
+    const size_t bytes = o_tab + al(nsub * sizeof(SubRect));
+    char *tmp = nullptr;
+    hipError_t e = hipMalloc((void **)&tmp, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CRB_ENOMEM, "subimages of %zu bytes: %s", bytes, hipGetErrorString(e));
+    }
+    std::vector<crb_frame> frames(nsub);
+    for (int q = 0; q < nsub; ++q) {
+        SubRect &r = subs[q];
+        const size_t n = (size_t)r.h * r.w;
+        r.sub_img = reinterpret_cast<float *>(tmp + off[q]);
+        r.sub_clean = reinterpret_cast<float *>(tmp + off[q] + al(4 * n));
+        r.sub_mask = reinterpret_cast<uint8_t *>(tmp + off[q] + 2 * al(4 * n));
+        crb_frame &f = frames[q];
+        memset(&f, 0, sizeof(f));
+        f.img = r.sub_img;
+        f.out_clean = r.sub_clean;
+        f.out_mask = r.sub_mask;
+        f.H = r.h;
+        f.W = r.w;
+        f.gain = gain;
+        f.readnoise = readnoise;
+        f.sky = sky;
+        f.sigclip = sigclip;
+        f.sigfrac = sigfrac;
+        f.objlim = objlim;
+        f.niter = niter;
+    }
+    SubRect *d_subs = reinterpret_cast<SubRect *>(tmp + o_tab);
+    crb_plan *plan = nullptr;
+    e = hipMemcpy(d_subs, subs.data(), nsub * sizeof(SubRect), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_extract(img, W, d_subs, nsub, max_sub, s);
+    if (e != hipSuccess) {
+        (void)hipFree(tmp);
+        return hip_status(e, "subimage extraction");
+    }
+    st = crb_plan_create(frames.data(), nsub, s, 0, &plan);
+    if (st == CRB_OK)
+        st = crb_plan_run(plan);
+    if (st == CRB_OK) {
+        e = launch_stitch(out_clean, out_mask, W, d_subs, nsub, max_sub, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        st = hip_status(e, "subimage stitching");
+    }
+    if (plan)
+        crb_plan_destroy(plan);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(tmp);
+    return st == CRB_OK ? ok() : st;
+}

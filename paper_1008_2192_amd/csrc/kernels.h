@@ -77,6 +77,20 @@ hipError_t launch_stats(const DevFrame *d_frames, int nframes, long long *d_stat
 hipError_t launch_round_stats(const DevFrame *d_frames, int nframes, long long *d_stats,
                               hipStream_t s);
 
+// Subimage of a frame: the extended rectangle [a0, a0+h) x [b0, b0+w) is copied into
+// sub (pitch w); its interior [y0, y1) x [x0, x1) (image coordinates) is written back.
+struct SubRect {
+    float *sub_img;        // h x w copy of the extended rectangle
+    float *sub_clean;      // h x w cleaned subimage
+    uint8_t *sub_mask;     // h x w mask of the subimage
+    int a0, b0, h, w;      // extended rectangle
+    int y0, y1, x0, x1;    // interior
+};
+hipError_t launch_extract(const float *img, int W, const SubRect *d_subs, int nsub,
+                          size_t max_pixels, hipStream_t s);
+hipError_t launch_stitch(float *out_clean, uint8_t *out_mask, int W, const SubRect *d_subs,
+                         int nsub, size_t max_pixels, hipStream_t s);
+
 hipError_t launch_debug_median(const float *in, int H, int W, int r, float *out, hipStream_t s);
 hipError_t launch_debug_fp64(const double *x, const double *y, int n, double *out_sqrt,
                              double *out_div, hipStream_t s);

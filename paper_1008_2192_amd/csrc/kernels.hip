@@ -95,11 +95,14 @@ constexpr int kRun3 = 14;
 
 template <int TY, int TX>
 struct DetectLayout {
-    static constexpr int JH = TY + 8, JW = TX + 8;              // J, apron 4
-    static constexpr int MH = TY + 6, MW = TX + 6;              // med3(J), apron 3
-    static constexpr int MWP = (MW + 3) & ~3;                   // 16-byte rows
-    static constexpr int SH = TY + 4, SW = TX + 4;              // S (binary64), apron 2
-    static_assert(JH * JW >= TY * TX, "med7 results reuse the J buffer");
+    // logical extents of the LDS planes and their row pitches; the pitches spread the
+    // stage-1 and stage-2 scalar accesses over the LDS banks (med3 rows stay 16-byte
+    // aligned for float4 reads, S rows for double2 reads)
+    static constexpr int JH = TY + 8, JW = TX + 8, JWP = TX + 11;   // J, apron 4
+    static constexpr int MH = TY + 6, MW = TX + 6, MWP = TX + 12;   // med3(J), apron 3
+    static constexpr int SH = TY + 4, SW = TX + 4, SWP = TX + 6;    // S (binary64), apron 2
+    static_assert(MWP % 4 == 0 && SWP % 2 == 0, "vector-read alignment");
+    static_assert(JH * JWP >= TY * TX, "med7 results reuse the J buffer");
 };
 
 template <int TY, int TX>
@@ -108,9 +111,9 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
               DevFrame single, int kiter) {
     using L = DetectLayout<TY, TX>;
     static_assert(TY % 2 == 0 && TX % 4 == 0, "detection tile must hold 2x4 thread tiles");
-    __shared__ __align__(16) float sJ[L::JH * L::JW];      // J, later med7(med3)
+    __shared__ __align__(16) float sJ[L::JH * L::JWP];     // J, later med7(med3)
     __shared__ __align__(16) float sM3[L::MH * L::MWP];
-    __shared__ __align__(16) double sS[L::SH * L::SW];
+    __shared__ __align__(16) double sS[L::SH * L::SWP];
     __shared__ float sM5[TY * TX];                          // med5(J) at the outputs
     float *const sM7 = sJ;
 
@@ -136,14 +139,14 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // J over [y0-4, y0+TY+4) x [x0-4, x0+TX+4), clamped reads
     for (int i = tid; i < L::JH * L::JW; i += kThreads) {
         const int r = i / L::JW, c = i - r * L::JW;
-        sJ[i] = J[(size_t)clampi(y0 - 4 + r, H) * W + clampi(x0 - 4 + c, W)];
+        sJ[r * L::JWP + c] = J[(size_t)clampi(y0 - 4 + r, H) * W + clampi(x0 - 4 + c, W)];
     }
     __syncthreads();
     if (k == 1 && f.img != f.J) {
         for (int i = tid; i < TY * TX; i += kThreads) {
             const int r = i / TX, c = i - r * TX;
             if (y0 + r < H && x0 + c < W)
-                f.J[(size_t)(y0 + r) * W + x0 + c] = sJ[(r + 4) * L::JW + c + 4];
+                f.J[(size_t)(y0 + r) * W + x0 + c] = sJ[(r + 4) * L::JWP + c + 4];
         }
     }
 
@@ -156,9 +159,9 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             float a[kRun3 + 2], b[kRun3 + 2], c[kRun3 + 2], o[kRun3];
 #pragma unroll
             for (int j = 0; j < kRun3 + 2; ++j) {
-                a[j] = sJ[r * L::JW + cx + j];
-                b[j] = sJ[(r + 1) * L::JW + cx + j];
-                c[j] = sJ[(r + 2) * L::JW + cx + j];
+                a[j] = sJ[r * L::JWP + cx + j];
+                b[j] = sJ[(r + 1) * L::JWP + cx + j];
+                c[j] = sJ[(r + 2) * L::JWP + cx + j];
             }
             med3_run<kRun3>(a, b, c, o);
 #pragma unroll
@@ -182,7 +185,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             for (int i = 0; i < TTY + 4; ++i)
 #pragma unroll
                 for (int j = 0; j < PW; ++j)
-                    v[i * PW + j] = sJ[(r + i) * L::JW + c + j];
+                    v[i * PW + j] = sJ[(r + i) * L::JWP + c + j];
             med5_t2x5(v, m5);
 #pragma unroll
             for (int i = 0; i < TTY; ++i) {
@@ -194,7 +197,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                     if (m <= 0.0)
                         m = 1e-4;
                     const double N = sqrt(gain * m + rn2) / gain;
-                    sS[(r + i) * L::SW + c + j] = lp / (2.0 * N);
+                    sS[(r + i) * L::SWP + c + j] = lp / (2.0 * N);
                     const int cy = r + i - 2, cxx = c + j - 2;
                     if (cy >= 0 && cy < TY && cxx >= 0 && cxx < TX)
                         sM5[cy * TX + cxx] = m5[i * TTX + j];
@@ -218,7 +221,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             const int r = i / L::SW, c = i - r * L::SW;
             const int gy = y0 - 2 + r, gx = x0 - 2 + c;
             if (gy < 0 || gy >= H || gx < 0 || gx >= W)
-                sS[i] = sS[(clampi(gy, H) - (y0 - 2)) * L::SW + (clampi(gx, W) - (x0 - 2))];
+                sS[r * L::SWP + c] =
+                    sS[(clampi(gy, H) - (y0 - 2)) * L::SWP + (clampi(gx, W) - (x0 - 2))];
         }
         __syncthreads();
     }
@@ -261,7 +265,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             for (int i = 0; i < 6; ++i)
 #pragma unroll
                 for (int j = 0; j < 8; j += 2) {
-                    const double2 q = *reinterpret_cast<const double2 *>(&sS[(r + i) * L::SW + c + j]);
+                    const double2 q = *reinterpret_cast<const double2 *>(&sS[(r + i) * L::SWP + c + j]);
                     v[i * 8 + j] = q.x;
                     v[i * 8 + j + 1] = q.y;
                 }
@@ -273,7 +277,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 for (int j = 0; j < 4; ++j) {
                     const int gx = x0 + c + j;
                     if (gy < H && gx < W) {
-                        const double S = sS[(r + i + 2) * L::SW + c + j + 2];
+                        const double S = sS[(r + i + 2) * L::SWP + c + j + 2];
                         const double sp = S - ms[i * 4 + j];
                         const bool hi = sp > sigclip;
                         const bool lo = sp > lowlim;
@@ -622,6 +626,36 @@ __global__ void k_round_stats(const DevFrame *__restrict__ frames, int nframes,
 }
 
 // ---------------------------------------------------------------------------
+// subimage partition (the paper's 2-D split with a border, Section 6.2)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kThreads) void k_extract(const float *__restrict__ img, int W,
+                                                      const SubRect *__restrict__ subs) {
+    const SubRect r = subs[blockIdx.y];
+    const size_t n = (size_t)r.h * r.w;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kThreads) {
+        const int y = (int)(i / r.w), x = (int)(i - (size_t)y * r.w);
+        r.sub_img[i] = img[(size_t)(r.a0 + y) * W + r.b0 + x];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_stitch(float *__restrict__ out_clean,
+                                                     uint8_t *__restrict__ out_mask, int W,
+                                                     const SubRect *__restrict__ subs) {
+    const SubRect r = subs[blockIdx.y];
+    const int ih = r.y1 - r.y0, iw = r.x1 - r.x0;
+    const size_t n = (size_t)ih * iw;
+    for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * kThreads) {
+        const int y = r.y0 + (int)(i / iw), x = r.x0 + (int)(i % iw);
+        const size_t q = (size_t)(y - r.a0) * r.w + (x - r.b0);
+        out_clean[(size_t)y * W + x] = r.sub_clean[q];
+        out_mask[(size_t)y * W + x] = r.sub_mask[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // parity-test kernels: the median networks alone, binary64 sqrt and division
 // ---------------------------------------------------------------------------
 
@@ -735,6 +769,20 @@ hipError_t launch_stats(const DevFrame *d_frames, int nframes, long long *d_stat
 hipError_t launch_round_stats(const DevFrame *d_frames, int nframes, long long *d_stats,
                               hipStream_t s) {
     k_round_stats<<<(nframes + 63) / 64, 64, 0, s>>>(d_frames, nframes, d_stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract(const float *img, int W, const SubRect *d_subs, int nsub,
+                          size_t max_pixels, hipStream_t s) {
+    dim3 grid(grid_for(max_pixels, 1024), nsub);
+    k_extract<<<grid, kThreads, 0, s>>>(img, W, d_subs);
+    return hipGetLastError();
+}
+
+hipError_t launch_stitch(float *out_clean, uint8_t *out_mask, int W, const SubRect *d_subs,
+                         int nsub, size_t max_pixels, hipStream_t s) {
+    dim3 grid(grid_for(max_pixels, 1024), nsub);
+    k_stitch<<<grid, kThreads, 0, s>>>(out_clean, out_mask, W, d_subs);
     return hipGetLastError();
 }
 
