@@ -150,6 +150,25 @@ crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int32_t W, floa
                                     float objlim, int32_t niter, int32_t ny, int32_t nx,
                                     int32_t border, float *out_clean, uint8_t *out_mask);
 
+/*
+ * The paper's framework probes (Section 6.3.2 POISSON, Section 6.3.3 WAITER): work
+ * functions of uniform per-pixel cost and no border, run by a persistent farm of
+ * `workers` workgroups that take bands of `band_rows` rows from an atomic ticket, as
+ * CRBLASTER's actors take subimages; timing the farm against `workers` gives the
+ * framework's efficiency independent of L.A.Cosmic.
+ *   CRB_WORK_POISSON: out = a Poisson deviate with mean in (Knuth's multiplication
+ *     method; mean clamped to [0, 500], non-finite -> 0; uniforms from Philox4x32-10
+ *     keyed by `seed`, counter = (pixel index, draw / 4); e^-mean by range reduction
+ *     and a degree-13 polynomial), bit-identical to the oracle's crb_ref_poisson;
+ *   CRB_WORK_WAITER: waits in[i] microseconds per pixel (clamped to [0, 1e6]), out = in.
+ * Device pointers, H*W FP32 each; workers >= 1, band_rows >= 1.  Asynchronous on
+ * the calling thread's stream (uses 4 bytes of that stream's workspace).
+ */
+#define CRB_WORK_POISSON 1
+#define CRB_WORK_WAITER 2
+crb_status crb_work_run(int32_t kind, const float *in, int32_t H, int32_t W, uint64_t seed,
+                        int32_t workers, int32_t band_rows, float *out);
+
 /* Per-thread stream used by crb_lacosmic (NULL: default stream). */
 crb_status crb_set_stream(void *hip_stream);
 /* Library-wide option (CRB_OPT_*). */

@@ -289,3 +289,90 @@ int crb_ref_lacosmic(const float *img, int H, int W, const crb_ref_params *p,
     free(J); free(Jn); free(M); free(Mn);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* POISSON work function (test infrastructure, as above)                      */
+/* ------------------------------------------------------------------------- */
+
+/* Philox4x32-10 (Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC 2011): ten rounds of two 32x32->64 multiplications with the
+ * round constants below, the key bumped by the Weyl constants after each round. */
+void crb_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* exp(-x) for 0 <= x <= 745: x = k ln2 + r with |r| <= ln2/2 (ln2 split in a high
+ * part with trailing zero bits and a low part, so k * ln2_hi is exact), then the
+ * Taylor series of exp(r) to degree 13 by Horner's rule, scaled by 2^-k. */
+double crb_ref_expneg(double x)
+{
+    const double ln2_hi = 6.93147180369123816490e-01;
+    const double ln2_lo = 1.90821492927058770002e-10;
+    const double inv_ln2 = 1.44269504088896338700e+00;
+    double y = -x;
+    double kf = floor(y * inv_ln2 + 0.5);
+    double r = (y - kf * ln2_hi) - kf * ln2_lo;
+    double p = 1.0 / 6227020800.0;                   /* 1/13! */
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)kf);
+}
+
+int crb_ref_poisson(const float *in, long long n, unsigned long long seed, float *out)
+{
+    if (!in || !out || n < 0)
+        return -1;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (long long i = 0; i < n; ++i) {
+        double mean = (double)in[i];
+        if (!(mean > 0.0))
+            mean = 0.0;           /* also maps NaN to 0 */
+        if (mean > 500.0)
+            mean = 500.0;
+        const double limit = crb_ref_expneg(mean);
+        uint32_t ctr[4] = {(uint32_t)i, (uint32_t)((unsigned long long)i >> 32), 0, 0};
+        uint32_t words[4];
+        long long k = 0;
+        double prod = 1.0;
+        for (uint32_t j = 0;; ++j) {
+            if (j % 4 == 0) {
+                ctr[2] = j / 4;
+                crb_ref_philox4x32_10(ctr, key, words);
+            }
+            const double u = ((double)words[j % 4] + 0.5) * (1.0 / 4294967296.0);
+            prod = prod * u;
+            if (!(prod > limit))
+                break;
+            ++k;
+        }
+        out[i] = (float)k;
+    }
+    return 0;
+}

@@ -77,6 +77,18 @@ int crb_ref_lacosmic(const float *img, int H, int W, const crb_ref_params *p,
                      int niter, int early_stop, double *out_clean, uint8_t *out_mask,
                      int *out_iters, long long *out_counts);
 
+/* ---- POISSON work function (the paper's framework probe, Section 6.3.2) ----
+ * out[i] = a Poisson deviate with mean in[i], drawn by Knuth's multiplication
+ * method: multiply uniforms until the product falls to exp(-mean) or below; the
+ * count of factors minus one is the deviate.  Means are clamped to [0, 500]
+ * (non-finite means give 0).  Uniform j of pixel i is
+ * (x + 0.5) * 2^-32 for the 32-bit word x = Philox4x32-10(counter = (i_lo, i_hi,
+ * j / 4, 0), key = (seed_lo, seed_hi)) word j % 4.  exp is computed by the
+ * range-reduced polynomial in crb_ref_expneg (basic operations only, fixed order). */
+void crb_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double crb_ref_expneg(double x);            /* exp(-x) for x in [0, 745] */
+int crb_ref_poisson(const float *in, long long n, unsigned long long seed, float *out);
+
 #ifdef __cplusplus
 }
 #endif

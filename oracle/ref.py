@@ -68,8 +68,13 @@ def lib():
         L.crb_ref_lacosmic.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Params),
                                        ctypes.c_int, ctypes.c_int, dp, dp,
                                        ctypes.POINTER(ctypes.c_int), dp]
+        L.crb_ref_philox4x32_10.argtypes = [dp, dp, dp]
+        L.crb_ref_philox4x32_10.restype = None
+        L.crb_ref_expneg.argtypes = [ctypes.c_double]
+        L.crb_ref_expneg.restype = ctypes.c_double
+        L.crb_ref_poisson.argtypes = [dp, ctypes.c_longlong, ctypes.c_ulonglong, dp]
         for f in (L.crb_ref_median_filter, L.crb_ref_lplus, L.crb_ref_iterate,
-                  L.crb_ref_lacosmic):
+                  L.crb_ref_lacosmic, L.crb_ref_poisson):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -153,3 +158,25 @@ def lacosmic_frame(frame, niter: Optional[int] = None, early_stop=True) -> dict:
     return lacosmic(frame.img, frame.gain, frame.readnoise, frame.sky, frame.sigclip,
                     frame.sigfrac, frame.objlim,
                     frame.niter if niter is None else niter, early_stop)
+
+
+def philox4x32_10(ctr, key) -> list:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().crb_ref_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return [int(v) for v in out]
+
+
+def expneg(x: float) -> float:
+    return float(lib().crb_ref_expneg(float(x)))
+
+
+def poisson(means: np.ndarray, seed: int) -> np.ndarray:
+    """The POISSON work function: one deviate per pixel (float32 counts)."""
+    m = np.ascontiguousarray(means, dtype=np.float32)
+    out = np.empty_like(m)
+    rc = lib().crb_ref_poisson(_ptr(m), m.size, int(seed), _ptr(out))
+    if rc:
+        raise ValueError("crb_ref_poisson failed")
+    return out

@@ -24,7 +24,9 @@ EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned", "
            "crb_last_error", "crb_workspace_bytes", "crb_release_workspace",
            "crb_server_create", "crb_server_submit", "crb_server_poll", "crb_server_pending",
            "crb_server_destroy", "crb_debug_iterate", "crb_debug_detect", "crb_debug_median",
-           "crb_debug_fp64"]
+           "crb_debug_fp64", "crb_work_run"]
+CRB_WORK_POISSON = 1
+CRB_WORK_WAITER = 2
 
 
 class CrbError(RuntimeError):
@@ -88,11 +90,13 @@ def lib():
     L.crb_debug_detect.argtypes = [vp, ctypes.POINTER(Frame), vp]
     L.crb_debug_median.argtypes = [vp, i32, i32, i32, vp]
     L.crb_debug_fp64.argtypes = [vp, vp, i32, vp, vp]
+    L.crb_work_run.argtypes = [i32, vp, i32, i32, ctypes.c_uint64, i32, i32, vp]
     for name in ("crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned",
                  "crb_plan_create", "crb_plan_run",
                  "crb_plan_stats", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option", "crb_release_workspace",
                  "crb_server_create", "crb_server_submit", "crb_server_poll",
-                 "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64"):
+                 "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64",
+                 "crb_work_run"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -294,3 +298,17 @@ def debug_fp64(x: torch.Tensor, y: torch.Tensor, stream: Optional[torch.cuda.Str
 
 def workspace_bytes(H: int, W: int) -> int:
     return int(lib().crb_workspace_bytes(H, W))
+
+
+def work_run(kind: int, x: torch.Tensor, seed: int = 0, workers: int = 1024,
+             band_rows: int = 1, out: Optional[torch.Tensor] = None,
+             stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """crb_work_run: the POISSON or WAITER work function on a persistent tile farm."""
+    _dev2d(x, torch.float32, "x")
+    if out is None:
+        out = torch.empty_like(x)
+    set_stream(stream)
+    check("crb_work_run", lib().crb_work_run(kind, x.data_ptr(), x.shape[0], x.shape[1],
+                                             int(seed) & (2 ** 64 - 1), workers, band_rows,
+                                             out.data_ptr()))
+    return out

@@ -289,6 +289,44 @@ crb_status crb_lacosmic(const float *img, int32_t H, int32_t W, float gain, floa
     return ok();
 }
 
+crb_status crb_work_run(int32_t kind, const float *in, int32_t H, int32_t W, uint64_t seed,
+                        int32_t workers, int32_t band_rows, float *out) {
+    if (kind != CRB_WORK_POISSON && kind != CRB_WORK_WAITER)
+        return fail(CRB_EINVAL, "unknown work function %d", kind);
+    if (!in || !out)
+        return fail(CRB_EINVAL, "null pointer");
+    if (H < 1 || W < 1)
+        return fail(CRB_EINVAL, "image size %d x %d: both must be >= 1", H, W);
+    if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX)
+        return fail(CRB_ETOOBIG, "image exceeds 2^31-1 pixels");
+    if (workers < 1 || workers > (1 << 20) || band_rows < 1)
+        return fail(CRB_EINVAL, "workers must lie in [1, 2^20] and band_rows >= 1");
+    if (in != out && ranges_overlap(in, (size_t)H * W * 4, out, (size_t)H * W * 4))
+        return fail(CRB_EINVAL, "out partially overlaps in");
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess)
+        return hip_status(e, "device query");
+    hipStream_t s = t_stream;
+    Workspace *ws = nullptr;
+    crb_status st = ws_get(s, &ws);
+    if (st != CRB_OK)
+        return st;
+    std::lock_guard<std::mutex> g(ws->mu);
+    if ((st = ws_reserve(ws, 256)) != CRB_OK)
+        return st;
+    unsigned int *ticket = reinterpret_cast<unsigned int *>(ws->buf);
+    e = launch_farm_reset(ticket, s);
+    if (e == hipSuccess)
+        e = launch_farm(kind == CRB_WORK_POISSON ? kWorkPoisson : kWorkWaiter, in, H, W,
+                        (unsigned long long)seed, workers, band_rows, out, ticket,
+                        (long long)khz, s);
+    st = hip_status(e, "kernel launch");
+    return st == CRB_OK ? ok() : st;
+}
+
 crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_frame *p,
                              uint8_t *out_G2, uint8_t *out_M, float *out_J_next,
                              int64_t *out_n_new) {

@@ -1,0 +1,38 @@
+"""GPU tile farm with the paper's POISSON and WAITER work functions (Section 6.3):
+POISSON deviates are bit-identical to the oracle for any farm layout; WAITER copies
+its input and takes at least the waited time."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ref
+from paper_1008_2192_amd import _lib
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.mark.parametrize("H,W,workers,band", [(97, 131, 1, 1), (97, 131, 7, 5), (256, 256, 512, 1),
+                                              (1, 3000, 3, 1), (600, 1, 64, 100)])
+def test_poisson_matches_oracle(H, W, workers, band):
+    rng = np.random.default_rng(H * 1000 + W)
+    x = rng.uniform(0, 60, (H, W)).astype(np.float32)
+    x.flat[:6] = [0.0, -2.0, np.nan, 1e-20, 499.9, 2e3][: x.size][:6] if x.size >= 6 else x.flat[:6]
+    g = _lib.work_run(_lib.CRB_WORK_POISSON, torch.from_numpy(x).to(DEV), seed=99,
+                      workers=workers, band_rows=band)
+    torch.cuda.synchronize()
+    exp = ref.poisson(x, 99)
+    np.testing.assert_array_equal(g.cpu().numpy(), exp)
+
+
+def test_waiter_copies_and_waits():
+    x = torch.full((64, 64), 50.0, device=DEV)
+    x[0, 0] = -5.0
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    y = _lib.work_run(_lib.CRB_WORK_WAITER, x, workers=1, band_rows=4)
+    e.record()
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
+    # one workgroup of 256 threads: 4096 pixels take >= 16 waits of 50 us
+    assert s.elapsed_time(e) >= 0.8 * 0.98
