@@ -9,12 +9,13 @@ namespace crb {
 
 // Upper bound on iterations per frame (sizes the per-frame counters).
 constexpr int kMaxIter = 1024;
-// Detection tile (outputs per block) and grow tile (outputs per wave: 62 words of
-// 4 pixels by kGrowTY rows).
+// Detection tile (outputs per block) and grow tile (outputs per wave: 62 groups of
+// 16 pixels by kGrowTY rows).
 constexpr int kDetectTY = 32;
 constexpr int kDetectTX = 64;
 constexpr int kGrowTY = 32;
-constexpr int kGrowTX = 248;
+constexpr int kGrowTYSmall = 8;     // strip height for single frames below 2^22 pixels
+constexpr int kGrowTX = 992;
 constexpr int kThreads = 256;
 
 // Kernel classes for per-launch timing (crb_plan_kernel_times order).

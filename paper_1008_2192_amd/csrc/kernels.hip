@@ -308,16 +308,22 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
 // grow + count + cumulative mask + flagged list
 // ---------------------------------------------------------------------------
 //
-// Word-parallel: a lane holds the codes of 4 horizontally adjacent pixels in one
-// dword (bytes 0..3 = pixels x..x+3), so a 3-wide dilation is two byte shifts plus
-// the edge bytes of the neighbouring lanes.  A wave covers 62 words (248 pixels) of
-// a strip of kGrowRows rows; lanes 0 and 63 hold the words just outside the strip,
-// whose inner edge bytes the dilation needs.  Rows stream through a delay line:
-// codes of row y give the horizontal dilation of the first selection at y, then
-// G1 at y-1 (vertical OR of three rows, gated by S' > sigclip), then G2 at y-2
-// (gated by S' > sigfrac*sigclip).  No LDS and no block barrier.
+// Word-parallel: a lane holds the codes of 16 horizontally adjacent pixels in four
+// dwords (byte j of dword d = pixel 4d + j), so a 3-wide dilation is byte shifts
+// inside the lane plus the edge bytes of the neighbouring lanes.  A wave covers 62
+// such groups (992 pixels) of a strip of kGrowTY rows; lanes 0 and 63 hold the
+// groups just outside the strip, whose inner edge bytes the dilation needs.  Rows
+// stream through a delay line: codes of row y give the horizontal dilation of the
+// first selection at y, then G1 at y-1 (vertical OR of three rows, gated by
+// S' > sigclip), then G2 at y-2 (gated by S' > sigfrac*sigclip).  No LDS and no
+// block barrier.  The flagged list is written row by row across the wave, so
+// consecutive entries are neighbours in a row.
 
 constexpr uint32_t kByteLsb = 0x01010101u;
+
+struct Px16 {
+    uint32_t d[4];
+};
 
 __device__ __forceinline__ uint32_t shfl_prev(uint32_t v) {   // value of lane-1
     return (uint32_t)__shfl_up((int)v, 1);
@@ -326,38 +332,53 @@ __device__ __forceinline__ uint32_t shfl_next(uint32_t v) {   // value of lane+1
     return (uint32_t)__shfl_down((int)v, 1);
 }
 // 3-wide horizontal OR of byte flags (one flag in bit 0 of each byte)
-__device__ __forceinline__ uint32_t hdilate(uint32_t v) {
-    return v | (v << 8) | (v >> 8) | (shfl_prev(v) >> 24) | (shfl_next(v) << 24);
+__device__ __forceinline__ Px16 hdilate(const Px16 &v) {
+    const uint32_t left = shfl_prev(v.d[3]) >> 24;          // pixel just left of this lane
+    const uint32_t right = shfl_next(v.d[0]) << 24;         // pixel just right of this lane
+    Px16 o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t lo = q == 0 ? left : (v.d[q - 1] >> 24);
+        const uint32_t hi = q == 3 ? right : (v.d[q + 1] << 24);
+        o.d[q] = v.d[q] | (v.d[q] << 8) | (v.d[q] >> 8) | lo | hi;
+    }
+    return o;
 }
 
-// four bytes of row y starting at pixel x (x multiple of 4); bytes outside the image read 0
-__device__ __forceinline__ uint32_t load_word(const uint8_t *__restrict__ p, int y, int x, int H,
-                                              int W, bool aligned) {
-    if (y < 0 || y >= H || x + 4 <= 0 || x >= W)
-        return 0u;
+// 16 bytes of row y starting at pixel x (x multiple of 16); bytes outside read 0
+__device__ __forceinline__ Px16 load16(const uint8_t *__restrict__ p, int y, int x, int H, int W,
+                                       bool aligned) {
+    Px16 v = {{0u, 0u, 0u, 0u}};
+    if (y < 0 || y >= H || x + 16 <= 0 || x >= W)
+        return v;
     const uint8_t *row = p + (size_t)y * W;
-    if (aligned && x >= 0)
-        return *reinterpret_cast<const uint32_t *>(row + x);
-    uint32_t v = 0;
+    if (aligned && x >= 0) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(row + x);
+        v.d[0] = q.x; v.d[1] = q.y; v.d[2] = q.z; v.d[3] = q.w;
+        return v;
+    }
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 16; ++b)
         if (x + b >= 0 && x + b < W)
-            v |= (uint32_t)row[x + b] << (8 * b);
+            v.d[b >> 2] |= (uint32_t)row[x + b] << (8 * (b & 3));
     return v;
 }
 
-__device__ __forceinline__ void store_word(uint8_t *__restrict__ p, int y, int x, int W,
-                                           bool aligned, uint32_t v) {
+__device__ __forceinline__ void store16(uint8_t *__restrict__ p, int y, int x, int W,
+                                        bool aligned, const Px16 &v) {
     uint8_t *row = p + (size_t)y * W;
     if (aligned) {
-        *reinterpret_cast<uint32_t *>(row + x) = v;
+        *reinterpret_cast<uint4 *>(row + x) = make_uint4(v.d[0], v.d[1], v.d[2], v.d[3]);
         return;
     }
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 16; ++b)
         if (x + b < W)
-            row[x + b] = (uint8_t)(v >> (8 * b));
+            row[x + b] = (uint8_t)(v.d[b >> 2] >> (8 * (b & 3)));
 }
+
+// bits 0, 8, 16, 24 of v -> bits 0..3 (the four products land on bits 21..24 without carries)
+__device__ __forceinline__ uint32_t squeeze4(uint32_t v) { return ((v * 0x00204081u) >> 21) & 0xFu; }
 
 __device__ __forceinline__ unsigned int wave_sum(unsigned int v) {
 #pragma unroll
@@ -366,6 +387,17 @@ __device__ __forceinline__ unsigned int wave_sum(unsigned int v) {
     return v;
 }
 
+__device__ __forceinline__ unsigned int wave_incl_scan(unsigned int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned int u = (unsigned int)__shfl_up((int)v, o);
+        if (lane >= o)
+            v += u;
+    }
+    return v;
+}
+
+template <int TYG>
 __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ frames,
                                                    const TileRef *__restrict__ tiles,
                                                    DevFrame single, int kiter, int ntiles) {
@@ -383,51 +415,70 @@ __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ 
     } else {
         f = single;
         const int ntx = (f.W + kGrowTX - 1) / kGrowTX;
-        y0 = (wt / ntx) * kGrowTY;
+        y0 = (wt / ntx) * TYG;
         x0 = (wt % ntx) * kGrowTX;
     }
     const int k = kiter ? kiter : f.k;
     if (frame_skips(f, k))
         return;
     const int H = f.H, W = f.W;
-    const bool aligned = (W & 3) == 0;
+    const bool aligned = (W & 15) == 0;
     const bool fresh = k == 1 && (f.flags & kFreshMask);   // mask not yet initialised
-    const int px = x0 - 4 + 4 * lane;                 // first pixel of this lane's word
-    const bool owner = lane >= 1 && lane <= kGrowTX / 4 && px < W;
+    const int px = x0 - 16 + 16 * lane;                // first pixel of this lane's group
+    const bool owner = lane >= 1 && lane <= kGrowTX / 16 && px < W;
 
-    uint32_t hA0 = 0, hA1 = 0;        // dilated first selection, rows y-2, y-1
-    uint32_t hi1 = 0;                 // [S' > sigclip] at row y-1
-    uint32_t lo1 = 0, lo2 = 0;        // [S' > low] at rows y-1, y-2
-    uint32_t hG0 = 0, hG1 = 0;        // dilated G1 at rows y-3, y-2
-    uint32_t mrow[kGrowTY];
+    Px16 hA0 = {}, hA1 = {};          // dilated first selection, rows y-2, y-1
+    Px16 hi1 = {};                    // [S' > sigclip] at row y-1
+    Px16 lo1 = {}, lo2 = {};          // [S' > low] at rows y-1, y-2
+    Px16 hG0 = {}, hG1 = {};          // dilated G1 at rows y-3, y-2
+    uint32_t mbits[TYG / 2];          // mask bits of the strip, 16 per row
     unsigned int nnew = 0, nm = 0;
 #pragma unroll
-    for (int t = 0; t < kGrowTY + 4; ++t) {
+    for (int t = 0; t < TYG + 4; ++t) {
         const int y = y0 - 2 + t;
-        const uint32_t c = load_word(f.codes, y, px, H, W, aligned);
-        const uint32_t hA2 = hdilate(c & kByteLsb);
-        const uint32_t hi2 = (c >> 1) & kByteLsb;
-        const uint32_t lo0 = (c >> 2) & kByteLsb;
-        // G1 at row y-1 (zero outside the image: its codes read as 0)
-        const uint32_t g1 = (hA0 | hA1 | hA2) & hi1;
-        const uint32_t hG2 = hdilate(g1);
-        // G2 at row y-2
+        const Px16 c = load16(f.codes, y, px, H, W, aligned);
+        Px16 a, hi2, lo0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a.d[q] = c.d[q] & kByteLsb;
+            hi2.d[q] = (c.d[q] >> 1) & kByteLsb;
+            lo0.d[q] = (c.d[q] >> 2) & kByteLsb;
+        }
+        const Px16 hA2 = hdilate(a);
+        Px16 g1;                                      // G1 at row y-1 (zero outside the image)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            g1.d[q] = (hA0.d[q] | hA1.d[q] | hA2.d[q]) & hi1.d[q];
+        const Px16 hG2 = hdilate(g1);
         if (t >= 4) {
             const int r = t - 4;                     // output row y0 + r == y - 2
-            const uint32_t g2 = (hG0 | hG1 | hG2) & lo2;
-            uint32_t m = 0;
+            Px16 g2;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                g2.d[q] = (hG0.d[q] | hG1.d[q] | hG2.d[q]) & lo2.d[q];
+            uint32_t m16 = 0;
             if (owner && y - 2 < H) {
-                const uint32_t mp = fresh ? 0u : load_word(f.mask, y - 2, px, H, W, aligned);
-                const uint32_t nw = g2 & ~mp;
-                m = mp | g2;
-                if (nw || fresh)
-                    store_word(f.mask, y - 2, px, W, aligned, m);
+                const Px16 mp = fresh ? Px16{} : load16(f.mask, y - 2, px, H, W, aligned);
+                Px16 m;
+                uint32_t anynew = 0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const uint32_t nw = g2.d[q] & ~mp.d[q];
+                    m.d[q] = mp.d[q] | g2.d[q];
+                    anynew |= nw;
+                    nnew += (unsigned int)__popc(nw);
+                    m16 |= squeeze4(m.d[q]) << (4 * q);
+                }
+                if (anynew || fresh)
+                    store16(f.mask, y - 2, px, W, aligned, m);
                 if (f.g2)
-                    store_word(f.g2, y - 2, px, W, aligned, g2);
-                nnew += (unsigned int)__popc(nw);
-                nm += (unsigned int)__popc(m);
+                    store16(f.g2, y - 2, px, W, aligned, g2);
+                nm += (unsigned int)__popc(m16);
             }
-            mrow[r] = m;
+            if (r & 1)
+                mbits[r >> 1] |= m16 << 16;
+            else
+                mbits[r >> 1] = m16;
         }
         hA0 = hA1; hA1 = hA2;
         lo2 = lo1; lo1 = lo0;
@@ -436,14 +487,7 @@ __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ 
     }
     // one atomic per wave for the count and one for the list space
     const unsigned int tn = wave_sum(nnew);
-    unsigned int incl = nm;                          // inclusive prefix over lanes
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned int v = (unsigned int)__shfl_up((int)incl, o);
-        if (lane >= o)
-            incl += v;
-    }
-    const unsigned int total = (unsigned int)__shfl((int)incl, 63);
+    const unsigned int total = wave_sum(nm);
     unsigned int base = 0;
     if (lane == 0) {
         if (tn)
@@ -454,15 +498,21 @@ __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ 
     base = (unsigned int)__shfl((int)base, 0);
     if (!total)
         return;
-    unsigned int off = base + incl - nm;
+    // entries row by row across the wave, each lane's pixels in order
 #pragma unroll
-    for (int r = 0; r < kGrowTY; ++r) {
-        uint32_t m = mrow[r];
-        while (m) {
-            const int b = __ffs(m) - 1;              // bit 8*j marks pixel j
-            f.list[off++] = (uint32_t)(y0 + r) * (uint32_t)W + (uint32_t)(px + (b >> 3));
-            m &= m - 1;
+    for (int r = 0; r < TYG; ++r) {
+        uint32_t m16 = (mbits[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+        if (__ballot(m16 != 0) == 0ull)
+            continue;
+        const unsigned int cnt = (unsigned int)__popc(m16);
+        const unsigned int incl = wave_incl_scan(cnt, lane);
+        unsigned int off = base + incl - cnt;
+        while (m16) {
+            const int b = __ffs(m16) - 1;
+            f.list[off++] = (uint32_t)(y0 + r) * (uint32_t)W + (uint32_t)(px + b);
+            m16 &= m16 - 1;
         }
+        base += (unsigned int)__shfl((int)incl, 63);
     }
 }
 
@@ -552,7 +602,17 @@ __global__ __launch_bounds__(kThreads) void k_replace(const DevFrame *__restrict
         return;
     }
     const unsigned int total = prefix[nframes];
-    for (; i < total; i += stride) {
+    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD one
+    // contiguous slice of the list (neighbouring pixels share cache lines in its L2).
+    unsigned int end = total, step = stride;
+    if ((gridDim.x & 7) == 0) {
+        const unsigned int slice = (total + 7) >> 3;
+        const unsigned int first = (blockIdx.x & 7) * slice;
+        end = min(total, first + slice);
+        i = first + (blockIdx.x >> 3) * kThreads + threadIdx.x;
+        step = (gridDim.x >> 3) * kThreads;
+    }
+    for (; i < end; i += step) {
         int lo = 0, hi = nframes - 1;                  // last frame with prefix <= i
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -856,12 +916,24 @@ hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int n
 
 hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
                        const DevFrame &single, int k, hipStream_t s) {
-    if (!d_tiles)
-        ntiles = ((single.W + kGrowTX - 1) / kGrowTX) * ((single.H + kGrowTY - 1) / kGrowTY);
-    if (ntiles <= 0)
-        return hipSuccess;
     constexpr int wpb = kThreads / 64;
-    k_grow<<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(d_frames, d_tiles, single, k, ntiles);
+    if (d_tiles) {
+        if (ntiles <= 0)
+            return hipSuccess;
+        k_grow<kGrowTY><<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(d_frames, d_tiles, single,
+                                                                       k, ntiles);
+        return hipGetLastError();
+    }
+    // a single frame: short strips when the frame is small, so more waves share it
+    const bool small = (size_t)single.H * single.W < ((size_t)1 << 22);
+    const int ty = small ? kGrowTYSmall : kGrowTY;
+    ntiles = ((single.W + kGrowTX - 1) / kGrowTX) * ((single.H + ty - 1) / ty);
+    if (small)
+        k_grow<kGrowTYSmall><<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(nullptr, nullptr,
+                                                                            single, k, ntiles);
+    else
+        k_grow<kGrowTY><<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(nullptr, nullptr, single,
+                                                                       k, ntiles);
     return hipGetLastError();
 }
 
