@@ -135,11 +135,16 @@ def serving_leg(rate, seconds, workers, budget=64 << 30):
         srv.close()
         out[name] = res.summary()
         print(f"[bench] serving {name}: {out[name]}", file=sys.stderr, flush=True)
-    # saturation: the whole trace arrives at once
-    for name, slots in (("burst_continuous", 64), ("burst_sequential", 1)):
+    # saturation: the whole trace arrives at once, from pageable host arrays, and
+    # from page-locked buffers (payloads that already sit in pinned memory)
+    import torch
+    n = min(len(frames), 128)
+    pinned = [torch.from_numpy(f).pin_memory() for f in frames[:n]]
+    for name, slots, src in (("burst_continuous", 64, frames), ("burst_sequential", 1, frames),
+                             ("burst_continuous_pinned", 64, pinned),
+                             ("burst_sequential_pinned", 1, pinned)):
         srv = serving.Server(budget, max_slots=slots)
-        n = min(len(frames), 128)
-        res = serving.replay(srv, [0.0] * n, frames[:n], params[:n])
+        res = serving.replay(srv, [0.0] * n, src[:n], params[:n])
         srv.close()
         out[name] = res.summary()
         print(f"[bench] serving {name}: {out[name]}", file=sys.stderr, flush=True)

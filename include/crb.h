@@ -187,9 +187,12 @@ crb_status crb_release_workspace(void *hip_stream);
  * for every admitted frame, so frames at different iterations share the GPU.
  * Frames leave after niter iterations or an early stop; their results are copied
  * to the caller's host buffers and a completion is reported.
- *   crb_server_submit: host FP32 image (copied at once into pinned staging), host
- *     outputs written at completion; returns CRB_EBUSY when the request can never
- *     fit the budget.  Requests wait in FIFO order until slots and memory allow.
+ *   crb_server_submit: host FP32 image, read when the request is admitted (it must
+ *     stay valid and unchanged until the request completes), host outputs written
+ *     at completion; returns CRB_EBUSY when the request can never fit the budget.
+ *     Requests wait in FIFO order until slots and memory allow.  When the image and
+ *     both outputs are page-locked host memory (hipHostMalloc) they are transferred
+ *     directly; otherwise they pass through the server's pinned staging buffers.
  *   crb_server_poll: enqueue the next round when the previous one has finished,
  *     admit waiting requests, retire finished frames; never blocks.  Writes up to
  *     max_done completed request ids to done_ids and their latency (seconds from

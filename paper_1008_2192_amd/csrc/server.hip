@@ -16,10 +16,15 @@
 
 #include <string.h>
 
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
+#include <functional>
+#include <thread>
 #include <vector>
 
 namespace crb {
@@ -31,11 +36,90 @@ static double now_s() {
 
 enum ReqState { kWaiting, kActive, kDraining };
 
+// Host copies between the caller's buffers and pinned staging, split over a few
+// threads (a single core copies well below the host link's bandwidth).
+class CopyPool {
+  public:
+    explicit CopyPool(unsigned n) {
+        for (unsigned i = 0; i < n; ++i)
+            threads_.emplace_back([this] { run(); });
+    }
+    ~CopyPool() {
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : threads_)
+            t.join();
+    }
+    void copy(void *dst, const void *src, size_t n) {
+        const size_t chunk = (size_t)4 << 20;
+        if (threads_.empty() || n <= chunk) {
+            memcpy(dst, src, n);
+            return;
+        }
+        const size_t parts = (n + chunk - 1) / chunk;
+        std::atomic<size_t> next{0}, done{0};
+        auto work = [&] {
+            for (size_t p; (p = next.fetch_add(1)) < parts;) {
+                const size_t off = p * chunk, len = off + chunk < n ? chunk : n - off;
+                memcpy((char *)dst + off, (const char *)src + off, len);
+                done.fetch_add(1);
+            }
+        };
+        {
+            std::lock_guard<std::mutex> g(mu_);
+            job_ = work;
+            ++gen_;
+        }
+        cv_.notify_all();
+        work();                                   // the calling thread helps
+        while (done.load() < parts)
+            std::this_thread::yield();
+        // retire the job and wait until no worker still holds it (it refers to this frame)
+        std::unique_lock<std::mutex> g(mu_);
+        job_ = nullptr;
+        cv_done_.wait(g, [&] { return busy_ == 0; });
+    }
+
+  private:
+    void run() {
+        uint64_t seen = 0;
+        std::unique_lock<std::mutex> g(mu_);
+        for (;;) {
+            cv_.wait(g, [&] { return stop_ || gen_ != seen; });
+            if (stop_)
+                return;
+            seen = gen_;
+            if (!job_)
+                continue;
+            auto job = job_;
+            ++busy_;
+            g.unlock();
+            job();
+            g.lock();
+            --busy_;
+            cv_done_.notify_all();
+        }
+    }
+    std::vector<std::thread> threads_;
+    std::mutex mu_;
+    std::condition_variable cv_;
+    std::condition_variable cv_done_;
+    std::function<void()> job_;
+    uint64_t gen_ = 0;
+    int busy_ = 0;
+    bool stop_ = false;
+};
+
 struct Request {
     int64_t id = 0;
     int32_t H = 0, W = 0;
     float gain = 0, readnoise = 0, sky = 0, sigclip = 0, sigfrac = 0, objlim = 0;
     int32_t niter = 0;
+    const float *host_img = nullptr;   // caller's input, valid until completion
+    bool direct = false;               // caller's buffers are pinned: no staging copies
     float *host_clean = nullptr;
     uint8_t *host_mask = nullptr;
     double t_submit = 0;
@@ -73,6 +157,7 @@ struct crb_server {
     // memory pools keyed by exact size
     std::multimap<size_t, char *> dev_free, pin_free;
     std::vector<hipEvent_t> event_pool;
+    CopyPool *copies = nullptr;
 };
 
 namespace crb {
@@ -133,6 +218,16 @@ static crb_status dev_alloc(crb_server *s, size_t bytes, char **out) {
     return CRB_OK;
 }
 
+// true when p is page-locked host memory the device can read and write directly
+static bool is_pinned_host(const void *p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
 static size_t frame_dev_bytes(int32_t H, int32_t W) {
     const size_t n = (size_t)H * (size_t)W;
     const size_t img = (4 * n + 255) / 256 * 256;
@@ -155,9 +250,13 @@ static void release_request(crb_server *s, Request *r) {
     delete r;
 }
 
-// admit waiting requests (FIFO) while slots and budget allow
+// Admit waiting requests (FIFO) while slots and budget allow, at most a few per
+// call: staging an admitted frame is a host copy, and the next round should start
+// while later frames are still being staged.
+constexpr int kAdmitPerPoll = 4;
+
 static crb_status admit(crb_server *s) {
-    while (!s->waiting.empty()) {
+    for (int admitted = 0; !s->waiting.empty() && admitted < kAdmitPerPoll; ++admitted) {
         Request *r = s->waiting.front();
         const int held = (int)(s->active.size() + s->draining.size());
         if (held >= s->max_slots || s->in_use + r->dev_bytes > s->budget)
@@ -172,6 +271,13 @@ static crb_status admit(crb_server *s) {
             s->dev_free.emplace(r->dev_bytes, dev);
             return st;
         }
+        if (!r->direct) {
+            if ((st = pin_alloc(s, r->pin_bytes, &r->pin)) != CRB_OK) {
+                s->dev_free.emplace(r->dev_bytes, dev);
+                return st;
+            }
+            s->copies->copy(r->pin, r->host_img, 4 * (size_t)r->H * r->W);
+        }
         const size_t n = (size_t)r->H * (size_t)r->W;
         const size_t img = (4 * n + 255) / 256 * 256;
         const size_t msk = (n + 255) / 256 * 256;
@@ -182,7 +288,8 @@ static crb_status admit(crb_server *s) {
         r->df = make_devframe(J, J, mask, dev + img + msk, ws_layout(r->H, r->W), r->H, r->W,
                               r->gain, r->readnoise, r->sky, r->sigclip, r->sigfrac, r->objlim,
                               r->niter, kFreshMask);
-        hipError_t e = hipMemcpyAsync(J, r->pin, 4 * n, hipMemcpyHostToDevice, s->copy);
+        hipError_t e = hipMemcpyAsync(J, r->direct ? (const void *)r->host_img : r->pin, 4 * n,
+                                      hipMemcpyHostToDevice, s->copy);
         if (e == hipSuccess)
             e = hipEventRecord(r->ev_h2d, s->copy);
         if (e != hipSuccess)
@@ -320,10 +427,12 @@ static crb_status finish_round(crb_server *s) {
             return st;
         const size_t npx = (size_t)r->H * r->W;
         hipError_t e = hipStreamWaitEvent(s->copy, s->ev_round, 0);
+        void *dst_clean = r->direct ? (void *)r->host_clean : (void *)r->pin;
+        void *dst_mask = r->direct ? (void *)r->host_mask : (void *)(r->pin + 4 * npx);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(r->pin, r->df.J, 4 * npx, hipMemcpyDeviceToHost, s->copy);
+            e = hipMemcpyAsync(dst_clean, r->df.J, 4 * npx, hipMemcpyDeviceToHost, s->copy);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(r->pin + 4 * npx, r->df.mask, npx, hipMemcpyDeviceToHost, s->copy);
+            e = hipMemcpyAsync(dst_mask, r->df.mask, npx, hipMemcpyDeviceToHost, s->copy);
         if (e == hipSuccess)
             e = hipEventRecord(r->ev_d2h, s->copy);
         if (e != hipSuccess)
@@ -355,6 +464,15 @@ crb_status crb_server_create(size_t hbm_budget, int32_t max_slots, crb_server **
         return fail(CRB_ENOMEM, "host allocation failed");
     s->budget = hbm_budget;
     s->max_slots = max_slots;
+    {
+        unsigned hw = std::thread::hardware_concurrency();
+        unsigned n = hw > 1 ? (hw < 9 ? hw - 1 : 7) : 0;
+        s->copies = new (std::nothrow) CopyPool(n);
+        if (!s->copies) {
+            delete s;
+            return fail(CRB_ENOMEM, "host allocation failed");
+        }
+    }
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess)
         e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
@@ -403,11 +521,9 @@ crb_status crb_server_submit(crb_server *s, const float *host_img, int32_t H, in
                     frame_dev_bytes(H, W), s->budget);
     }
     r->pin_bytes = 5 * npx;
-    if ((st = pin_alloc(s, r->pin_bytes, &r->pin)) != CRB_OK) {
-        delete r;
-        return st;
-    }
-    memcpy(r->pin, host_img, 4 * npx);
+    r->host_img = host_img;
+    r->direct = is_pinned_host(host_img) && is_pinned_host(host_clean) &&
+                is_pinned_host(host_mask);
     r->id = s->next_id++;
     *out_id = r->id;
     if (niter == 0) {              // nothing to compute: the result is the input
@@ -448,8 +564,10 @@ crb_status crb_server_poll(crb_server *s, int64_t *done_ids, double *done_latenc
         if (q != hipSuccess)
             return hip_status(q, "download event");
         const size_t npx = (size_t)r->H * r->W;
-        memcpy(r->host_clean, r->pin, 4 * npx);
-        memcpy(r->host_mask, r->pin + 4 * npx, npx);
+        if (!r->direct) {
+            s->copies->copy(r->host_clean, r->pin, 4 * npx);
+            s->copies->copy(r->host_mask, r->pin + 4 * npx, npx);
+        }
         done_ids[*n_done] = r->id;
         done_latency[*n_done] = now_s() - r->t_submit;
         ++*n_done;
@@ -511,6 +629,7 @@ void crb_server_destroy(crb_server *s) {
         (void)hipStreamDestroy(s->compute);
     if (s->copy)
         (void)hipStreamDestroy(s->copy);
+    delete s->copies;
     delete s;
 }
 

@@ -27,17 +27,31 @@ class Server:
         self._ids = (ctypes.c_int64 * 256)()
         self._lat = (ctypes.c_double * 256)()
 
-    def submit(self, img: np.ndarray, gain: float, readnoise: float, sky: float = 0.0,
+    def submit(self, img, gain: float, readnoise: float, sky: float = 0.0,
                sigclip: float = 4.5, sigfrac: float = 0.3, objlim: float = 4.0,
                niter: int = 4) -> int:
-        img = np.ascontiguousarray(img, dtype=np.float32)
-        H, W = img.shape
-        clean = np.empty((H, W), np.float32)
-        mask = np.empty((H, W), np.uint8)
+        """img: a numpy array, or a pinned CPU torch tensor (then the outputs are pinned
+        tensors too and the server transfers without staging copies)."""
+        import torch
+        if isinstance(img, torch.Tensor):
+            if img.is_cuda or img.dtype != torch.float32 or img.dim() != 2 or \
+                    not img.is_contiguous():
+                raise ValueError("img must be a contiguous 2-D float32 CPU tensor")
+            H, W = img.shape
+            pinned = img.is_pinned()
+            clean = torch.empty((H, W), dtype=torch.float32, pin_memory=pinned)
+            mask = torch.empty((H, W), dtype=torch.uint8, pin_memory=pinned)
+            p_img, p_clean, p_mask = img.data_ptr(), clean.data_ptr(), mask.data_ptr()
+        else:
+            img = np.ascontiguousarray(img, dtype=np.float32)
+            H, W = img.shape
+            clean = np.empty((H, W), np.float32)
+            mask = np.empty((H, W), np.uint8)
+            p_img, p_clean, p_mask = img.ctypes.data, clean.ctypes.data, mask.ctypes.data
         rid = ctypes.c_int64(0)
         _lib.check("crb_server_submit", _lib.lib().crb_server_submit(
-            self.handle, img.ctypes.data, H, W, gain, readnoise, sky, sigclip, sigfrac, objlim,
-            niter, clean.ctypes.data, mask.ctypes.data, ctypes.byref(rid)))
+            self.handle, p_img, H, W, gain, readnoise, sky, sigclip, sigfrac, objlim,
+            niter, p_clean, p_mask, ctypes.byref(rid)))
         self._outs[rid.value] = (img, clean, mask)    # keep buffers alive until done
         return rid.value
 
@@ -50,6 +64,8 @@ class Server:
         for i in range(n.value):
             rid = int(self._ids[i])
             _, clean, mask = self._outs.pop(rid)
+            if not isinstance(clean, np.ndarray):
+                clean, mask = clean.numpy(), mask.numpy()
             out.append((rid, float(self._lat[i]), clean, mask))
         return out
 
@@ -113,7 +129,7 @@ def replay(server: Server, arrivals: Sequence[float], frames: Sequence, params: 
             j = int(order[i])
             rid = server.submit(frames[j], **params[j])
             idmap[rid] = j
-            px += frames[j].size
+            px += frames[j].shape[0] * frames[j].shape[1]
             i += 1
         for rid, l, clean, mask in server.poll():
             lat.append(l)

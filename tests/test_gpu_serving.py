@@ -102,3 +102,17 @@ def test_realtime_trace_drains():
         c, m = solo(frames[j % len(frames)])
         np.testing.assert_array_equal(res.results[j][0], c)
         np.testing.assert_array_equal(res.results[j][1], m)
+
+
+def test_pinned_buffers_transfer_directly():
+    frames = mixed_frames()[:4]
+    srv = serving.Server(1 << 34, max_slots=4)
+    ids = {srv.submit(torch.from_numpy(f.img).pin_memory(), **params(f)): i
+           for i, f in enumerate(frames)}
+    done = srv.drain()
+    srv.close()
+    assert len(done) == len(frames)
+    for rid, lat, clean, mask in done:
+        c, m = solo(frames[ids[rid]])
+        np.testing.assert_array_equal(clean, c)
+        np.testing.assert_array_equal(mask, m)
