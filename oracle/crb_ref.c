@@ -376,3 +376,76 @@ int crb_ref_poisson(const float *in, long long n, unsigned long long seed, float
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* SOURCES work function (test infrastructure, as above)                      */
+/* ------------------------------------------------------------------------- */
+
+/* Is q = (yq, xq) allowed to sit beside the peak candidate p = (y, x) of value v?
+ * Only a smaller value, or an equal value later in raster order. */
+static int yields_to(float vq, int yq, int xq, float v, int y, int x)
+{
+    if (vq < v)
+        return 1;
+    if (vq == v)
+        return yq > y || (yq == y && xq > x);
+    return 0;
+}
+
+int crb_ref_sources(const float *in, int H, int W, float threshold, float sky, int r, int a,
+                    crb_ref_source *out, long long capacity, long long *count)
+{
+    if (!in || !count || H < 1 || W < 1 || r < 1 || r > 8 || a < 0 || a > 8 ||
+        capacity < 0 || (capacity > 0 && !out) || !isfinite(threshold) || !isfinite(sky))
+        return -1;
+    long long found = 0;
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            const float v = in[(size_t)y * W + x];
+            if (!(v > threshold))
+                continue;
+            int peak = 1;
+            for (int yq = y - r; yq <= y + r && peak; ++yq) {
+                if (yq < 0 || yq >= H)
+                    continue;
+                for (int xq = x - r; xq <= x + r; ++xq) {
+                    if (xq < 0 || xq >= W || (yq == y && xq == x))
+                        continue;
+                    if (!yields_to(in[(size_t)yq * W + xq], yq, xq, v, y, x)) {
+                        peak = 0;
+                        break;
+                    }
+                }
+            }
+            if (!peak)
+                continue;
+            if (found < capacity) {
+                crb_ref_source rec;
+                rec.y = y;
+                rec.x = x;
+                rec.peak = v;
+                rec.npix = 0;
+                rec.flux = 0.0;
+                rec.sy = 0.0;
+                rec.sx = 0.0;
+                for (int dy = -a; dy <= a; ++dy) {
+                    if (y + dy < 0 || y + dy >= H)
+                        continue;
+                    for (int dx = -a; dx <= a; ++dx) {
+                        if (x + dx < 0 || x + dx >= W)
+                            continue;
+                        const double d = (double)in[(size_t)(y + dy) * W + (x + dx)] - (double)sky;
+                        rec.flux = rec.flux + d;
+                        rec.sy = rec.sy + (double)dy * d;
+                        rec.sx = rec.sx + (double)dx * d;
+                        rec.npix += 1;
+                    }
+                }
+                out[found] = rec;
+            }
+            ++found;
+        }
+    }
+    *count = found;
+    return 0;
+}

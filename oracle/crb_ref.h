@@ -89,6 +89,29 @@ void crb_ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_
 double crb_ref_expneg(double x);            /* exp(-x) for x in [0, 745] */
 int crb_ref_poisson(const float *in, long long n, unsigned long long seed, float *out);
 
+/* ---- SOURCES work function (the paper's example of a work function whose
+ * actors return structures instead of subimages: stellar photometry, Section 7) --
+ * A pixel p = (y, x) is a source when its value v exceeds `threshold` and, over
+ * every other pixel q of the frame with |y'-y| <= r and |x'-x| <= r, either
+ * in[q] < v, or in[q] == v and q comes after p in raster order (so a plateau of
+ * equal values yields its first pixel).  The record holds the peak and aperture
+ * sums over the in-frame pixels of the (2a+1)^2 box around p, in binary64,
+ * accumulated row by row (dy = -a..a, then dx = -a..a):
+ *   flux = sum (in[q] - sky),  sy = sum dy * (in[q] - sky),  sx = sum dx * (in[q] - sky),
+ *   npix = number of in-frame aperture pixels.
+ * Records come out in raster order of their peaks; at most `capacity` are written
+ * and *count receives the total.  r in [1, 8], a in [0, 8], threshold and sky finite.
+ * The dependency radius of this work function is max(r, a). */
+typedef struct {
+    int32_t y, x;
+    float peak;
+    int32_t npix;
+    double flux, sy, sx;
+} crb_ref_source;
+
+int crb_ref_sources(const float *in, int H, int W, float threshold, float sky, int r, int a,
+                    crb_ref_source *out, long long capacity, long long *count);
+
 #ifdef __cplusplus
 }
 #endif

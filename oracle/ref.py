@@ -73,8 +73,11 @@ def lib():
         L.crb_ref_expneg.argtypes = [ctypes.c_double]
         L.crb_ref_expneg.restype = ctypes.c_double
         L.crb_ref_poisson.argtypes = [dp, ctypes.c_longlong, ctypes.c_ulonglong, dp]
+        L.crb_ref_sources.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_int, ctypes.c_int, dp,
+                                      ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)]
         for f in (L.crb_ref_median_filter, L.crb_ref_lplus, L.crb_ref_iterate,
-                  L.crb_ref_lacosmic, L.crb_ref_poisson):
+                  L.crb_ref_lacosmic, L.crb_ref_poisson, L.crb_ref_sources):
             f.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -180,3 +183,29 @@ def poisson(means: np.ndarray, seed: int) -> np.ndarray:
     if rc:
         raise ValueError("crb_ref_poisson failed")
     return out
+
+
+# One record of the SOURCES work function (crb_ref_source, 40 bytes).
+SOURCE_DTYPE = np.dtype([("y", np.int32), ("x", np.int32), ("peak", np.float32),
+                         ("npix", np.int32), ("flux", np.float64), ("sy", np.float64),
+                         ("sx", np.float64)])
+
+
+def sources(img: np.ndarray, threshold: float, sky: float = 0.0, r: int = 2,
+            a: int = 2) -> np.ndarray:
+    """The SOURCES work function on a whole frame: a structured array (SOURCE_DTYPE)
+    of the local peaks above threshold, in raster order, with their aperture sums."""
+    img = np.ascontiguousarray(img, dtype=np.float32)
+    H, W = img.shape
+    L = lib()
+    cnt = ctypes.c_longlong(0)
+    rc = L.crb_ref_sources(_ptr(img), H, W, float(threshold), float(sky), int(r), int(a),
+                           None, 0, ctypes.byref(cnt))
+    if rc:
+        raise ValueError(f"crb_ref_sources failed ({rc})")
+    out = np.zeros(max(cnt.value, 1), SOURCE_DTYPE)
+    rc = L.crb_ref_sources(_ptr(img), H, W, float(threshold), float(sky), int(r), int(a),
+                           _ptr(out), out.size, ctypes.byref(cnt))
+    if rc:
+        raise ValueError(f"crb_ref_sources failed ({rc})")
+    return out[:cnt.value].copy()

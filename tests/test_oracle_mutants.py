@@ -11,6 +11,7 @@ import pytest
 
 from oracle import ref
 import tests.test_oracle_pins as P
+import tests.test_oracle_sources as SRCP
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle",
                    "crb_ref.c")
@@ -59,6 +60,15 @@ MUTANTS = [
     ("even median upper", "return 0.5 * (v[n / 2 - 1] + v[n / 2]);", "return v[n / 2];"),
     ("median filter radius", "int k = 2 * r + 1;", "int k = 2 * r + 1; r = r > 1 ? r - 1 : r;"),
     ("early stop test", "if (early_stop && nk == 0)", "if (early_stop && nk <= 1)"),
+    ("sources tie order", "return yq > y || (yq == y && xq > x);",
+     "return yq < y || (yq == y && xq < x);"),
+    ("sources ties always yield", "if (vq == v)\n        return yq > y", "if (vq == v)\n        return 1 || yq > y"),
+    ("sources non-strict threshold", "if (!(v > threshold))", "if (!(v >= threshold))"),
+    ("sources window short", "for (int yq = y - r; yq <= y + r && peak; ++yq)",
+     "for (int yq = y - r + 1; yq <= y + r && peak; ++yq)"),
+    ("sources sky kept", "- (double)sky;", "- 0.0 * (double)sky;"),
+    ("sources moment sign", "rec.sy = rec.sy + (double)dy * d;", "rec.sy = rec.sy - (double)dy * d;"),
+    ("sources aperture half", "for (int dx = -a; dx <= a; ++dx) {", "for (int dx = 0; dx <= a; ++dx) {"),
     ("edge wrap instead of clamp", "static int clampi(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }",
      "static int clampi(int i, int n) { return ((i % n) + n) % n; }"),
 ]
@@ -84,6 +94,13 @@ def pin_battery():
     P.test_iteration_matches_scipy_composition()
     P.test_early_stop_neutral_and_invariants()
     P.test_sky_argument_enters_noise_only()
+    for args in [(6, 7, 2, 2), (1, 9, 2, 3)]:
+        SRCP.test_constant_frame_has_one_source_at_origin(*args)
+    for args in [(2, 1, 2), (4, 3, 3)]:
+        SRCP.test_brute_force_with_ties(*args)
+    SRCP.test_symmetric_star()
+    SRCP.test_separation_rule(2)
+    SRCP.test_threshold_is_strict_and_plateau_first_pixel()
 
 
 @pytest.fixture(scope="module")
