@@ -141,9 +141,11 @@ crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
  * in one batched pass; only the interiors are written to out_clean / out_mask.
  * With border >= 8 * niter the result equals crb_lacosmic's (an iteration's
  * dependency radius is 8 pixels); smaller borders show the subimage edge effects
- * the paper's 6-pixel border trades against overlap.  Synchronous on the calling
- * thread's stream; allocates temporary device memory for the subimages.
- *   ny, nx >= 1 with ny <= H and nx <= W; border >= 0; other arguments as crb_lacosmic.
+ * the paper's 6-pixel border trades against overlap.  border = -1 takes the declared
+ * radius of the cleaning pass, 8 * niter (crb_work_radius of CRB_WORK_LACOSMIC).
+ * Synchronous on the calling thread's stream; allocates temporary device memory for
+ * the subimages.
+ *   ny, nx >= 1 with ny <= H and nx <= W; border >= -1; other arguments as crb_lacosmic.
  */
 crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int32_t W, float gain,
                                     float readnoise, float sky, float sigclip, float sigfrac,
@@ -151,21 +153,79 @@ crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int32_t W, floa
                                     int32_t border, float *out_clean, uint8_t *out_mask);
 
 /*
- * The paper's framework probes (Section 6.3.2 POISSON, Section 6.3.3 WAITER): work
- * functions of uniform per-pixel cost and no border, run by a persistent farm of
- * `workers` workgroups that take bands of `band_rows` rows from an atomic ticket, as
- * CRBLASTER's actors take subimages; timing the farm against `workers` gives the
- * framework's efficiency independent of L.A.Cosmic.
- *   CRB_WORK_POISSON: out = a Poisson deviate with mean in (Knuth's multiplication
- *     method; mean clamped to [0, 500], non-finite -> 0; uniforms from Philox4x32-10
- *     keyed by `seed`, counter = (pixel index, draw / 4); e^-mean by range reduction
- *     and a degree-13 polynomial), bit-identical to the oracle's crb_ref_poisson;
- *   CRB_WORK_WAITER: waits in[i] microseconds per pixel (clamped to [0, 1e6]), out = in.
- * Device pointers, H*W FP32 each; workers >= 1, band_rows >= 1.  Asynchronous on
- * the calling thread's stream (uses 4 bytes of that stream's workspace).
+ * The tile farm (the paper's computational framework, Sections 6.3 and 7).  A work
+ * function declares its dependency radius; the farm cuts the frame into tile_h x
+ * tile_w rectangles, stages each with an apron of that radius when the function
+ * reads neighbours (positions outside the frame are never read as pixels), and hands
+ * the rectangles to `workers` persistent workgroups through an atomic ticket, as
+ * CRBLASTER's director hands subimages to free actors.  Work functions:
+ *   CRB_WORK_LACOSMIC (radius query only): the cleaning pass; radius 8 * niter, the
+ *     border independent subimages need to reproduce a whole-frame run (one iteration
+ *     reaches 8 pixels: 4 for the detection statistics, 1 for each of the two grows,
+ *     2 for the replacement window);
+ *   CRB_WORK_POISSON (Section 6.3.2), image output, radius 0: out = a Poisson deviate
+ *     with mean in (Knuth's multiplication method; mean clamped to [0, 500],
+ *     non-finite -> 0; uniforms from Philox4x32-10 keyed by `seed`, counter = (pixel
+ *     index, draw / 4); e^-mean by range reduction and a degree-13 polynomial),
+ *     bit-identical to the oracle's crb_ref_poisson;
+ *   CRB_WORK_WAITER (Section 6.3.3), image output, radius 0: waits in[i]
+ *     microseconds per pixel (clamped to [0, 1e6]), out = in;
+ *   CRB_WORK_SOURCES (Section 7: actors returning structures, e.g. stellar
+ *     photometry), list output, radius max(peak_radius, aperture_radius): a pixel p
+ *     of value v is a source when v > threshold and every other in-frame pixel q
+ *     within Chebyshev distance peak_radius has in[q] < v, or in[q] == v and q later
+ *     in raster order.  Its crb_source record holds p, v and binary64 sums over the
+ *     in-frame pixels q of the (2a+1)^2 box around p (a = aperture_radius), taken row
+ *     by row: flux = sum(in[q] - sky), sy = sum(dy * (in[q] - sky)),
+ *     sx = sum(dx * (in[q] - sky)), npix = their count.  Pixel values must be finite.
  */
+#define CRB_WORK_LACOSMIC 0
 #define CRB_WORK_POISSON 1
 #define CRB_WORK_WAITER 2
+#define CRB_WORK_SOURCES 3
+
+typedef struct {
+    int32_t kind;              /* CRB_WORK_*                                        */
+    int32_t niter;             /* LACOSMIC: iterations (radius query only), >= 0     */
+    uint64_t seed;             /* POISSON: generator key                            */
+    float threshold;           /* SOURCES: peak threshold, finite                   */
+    float sky;                 /* SOURCES: level subtracted in the sums, finite     */
+    int32_t peak_radius;       /* SOURCES: r in [1, 8]                              */
+    int32_t aperture_radius;   /* SOURCES: a in [0, 8]                              */
+} crb_work;                    /* 32 bytes */
+
+typedef struct {
+    int32_t y, x;              /* peak position                                     */
+    float peak;                /* in[y, x]                                          */
+    int32_t npix;              /* in-frame aperture pixels                          */
+    double flux, sy, sx;       /* aperture sums (see CRB_WORK_SOURCES)              */
+} crb_source;                  /* 40 bytes */
+
+/* Declared dependency radius of the work function described by w, or -1 (with
+ * crb_last_error set) if w is null or its parameters are invalid. */
+int32_t crb_work_radius(const crb_work *w);
+
+/*
+ * Run a farm work function (POISSON, WAITER or SOURCES) over the H x W FP32 device
+ * frame `in`.  workers in [1, 2^20]; tile_h, tile_w >= 1, and for SOURCES the staged
+ * tile (tile_h + 2R) x (tile_w + 2R) x 4 bytes must fit in 64 KiB (R the radius).
+ *   Image kinds: out_image (device, H x W FP32; may equal in, must not partially
+ *     overlap it); out_list and out_count must be null.
+ *   SOURCES: out_count (device int64, 8-byte aligned) receives the number of sources;
+ *     the first min(count, list_capacity) of them are written to out_list (device,
+ *     8-byte aligned; null only when list_capacity is 0) in no particular order --
+ *     sort by (y, x) for raster order; a count above list_capacity means the list
+ *     was truncated and a rerun with a larger list returns all.  out_image must be null.
+ * Asynchronous on the calling thread's stream; uses 4 bytes of that stream's
+ * workspace, so calls on one stream are ordered and calls on different streams are
+ * independent.
+ */
+crb_status crb_farm_run(const crb_work *w, const float *in, int32_t H, int32_t W,
+                        int32_t workers, int32_t tile_h, int32_t tile_w, float *out_image,
+                        crb_source *out_list, int64_t list_capacity, int64_t *out_count);
+
+/* POISSON or WAITER on bands of band_rows full rows: crb_farm_run with tile_h =
+ * band_rows and tile_w = W. */
 crb_status crb_work_run(int32_t kind, const float *in, int32_t H, int32_t W, uint64_t seed,
                         int32_t workers, int32_t band_rows, float *out);
 

@@ -9,6 +9,7 @@ import ctypes
 import os
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,15 +25,29 @@ EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned", "
            "crb_last_error", "crb_workspace_bytes", "crb_release_workspace",
            "crb_server_create", "crb_server_submit", "crb_server_poll", "crb_server_pending",
            "crb_server_destroy", "crb_debug_iterate", "crb_debug_detect", "crb_debug_median",
-           "crb_debug_fp64", "crb_work_run"]
+           "crb_debug_fp64", "crb_work_run", "crb_work_radius", "crb_farm_run"]
+CRB_WORK_LACOSMIC = 0
 CRB_WORK_POISSON = 1
 CRB_WORK_WAITER = 2
+CRB_WORK_SOURCES = 3
+
+# One record of the SOURCES work function (crb_source, 40 bytes).
+SOURCE_DTYPE = np.dtype([("y", np.int32), ("x", np.int32), ("peak", np.float32),
+                         ("npix", np.int32), ("flux", np.float64), ("sy", np.float64),
+                         ("sx", np.float64)])
 
 
 class CrbError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn}: {STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class Work(ctypes.Structure):
+    """Mirror of ``crb_work``."""
+    _fields_ = [("kind", ctypes.c_int32), ("niter", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("threshold", ctypes.c_float), ("sky", ctypes.c_float),
+                ("peak_radius", ctypes.c_int32), ("aperture_radius", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -91,12 +106,15 @@ def lib():
     L.crb_debug_median.argtypes = [vp, i32, i32, i32, vp]
     L.crb_debug_fp64.argtypes = [vp, vp, i32, vp, vp]
     L.crb_work_run.argtypes = [i32, vp, i32, i32, ctypes.c_uint64, i32, i32, vp]
+    L.crb_work_radius.argtypes = [ctypes.POINTER(Work)]
+    L.crb_work_radius.restype = i32
+    L.crb_farm_run.argtypes = [ctypes.POINTER(Work), vp, i32, i32, i32, i32, i32, vp, vp, i64, vp]
     for name in ("crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned",
                  "crb_plan_create", "crb_plan_run",
                  "crb_plan_stats", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option", "crb_release_workspace",
                  "crb_server_create", "crb_server_submit", "crb_server_poll",
                  "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64",
-                 "crb_work_run"):
+                 "crb_work_run", "crb_farm_run"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -311,4 +329,73 @@ def work_run(kind: int, x: torch.Tensor, seed: int = 0, workers: int = 1024,
     check("crb_work_run", lib().crb_work_run(kind, x.data_ptr(), x.shape[0], x.shape[1],
                                              int(seed) & (2 ** 64 - 1), workers, band_rows,
                                              out.data_ptr()))
+    return out
+
+
+def make_work(kind: int, seed: int = 0, threshold: float = 0.0, sky: float = 0.0, r: int = 1,
+              a: int = 0, niter: int = 0) -> Work:
+    return Work(int(kind), int(niter), int(seed) & (2 ** 64 - 1), float(threshold), float(sky),
+                int(r), int(a))
+
+
+def work_radius(kind: int, **kw) -> int:
+    """crb_work_radius: the dependency radius a work function declares."""
+    w = make_work(kind, **kw)
+    rad = lib().crb_work_radius(ctypes.byref(w))
+    if rad < 0:
+        check("crb_work_radius", -1)
+    return int(rad)
+
+
+def farm_image(kind: int, x: torch.Tensor, seed: int = 0, workers: int = 1024, tile_h: int = 1,
+               tile_w: Optional[int] = None, out: Optional[torch.Tensor] = None,
+               stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """crb_farm_run for an image work function (POISSON, WAITER) on tile_h x tile_w
+    rectangles (tile_w defaults to the full width)."""
+    _dev2d(x, torch.float32, "x")
+    H, W = x.shape
+    if out is None:
+        out = torch.empty_like(x)
+    w = make_work(kind, seed=seed)
+    set_stream(stream)
+    check("crb_farm_run", lib().crb_farm_run(ctypes.byref(w), x.data_ptr(), H, W, workers,
+                                             tile_h, W if tile_w is None else tile_w,
+                                             out.data_ptr(), None, 0, None))
+    return out
+
+
+class SourceList:
+    """Device-side result of the SOURCES work function: `records` (uint8 tensor of
+    capacity x 40 bytes) and `count` (int64 tensor of one element)."""
+
+    def __init__(self, records: torch.Tensor, count: torch.Tensor, capacity: int):
+        self.records, self.count, self.capacity = records, count, capacity
+
+    def numpy(self) -> np.ndarray:
+        """The records as a structured array (SOURCE_DTYPE) sorted by (y, x); raises
+        if the list was truncated."""
+        n = int(self.count.item())
+        if n > self.capacity:
+            raise OverflowError(f"{n} sources found, capacity {self.capacity}")
+        rec = self.records[: n * SOURCE_DTYPE.itemsize].cpu().numpy().view(SOURCE_DTYPE)
+        return rec[np.lexsort((rec["x"], rec["y"]))]
+
+
+def farm_sources(x: torch.Tensor, threshold: float, sky: float = 0.0, r: int = 2, a: int = 2,
+                 workers: int = 2048, tile_h: int = 32, tile_w: int = 64,
+                 capacity: int = 1 << 20, out: Optional[SourceList] = None,
+                 stream: Optional[torch.cuda.Stream] = None) -> SourceList:
+    """crb_farm_run with the SOURCES work function: peaks above threshold with their
+    aperture sums; asynchronous (read the result with .numpy())."""
+    _dev2d(x, torch.float32, "x")
+    H, W = x.shape
+    if out is None:
+        out = SourceList(torch.empty(max(capacity, 1) * SOURCE_DTYPE.itemsize, dtype=torch.uint8,
+                                     device=x.device),
+                         torch.empty(1, dtype=torch.int64, device=x.device), capacity)
+    w = make_work(CRB_WORK_SOURCES, threshold=threshold, sky=sky, r=r, a=a)
+    set_stream(stream)
+    check("crb_farm_run", lib().crb_farm_run(ctypes.byref(w), x.data_ptr(), H, W, workers,
+                                             tile_h, tile_w, None, out.records.data_ptr(),
+                                             out.capacity, out.count.data_ptr()))
     return out

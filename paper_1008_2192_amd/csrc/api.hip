@@ -289,42 +289,128 @@ crb_status crb_lacosmic(const float *img, int32_t H, int32_t W, float gain, floa
     return ok();
 }
 
-crb_status crb_work_run(int32_t kind, const float *in, int32_t H, int32_t W, uint64_t seed,
-                        int32_t workers, int32_t band_rows, float *out) {
-    if (kind != CRB_WORK_POISSON && kind != CRB_WORK_WAITER)
-        return fail(CRB_EINVAL, "unknown work function %d", kind);
-    if (!in || !out)
+static crb_status check_work(const crb_work *w, WorkArgs *args) {
+    if (!w)
+        return fail(CRB_EINVAL, "null work description");
+    memset(args, 0, sizeof(*args));
+    switch (w->kind) {
+    case CRB_WORK_LACOSMIC:
+        if (w->niter < 0 || w->niter > kMaxIter)
+            return fail(CRB_EINVAL, "niter %d outside [0, %d]", w->niter, kMaxIter);
+        return CRB_OK;
+    case CRB_WORK_POISSON:
+        args->seed = (unsigned long long)w->seed;
+        return CRB_OK;
+    case CRB_WORK_WAITER:
+        return CRB_OK;
+    case CRB_WORK_SOURCES:
+        if (w->peak_radius < 1 || w->peak_radius > kMaxWorkRadius || w->aperture_radius < 0 ||
+            w->aperture_radius > kMaxWorkRadius)
+            return fail(CRB_EINVAL, "SOURCES radii r = %d, a = %d: need 1 <= r <= %d, 0 <= a <= %d",
+                        w->peak_radius, w->aperture_radius, kMaxWorkRadius, kMaxWorkRadius);
+        if (!finite32(w->threshold) || !finite32(w->sky))
+            return fail(CRB_EINVAL, "SOURCES threshold and sky must be finite");
+        args->threshold = w->threshold;
+        args->sky = w->sky;
+        args->r = w->peak_radius;
+        args->a = w->aperture_radius;
+        return CRB_OK;
+    default:
+        return fail(CRB_EINVAL, "unknown work function %d", w->kind);
+    }
+}
+
+int32_t crb_work_radius(const crb_work *w) {
+    WorkArgs args;
+    if (check_work(w, &args) != CRB_OK)
+        return -1;
+    ok();
+    return work_radius(w->kind, args, w->niter);
+}
+
+crb_status crb_farm_run(const crb_work *w, const float *in, int32_t H, int32_t W,
+                        int32_t workers, int32_t tile_h, int32_t tile_w, float *out_image,
+                        crb_source *out_list, int64_t list_capacity, int64_t *out_count) {
+    WorkArgs args;
+    crb_status st = check_work(w, &args);
+    if (st != CRB_OK)
+        return st;
+    if (w->kind == CRB_WORK_LACOSMIC)
+        return fail(CRB_EINVAL, "the cleaning pass runs through crb_lacosmic*, not the farm");
+    if (!in)
         return fail(CRB_EINVAL, "null pointer");
     if (H < 1 || W < 1)
         return fail(CRB_EINVAL, "image size %d x %d: both must be >= 1", H, W);
     if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX)
         return fail(CRB_ETOOBIG, "image exceeds 2^31-1 pixels");
-    if (workers < 1 || workers > (1 << 20) || band_rows < 1)
-        return fail(CRB_EINVAL, "workers must lie in [1, 2^20] and band_rows >= 1");
-    if (in != out && ranges_overlap(in, (size_t)H * W * 4, out, (size_t)H * W * 4))
-        return fail(CRB_EINVAL, "out partially overlaps in");
-    int dev = 0, khz = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
-    if (e != hipSuccess)
-        return hip_status(e, "device query");
+    if (workers < 1 || workers > (1 << 20) || tile_h < 1 || tile_w < 1)
+        return fail(CRB_EINVAL, "workers must lie in [1, 2^20] and tiles be at least 1 x 1");
+    const size_t nbytes = (size_t)H * (size_t)W * 4;
+    const bool list = w->kind == CRB_WORK_SOURCES;
+    if (list) {
+        if (out_image)
+            return fail(CRB_EINVAL, "SOURCES writes a list: out_image must be null");
+        if (!out_count || ((uintptr_t)out_count & 7))
+            return fail(CRB_EINVAL, "out_count must be an 8-byte aligned device pointer");
+        if (list_capacity < 0 || (list_capacity > 0 && (!out_list || ((uintptr_t)out_list & 7))))
+            return fail(CRB_EINVAL, "out_list must be 8-byte aligned and hold list_capacity >= 0 "
+                                    "records");
+        const size_t lbytes = (size_t)list_capacity * sizeof(crb_source);
+        if (list_capacity > 0 && (ranges_overlap(out_list, lbytes, in, nbytes) ||
+                                  ranges_overlap(out_list, lbytes, out_count, 8)))
+            return fail(CRB_EINVAL, "out_list overlaps the frame or the count");
+        if (ranges_overlap(out_count, 8, in, nbytes))
+            return fail(CRB_EINVAL, "out_count overlaps the frame");
+        if ((size_t)tile_h + 2 * kMaxWorkRadius > (1u << 20) ||
+            (size_t)tile_w + 2 * kMaxWorkRadius > (1u << 20) ||
+            farm_lds_bytes(w->kind, args, tile_h, tile_w) > kMaxFarmLds)
+            return fail(CRB_EINVAL, "staged tile %d x %d with radius %d exceeds %zu bytes of LDS",
+                        tile_h, tile_w, work_radius(w->kind, args, 0), kMaxFarmLds);
+    } else {
+        if (!out_image)
+            return fail(CRB_EINVAL, "null out_image");
+        if (out_list || out_count)
+            return fail(CRB_EINVAL, "image work functions take no out_list / out_count");
+        if (in != out_image && ranges_overlap(in, nbytes, out_image, nbytes))
+            return fail(CRB_EINVAL, "out_image partially overlaps in");
+    }
+    WorkArgs a2 = args;
+    if (w->kind == CRB_WORK_WAITER) {
+        int dev = 0, khz = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess)
+            e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+        if (e != hipSuccess)
+            return hip_status(e, "device query");
+        a2.wall_khz = khz;
+    }
     hipStream_t s = t_stream;
     Workspace *ws = nullptr;
-    crb_status st = ws_get(s, &ws);
-    if (st != CRB_OK)
+    if ((st = ws_get(s, &ws)) != CRB_OK)
         return st;
     std::lock_guard<std::mutex> g(ws->mu);
     if ((st = ws_reserve(ws, 256)) != CRB_OK)
         return st;
     unsigned int *ticket = reinterpret_cast<unsigned int *>(ws->buf);
-    e = launch_farm_reset(ticket, s);
+    unsigned long long *count = reinterpret_cast<unsigned long long *>(out_count);
+    hipError_t e = launch_farm_reset(ticket, count, s);
     if (e == hipSuccess)
-        e = launch_farm(kind == CRB_WORK_POISSON ? kWorkPoisson : kWorkWaiter, in, H, W,
-                        (unsigned long long)seed, workers, band_rows, out, ticket,
-                        (long long)khz, s);
+        e = launch_farm(w->kind, a2, in, H, W, workers, tile_h, tile_w, out_image,
+                        reinterpret_cast<SourceRec *>(out_list), (long long)list_capacity, count,
+                        ticket, s);
     st = hip_status(e, "kernel launch");
     return st == CRB_OK ? ok() : st;
+}
+
+crb_status crb_work_run(int32_t kind, const float *in, int32_t H, int32_t W, uint64_t seed,
+                        int32_t workers, int32_t band_rows, float *out) {
+    if (kind != CRB_WORK_POISSON && kind != CRB_WORK_WAITER)
+        return fail(CRB_EINVAL, "crb_work_run takes POISSON or WAITER, not %d", kind);
+    crb_work w;
+    memset(&w, 0, sizeof(w));
+    w.kind = kind;
+    w.seed = seed;
+    return crb_farm_run(&w, in, H, W, workers, band_rows, W, out, nullptr, 0, nullptr);
 }
 
 crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_frame *p,
@@ -753,6 +839,11 @@ extern "C" crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int3
     const size_t npix = (size_t)H * (size_t)W;
     if ((st = check_buffers(img, out_clean, out_mask, npix)) != CRB_OK)
         return st;
+    if (border == -1) {
+        WorkArgs none;
+        memset(&none, 0, sizeof(none));
+        border = work_radius(kWorkLacosmic, none, niter);
+    }
     if (ny < 1 || nx < 1 || ny > H || nx > W || border < 0)
         return fail(CRB_EINVAL, "partition %d x %d with border %d does not fit %d x %d", ny, nx,
                     border, H, W);
@@ -833,3 +924,10 @@ extern "C" crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int3
     (void)hipFree(tmp);
     return st == CRB_OK ? ok() : st;
 }
+
+static_assert(sizeof(crb_work) == 32, "crb_work layout");
+static_assert(sizeof(crb_source) == 40 && sizeof(crb_source) == sizeof(crb::SourceRec),
+              "crb_source layout");
+static_assert(offsetof(crb_source, flux) == offsetof(crb::SourceRec, flux) &&
+              offsetof(crb_source, sx) == offsetof(crb::SourceRec, sx),
+              "crb_source layout");

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "../../include/crb.h"
+#include "farm.h"
 #include "kernels.h"
 
 namespace crb {

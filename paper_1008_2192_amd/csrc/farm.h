@@ -1,0 +1,58 @@
+// The tile farm and its work functions (the paper's framework, Sections 6.3 and 7).
+//
+// A work function is a struct that declares what the farm needs to know about it:
+//   kList        false: one FP32 output per pixel (an image, like a cleaned subimage);
+//                true : a variable number of SourceRec records (the paper's example of
+//                actors returning structures instead of subimages);
+//   kStaged      true : the function reads neighbours, so the farm stages each tile
+//                with an apron of radius() pixels in LDS (out-of-frame positions hold
+//                kOutside); false: it reads its own pixel from global memory only;
+//   radius(args) the dependency radius: the farm's apron, and the border a partition
+//                into independent subimages needs for an exact result.
+// The farm cuts the frame into tile_h x tile_w rectangles and hands them to a
+// persistent grid of workgroups through an atomic ticket, as CRBLASTER's director
+// hands subimages to free actors; adding a work function means adding one struct and
+// one dispatch line, nothing else in the farm changes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace crb {
+
+constexpr int kWorkLacosmic = 0, kWorkPoisson = 1, kWorkWaiter = 2, kWorkSources = 3;
+constexpr int kMaxWorkRadius = 8;        // largest apron a staged work function may declare
+constexpr size_t kMaxFarmLds = 64 * 1024;
+
+struct WorkArgs {
+    unsigned long long seed;   // POISSON: generator key
+    long long wall_khz;        // WAITER: rate of the wall-clock counter
+    float threshold, sky;      // SOURCES: peak threshold, level subtracted in the sums
+    int r, a;                  // SOURCES: peak window radius, aperture radius
+};
+
+// One SOURCES record; the layout of crb_source (40 bytes).
+struct SourceRec {
+    int y, x;
+    float peak;
+    int npix;
+    double flux, sy, sx;
+};
+
+// Declared dependency radius of a work function (host side); -1 for an unknown kind.
+int work_radius(int kind, const WorkArgs &a, int niter);
+// LDS bytes one workgroup needs for a tile (0 for unstaged kinds).
+size_t farm_lds_bytes(int kind, const WorkArgs &a, int tile_h, int tile_w);
+
+// Clears the ticket and, if count is not null, the record counter.
+hipError_t launch_farm_reset(unsigned int *ticket, unsigned long long *count, hipStream_t s);
+// Runs work function `kind` over the frame with `workers` persistent workgroups.
+// Image kinds write out_img (H x W); list kinds append to out_list (at most capacity
+// records are stored, *count receives the total).  *ticket (and *count) must be zero.
+hipError_t launch_farm(int kind, const WorkArgs &args, const float *in, int H, int W,
+                       int workers, int tile_h, int tile_w, float *out_img,
+                       SourceRec *out_list, long long capacity, unsigned long long *count,
+                       unsigned int *ticket, hipStream_t s);
+
+}  // namespace crb

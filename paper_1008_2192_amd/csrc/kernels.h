@@ -92,15 +92,6 @@ hipError_t launch_extract(const float *img, int W, const SubRect *d_subs, int ns
 hipError_t launch_stitch(float *out_clean, uint8_t *out_mask, int W, const SubRect *d_subs,
                          int nsub, size_t max_pixels, hipStream_t s);
 
-// Work functions for the tile farm (the paper's framework probes, Section 6.3).
-constexpr int kWorkPoisson = 1, kWorkWaiter = 2;
-// Persistent farm: `workers` blocks pull bands of `band_rows` rows from an atomic
-// ticket (*ticket must be 0 at launch; launch_farm_reset clears it on the stream).
-hipError_t launch_farm_reset(unsigned int *ticket, hipStream_t s);
-hipError_t launch_farm(int kind, const float *in, int H, int W, unsigned long long seed,
-                       int workers, int band_rows, float *out, unsigned int *ticket,
-                       long long wall_khz, hipStream_t s);
-
 hipError_t launch_debug_median(const float *in, int H, int W, int r, float *out, hipStream_t s);
 hipError_t launch_debug_fp64(const double *x, const double *y, int n, double *out_sqrt,
                              double *out_div, hipStream_t s);

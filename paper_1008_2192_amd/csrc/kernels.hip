@@ -716,117 +716,6 @@ __global__ __launch_bounds__(kThreads) void k_stitch(float *__restrict__ out_cle
 }
 
 // ---------------------------------------------------------------------------
-// tile farm with the POISSON and WAITER work functions (Section 6.3)
-// ---------------------------------------------------------------------------
-
-// Philox4x32-10 counter-based generator (Salmon et al., SC 2011): ten rounds of
-// two 32x32->64-bit products with the multipliers 0xD2511F53 and 0xCD9E8D57; the
-// key advances by 0x9E3779B9 and 0xBB67AE85 after each round.
-__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int i = 0; i < 10; ++i) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
-// e^-x for 0 <= x <= 500: split x by ln 2 (Cody-Waite: a short high part of ln 2
-// makes k * ln2_hi exact), degree-13 Taylor series of e^r by Horner's rule, then an
-// exact power-of-two scale.  Only correctly rounded operations in a fixed order.
-__device__ __forceinline__ double exp_neg(double x) {
-    const double ln2_hi = 6.93147180369123816490e-01;
-    const double ln2_lo = 1.90821492927058770002e-10;
-    const double inv_ln2 = 1.44269504088896338700e+00;
-    const double y = -x;
-    const double kf = floor(y * inv_ln2 + 0.5);
-    const double r = (y - kf * ln2_hi) - kf * ln2_lo;
-    const double inv_fact[14] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0,
-                                 1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0, 1.0 / 362880.0,
-                                 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0,
-                                 1.0 / 6227020800.0};
-    double p = inv_fact[13];
-#pragma unroll
-    for (int n = 12; n >= 0; --n)
-        p = p * r + inv_fact[n];
-    return ldexp(p, (int)kf);
-}
-
-// Poisson deviate with mean `mean` by multiplying uniforms until the product drops
-// to e^-mean (Knuth's method); uniform j of pixel i comes from word j%4 of the
-// generator at counter (i_lo, i_hi, j/4, 0).
-__device__ __forceinline__ float poisson_deviate(float mean_f, size_t i, uint32_t k0,
-                                                 uint32_t k1) {
-    double mean = (double)mean_f;
-    if (!(mean > 0.0))
-        mean = 0.0;
-    if (mean > 500.0)
-        mean = 500.0;
-    const double limit = exp_neg(mean);
-    double prod = 1.0;
-    unsigned int k = 0;
-    for (uint32_t blk = 0;; ++blk) {
-        const uint4 w = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), blk, 0u), k0, k1);
-        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            prod = prod * (((double)words[q] + 0.5) * (1.0 / 4294967296.0));
-            if (!(prod > limit))
-                return (float)k;
-            ++k;
-        }
-    }
-}
-
-__global__ void k_farm_reset(unsigned int *ticket) { *ticket = 0u; }
-
-// Persistent farm: each block repeatedly takes the next band of rows from an atomic
-// ticket -- the analogue of the paper's director handing subimages to free actors.
-template <int KIND>
-__global__ __launch_bounds__(kThreads) void k_farm(const float *__restrict__ in, int H, int W,
-                                                   unsigned long long seed, int band_rows,
-                                                   float *__restrict__ out,
-                                                   unsigned int *__restrict__ ticket,
-                                                   long long wall_khz) {
-    __shared__ int sBand;
-    const int nbands = (H + band_rows - 1) / band_rows;
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    for (;;) {
-        if (threadIdx.x == 0)
-            sBand = (int)atomicAdd(ticket, 1u);
-        __syncthreads();
-        const int b = sBand;
-        __syncthreads();
-        if (b >= nbands)
-            return;
-        const int r0 = b * band_rows;
-        const int r1 = min(H, r0 + band_rows);
-        const size_t first = (size_t)r0 * W, n = (size_t)(r1 - r0) * W;
-        for (size_t j = threadIdx.x; j < n; j += kThreads) {
-            const size_t i = first + j;
-            if constexpr (KIND == kWorkPoisson) {
-                out[i] = poisson_deviate(in[i], i, k0, k1);
-            } else {
-                // WAITER: wait in[i] microseconds (clamped to [0, 1e6]), copy the pixel
-                float x = in[i];
-                if (!(x > 0.0f))
-                    x = 0.0f;
-                if (x > 1.0e6f)
-                    x = 1.0e6f;
-                const long long ticks = (long long)((double)x * (double)wall_khz / 1000.0);
-                const long long t0 = (long long)wall_clock64();
-                while ((long long)wall_clock64() - t0 < ticks)
-                    __builtin_amdgcn_s_sleep(1);
-                out[i] = in[i];
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
 // parity-test kernels: the median networks alone, binary64 sqrt and division
 // ---------------------------------------------------------------------------
 
@@ -966,23 +855,6 @@ hipError_t launch_stitch(float *out_clean, uint8_t *out_mask, int W, const SubRe
                          int nsub, size_t max_pixels, hipStream_t s) {
     dim3 grid(grid_for(max_pixels, 1024), nsub);
     k_stitch<<<grid, kThreads, 0, s>>>(out_clean, out_mask, W, d_subs);
-    return hipGetLastError();
-}
-
-hipError_t launch_farm_reset(unsigned int *ticket, hipStream_t s) {
-    k_farm_reset<<<1, 1, 0, s>>>(ticket);
-    return hipGetLastError();
-}
-
-hipError_t launch_farm(int kind, const float *in, int H, int W, unsigned long long seed,
-                       int workers, int band_rows, float *out, unsigned int *ticket,
-                       long long wall_khz, hipStream_t s) {
-    if (kind == kWorkPoisson)
-        k_farm<kWorkPoisson><<<workers, kThreads, 0, s>>>(in, H, W, seed, band_rows, out, ticket,
-                                                          wall_khz);
-    else
-        k_farm<kWorkWaiter><<<workers, kThreads, 0, s>>>(in, H, W, seed, band_rows, out, ticket,
-                                                         wall_khz);
     return hipGetLastError();
 }
 

@@ -94,3 +94,61 @@ def test_server_argument_validation(L):
     n = ctypes.c_int32()
     assert L.crb_server_poll(None, None, None, 0, ctypes.byref(n)) == -1
     assert L.crb_server_pending(None) == 0
+
+
+def test_work_struct_layouts():
+    from paper_1008_2192_amd import _lib
+    assert ctypes.sizeof(_lib.Work) == 32
+    assert _lib.Work.seed.offset == 8 and _lib.Work.aperture_radius.offset == 28
+    assert _lib.SOURCE_DTYPE.itemsize == 40 and _lib.SOURCE_DTYPE.fields["flux"][1] == 16
+
+
+def test_work_radius_declarations(L):
+    from paper_1008_2192_amd import _lib
+    assert _lib.work_radius(_lib.CRB_WORK_LACOSMIC, niter=4) == 32
+    assert _lib.work_radius(_lib.CRB_WORK_LACOSMIC, niter=1) == 8
+    assert _lib.work_radius(_lib.CRB_WORK_POISSON) == 0
+    assert _lib.work_radius(_lib.CRB_WORK_WAITER) == 0
+    assert _lib.work_radius(_lib.CRB_WORK_SOURCES, r=2, a=5) == 5
+    assert _lib.work_radius(_lib.CRB_WORK_SOURCES, r=3, a=0) == 3
+    for kw in [dict(kind=_lib.CRB_WORK_SOURCES, r=0), dict(kind=_lib.CRB_WORK_SOURCES, r=9),
+               dict(kind=_lib.CRB_WORK_SOURCES, r=2, a=-1),
+               dict(kind=_lib.CRB_WORK_SOURCES, r=2, threshold=float("inf")),
+               dict(kind=_lib.CRB_WORK_LACOSMIC, niter=-1), dict(kind=9)]:
+        w = _lib.make_work(**kw)
+        assert L.crb_work_radius(ctypes.byref(w)) == -1, kw
+        assert L.crb_last_error()
+    assert L.crb_work_radius(None) == -1
+
+
+def test_farm_argument_validation(L):
+    from paper_1008_2192_amd import _lib
+    src = _lib.make_work(_lib.CRB_WORK_SOURCES, threshold=1.0, r=2, a=2)
+    poi = _lib.make_work(_lib.CRB_WORK_POISSON, seed=1)
+    lac = _lib.make_work(_lib.CRB_WORK_LACOSMIC, niter=4)
+    x = ctypes.c_void_p(1 << 40)          # never dereferenced: validation fails first
+    img = ctypes.c_void_p(1 << 41)
+    lst = ctypes.c_void_p(1 << 42)
+    cnt = ctypes.c_void_p(1 << 43)
+    run = L.crb_farm_run
+    b = ctypes.byref
+    assert run(b(lac), x, 8, 8, 4, 8, 8, img, None, 0, None) == -1
+    assert run(None, x, 8, 8, 4, 8, 8, img, None, 0, None) == -1
+    assert run(b(poi), None, 8, 8, 4, 8, 8, img, None, 0, None) == -1
+    assert run(b(poi), x, 0, 8, 4, 8, 8, img, None, 0, None) == -1
+    assert run(b(poi), x, 65536, 65536, 4, 8, 8, img, None, 0, None) == -4
+    assert run(b(poi), x, 8, 8, 0, 8, 8, img, None, 0, None) == -1
+    assert run(b(poi), x, 8, 8, 4, 0, 8, img, None, 0, None) == -1
+    assert run(b(poi), x, 8, 8, 4, 8, 8, None, None, 0, None) == -1
+    assert run(b(poi), x, 8, 8, 4, 8, 8, img, lst, 4, cnt) == -1
+    assert run(b(poi), x, 8, 8, 4, 8, 8, ctypes.c_void_p((1 << 40) + 4), None, 0, None) == -1
+    assert run(b(src), x, 8, 8, 4, 8, 8, img, lst, 4, cnt) == -1       # list kind, image out
+    assert run(b(src), x, 8, 8, 4, 8, 8, None, lst, 4, None) == -1     # no count
+    assert run(b(src), x, 8, 8, 4, 8, 8, None, lst, 4, ctypes.c_void_p((1 << 43) + 4)) == -1
+    assert run(b(src), x, 8, 8, 4, 8, 8, None, None, 4, cnt) == -1     # capacity, no list
+    assert run(b(src), x, 8, 8, 4, 8, 8, None, lst, -1, cnt) == -1
+    assert run(b(src), x, 8, 8, 4, 200, 200, None, lst, 4, cnt) == -1  # staged tile > 64 KiB
+    assert run(b(src), x, 8, 8, 4, 8, 8, None, x, 4, cnt) == -1        # list overlaps frame
+    assert L.crb_work_run(_lib.CRB_WORK_SOURCES, x, 8, 8, 0, 4, 1, img) == -1
+    assert L.crb_lacosmic_partitioned(x, 64, 64, 1.0, 5.0, 0.0, 4.5, 0.3, 4.0, 4, 2, 2, -2,
+                                      img, lst) == -1
