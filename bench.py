@@ -228,6 +228,11 @@ def main():
     ktimes = plan.kernel_times()
     stats = plan.stats()
     plan.set_timing(False)
+    # detection work counters, from one more (untimed) step
+    plan.set_counting(True)
+    plan.run()
+    work = plan.work_counts()
+    plan.set_counting(False)
     plan.close()
     ms_per_step = dt / args.steps * 1e3
     value = px_iter / (dt / args.steps) / 1e6
@@ -237,14 +242,24 @@ def main():
 
     det_ms, det_n = ktimes["detect"]
     det_avg_s = det_ms / det_n / 1e3
-    ops = roofline.detect_ops_per_pixel()
-    achieved = ops["total"] * total_px / det_avg_s        # lane-ops per second
-    roof = {"bound": "alu", "kernel": "k_detect (detection: med3/med5/med7 networks, L+, N, "
-                                      "S, S', F^, thresholds)",
+    # per launch: the step's 4 detection launches share the counted work equally on average
+    work_px = work["work_pixels"] / 4.0
+    contrast = work["contrast_tests"] / 4.0
+    ops_launch = roofline.detect_ops_per_launch(total_px, work_px, contrast)
+    achieved = ops_launch / det_avg_s                      # lane-ops per second
+    o = roofline.detect_ops()
+    roof = {"bound": "alu", "kernel": "k_detect (detection: med3 and med5 networks, L+, N, S "
+                                      "everywhere; med5(S), S' and the threshold bits on the "
+                                      "work set; med7 and F^ where S' > sigclip)",
             "achieved": round(achieved / 1e12, 3), "peak": round(roofline.ALU_PEAK / 1e12, 3),
             "unit": "Tlane-op/s", "frac": round(achieved / roofline.ALU_PEAK, 4),
             "traffic": profiled_traffic() if args.workload == "c4" else None,
-            "ops_per_pixel": round(ops["total"], 2),
+            "ops_per_launch": round(ops_launch),
+            "ops_per_pixel": round(ops_launch / total_px, 2),
+            "dense_ops_per_pixel": round(o["dense"]["total"], 2),
+            "ops_per_work_pixel": round(o["per_work_pixel"], 2),
+            "ops_per_contrast_test": round(o["per_contrast"], 2),
+            "work_pixels_per_launch": round(work_px), "contrast_tests_per_launch": round(contrast),
             "pixels_per_launch": total_px, "avg_launch_ms": round(det_avg_s * 1e3, 4),
             "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}}
 

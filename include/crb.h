@@ -131,6 +131,17 @@ void crb_plan_destroy(crb_plan *plan);
  * the number of launches since timing was enabled (ms[4], launches[4]). */
 crb_status crb_plan_set_timing(crb_plan *plan, int32_t enable);
 crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
+/* Work counters of the detection kernel (for roofline accounting).  The detection
+ * evaluates med5(S), S' and the threshold bits only on its work set, the pixels
+ * within 2 of a pixel with S > sigclip whose own S exceeds sigfrac * sigclip, and the
+ * fine-structure contrast (med7 of med3, F^, S'/F^) only where S' > sigclip.  With
+ * counting enabled every detection launch adds, per frame, the size of its work set
+ * and its number of contrast tests; crb_plan_set_counting (which waits for the
+ * plan's stream) clears the counters, crb_plan_work_counts waits for the stream and
+ * returns the totals over all frames since then: counts[0] work-set pixels,
+ * counts[1] contrast tests. */
+crb_status crb_plan_set_counting(crb_plan *plan, int32_t enable);
+crb_status crb_plan_work_counts(crb_plan *plan, int64_t *counts);
 
 /*
  * The paper's partitioned run (Section 6.2): the frame is split into ny x nx
@@ -208,7 +219,8 @@ int32_t crb_work_radius(const crb_work *w);
 /*
  * Run a farm work function (POISSON, WAITER or SOURCES) over the H x W FP32 device
  * frame `in`.  workers in [1, 2^20]; tile_h, tile_w >= 1, and for SOURCES the staged
- * tile (tile_h + 2R) x (tile_w + 2R) x 4 bytes must fit in 64 KiB (R the radius).
+ * tile (tile_h + 2R) x (tile_w + 2R) x 4 bytes (R the radius) and the workgroup's
+ * 20 KiB record buffer must fit in 64 KiB together.
  *   Image kinds: out_image (device, H x W FP32; may equal in, must not partially
  *     overlap it); out_list and out_count must be null.
  *   SOURCES: out_count (device int64, 8-byte aligned) receives the number of sources;
@@ -216,9 +228,11 @@ int32_t crb_work_radius(const crb_work *w);
  *     8-byte aligned; null only when list_capacity is 0) in no particular order --
  *     sort by (y, x) for raster order; a count above list_capacity means the list
  *     was truncated and a rerun with a larger list returns all.  out_image must be null.
- * Asynchronous on the calling thread's stream; uses 4 bytes of that stream's
- * workspace, so calls on one stream are ordered and calls on different streams are
- * independent.
+ * Tiles are handed out through 8 ticket counters, each over a contiguous range of
+ * tiles, in runs of several tiles; a workgroup drains its own range first and then
+ * helps with the others.  Asynchronous on the calling thread's stream; uses 32 bytes
+ * of that stream's workspace, so calls on one stream are ordered and calls on
+ * different streams are independent.
  */
 crb_status crb_farm_run(const crb_work *w, const float *in, int32_t H, int32_t W,
                         int32_t workers, int32_t tile_h, int32_t tile_w, float *out_image,
@@ -281,10 +295,18 @@ void crb_server_destroy(crb_server *srv);
 crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_frame *params,
                              uint8_t *out_G2, uint8_t *out_M, float *out_J_next,
                              int64_t *out_n_new);
-/* Detection stage only: code = A | [S' > sigclip] << 1 | [S' > sigfrac sigclip] << 2. */
+/* Detection stage only: code = A | [S' > sigclip] << 1 | [S' > sigfrac sigclip] << 2
+ * on the pixels within distance 2 (8-connected) of a pixel with S > sigclip, 0
+ * elsewhere.  The grow reads a code only through its two 3x3 dilations of A, and A
+ * lies inside {S' > sigclip}, which lies inside {S > sigclip}; so the codes equal the
+ * full definition wherever they can change G1 or G2. */
 crb_status crb_debug_detect(const float *J, const crb_frame *params, uint8_t *out_codes);
-/* Clamped (2r+1)^2 median filter, r in {1, 2, 3}, by the kernels' networks. */
+/* Clamped (2r+1)^2 median filter, r in {1, 2, 3}, by the kernels' networks (3x3 by
+ * sorted columns, 5x5 by the 2 x 5 output network, 7x7 by the single-output one). */
 crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out);
+/* Clamped 5x5 median filter of binary64 values by the single-output network the
+ * detection applies to S. */
+crb_status crb_debug_median5_f64(const double *in, int32_t H, int32_t W, double *out);
 /* Elementwise binary64 sqrt(x) and x / y on the device (rounding checks). */
 crb_status crb_debug_fp64(const double *x, const double *y, int32_t n, double *out_sqrt,
                           double *out_div);

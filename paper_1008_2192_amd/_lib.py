@@ -25,7 +25,8 @@ EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned", "
            "crb_last_error", "crb_workspace_bytes", "crb_release_workspace",
            "crb_server_create", "crb_server_submit", "crb_server_poll", "crb_server_pending",
            "crb_server_destroy", "crb_debug_iterate", "crb_debug_detect", "crb_debug_median",
-           "crb_debug_fp64", "crb_work_run", "crb_work_radius", "crb_farm_run"]
+           "crb_debug_fp64", "crb_work_run", "crb_work_radius", "crb_farm_run",
+           "crb_plan_set_counting", "crb_plan_work_counts", "crb_debug_median5_f64"]
 CRB_WORK_LACOSMIC = 0
 CRB_WORK_POISSON = 1
 CRB_WORK_WAITER = 2
@@ -86,6 +87,9 @@ def lib():
     L.crb_plan_set_timing.argtypes = [vp, i32]
     L.crb_plan_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(i64)]
+    L.crb_plan_set_counting.argtypes = [vp, i32]
+    L.crb_plan_work_counts.argtypes = [vp, ctypes.POINTER(i64)]
+    L.crb_debug_median5_f64.argtypes = [vp, i32, i32, vp]
     L.crb_set_stream.argtypes = [vp]
     L.crb_set_option.argtypes = [i32, i64]
     L.crb_last_error.argtypes = []
@@ -114,7 +118,8 @@ def lib():
                  "crb_plan_stats", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option", "crb_release_workspace",
                  "crb_server_create", "crb_server_submit", "crb_server_poll",
                  "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64",
-                 "crb_work_run", "crb_farm_run"):
+                 "crb_work_run", "crb_farm_run", "crb_plan_set_counting", "crb_plan_work_counts",
+                 "crb_debug_median5_f64"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -240,6 +245,17 @@ class Plan:
         check("crb_plan_kernel_times", lib().crb_plan_kernel_times(self.handle, ms, n))
         return {k: (ms[i], int(n[i])) for i, k in enumerate(self.KINDS)}
 
+    def set_counting(self, enable: bool) -> None:
+        check("crb_plan_set_counting", lib().crb_plan_set_counting(self.handle,
+                                                                   1 if enable else 0))
+
+    def work_counts(self) -> dict:
+        """Detection work since counting was enabled: work-set pixels (med5 of S and
+        the threshold bits) and contrast tests (med7 of med3 and F^)."""
+        c = (ctypes.c_int64 * 2)()
+        check("crb_plan_work_counts", lib().crb_plan_work_counts(self.handle, c))
+        return dict(work_pixels=int(c[0]), contrast_tests=int(c[1]))
+
     def close(self) -> None:
         if self.handle:
             lib().crb_plan_destroy(self.handle)
@@ -297,6 +313,16 @@ def debug_median(x: torch.Tensor, r: int, stream: Optional[torch.cuda.Stream] = 
     set_stream(stream)
     check("crb_debug_median", lib().crb_debug_median(x.data_ptr(), x.shape[0], x.shape[1], r,
                                                      out.data_ptr()))
+    return out
+
+
+def debug_median5_f64(x: torch.Tensor, stream: Optional[torch.cuda.Stream] = None
+                      ) -> torch.Tensor:
+    _dev2d(x, torch.float64, "x")
+    out = torch.empty_like(x)
+    set_stream(stream)
+    check("crb_debug_median5_f64", lib().crb_debug_median5_f64(x.data_ptr(), x.shape[0],
+                                                               x.shape[1], out.data_ptr()))
     return out
 
 

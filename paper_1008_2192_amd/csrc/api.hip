@@ -364,7 +364,8 @@ crb_status crb_farm_run(const crb_work *w, const float *in, int32_t H, int32_t W
         if ((size_t)tile_h + 2 * kMaxWorkRadius > (1u << 20) ||
             (size_t)tile_w + 2 * kMaxWorkRadius > (1u << 20) ||
             farm_lds_bytes(w->kind, args, tile_h, tile_w) > kMaxFarmLds)
-            return fail(CRB_EINVAL, "staged tile %d x %d with radius %d exceeds %zu bytes of LDS",
+            return fail(CRB_EINVAL, "staged tile %d x %d with radius %d and the record buffer "
+                                    "exceed %zu bytes of LDS",
                         tile_h, tile_w, work_radius(w->kind, args, 0), kMaxFarmLds);
     } else {
         if (!out_image)
@@ -391,13 +392,13 @@ crb_status crb_farm_run(const crb_work *w, const float *in, int32_t H, int32_t W
     std::lock_guard<std::mutex> g(ws->mu);
     if ((st = ws_reserve(ws, 256)) != CRB_OK)
         return st;
-    unsigned int *ticket = reinterpret_cast<unsigned int *>(ws->buf);
+    unsigned int *tickets = reinterpret_cast<unsigned int *>(ws->buf);
     unsigned long long *count = reinterpret_cast<unsigned long long *>(out_count);
-    hipError_t e = launch_farm_reset(ticket, count, s);
+    hipError_t e = launch_farm_reset(tickets, count, s);
     if (e == hipSuccess)
         e = launch_farm(w->kind, a2, in, H, W, workers, tile_h, tile_w, out_image,
                         reinterpret_cast<SourceRec *>(out_list), (long long)list_capacity, count,
-                        ticket, s);
+                        tickets, s);
     st = hip_status(e, "kernel launch");
     return st == CRB_OK ? ok() : st;
 }
@@ -483,6 +484,17 @@ crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, fl
     return st == CRB_OK ? ok() : st;
 }
 
+crb_status crb_debug_median5_f64(const double *in, int32_t H, int32_t W, double *out) {
+    if (!in || !out)
+        return fail(CRB_EINVAL, "null pointer");
+    if (H < 1 || W < 1 || (int64_t)H * W > (int64_t)INT32_MAX)
+        return fail(CRB_EINVAL, "bad size %d x %d", H, W);
+    if (ranges_overlap(in, (size_t)H * W * 8, out, (size_t)H * W * 8))
+        return fail(CRB_EINVAL, "in and out overlap");
+    crb_status st = hip_status(launch_debug_median5_f64(in, H, W, out, t_stream), "kernel launch");
+    return st == CRB_OK ? ok() : st;
+}
+
 crb_status crb_debug_fp64(const double *x, const double *y, int32_t n, double *out_sqrt,
                           double *out_div) {
     if (!x || !y || !out_sqrt || !out_div || n < 0)
@@ -515,6 +527,9 @@ struct crb_plan {
     int ntgrow = 0;
     long long *d_stats = nullptr;
     unsigned int *d_prefix = nullptr;   // flat offsets of the frames' flagged lists
+    unsigned long long *d_work = nullptr;   // per frame: work-set pixels, contrast tests
+    std::vector<DevFrame> hframes;      // host copy of the frame table
+    bool counting = false;
     int rgrid = 1;
     bool use_graph = false;
     hipGraph_t graph = nullptr;
@@ -652,7 +667,8 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     const size_t o_tgrow = o_tdet + ((ntdet * sizeof(TileRef) + 255) / 256) * 256;
     const size_t o_stats = o_tgrow + ((ntgrow * sizeof(TileRef) + 255) / 256) * 256;
     const size_t o_prefix = o_stats + ((2 * n * sizeof(long long) + 255) / 256) * 256;
-    const size_t bytes = o_prefix + (((n + 1) * sizeof(unsigned int) + 255) / 256) * 256;
+    const size_t o_work = o_prefix + (((n + 1) * sizeof(unsigned int) + 255) / 256) * 256;
+    const size_t bytes = o_work + ((2 * n * sizeof(unsigned long long) + 255) / 256) * 256;
 
     crb_plan *p = new (std::nothrow) crb_plan();
     if (!p)
@@ -686,6 +702,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     p->d_tgrow = reinterpret_cast<TileRef *>(p->dmem + o_tgrow);
     p->d_stats = reinterpret_cast<long long *>(p->dmem + o_stats);
     p->d_prefix = reinterpret_cast<unsigned int *>(p->dmem + o_prefix);
+    p->d_work = reinterpret_cast<unsigned long long *>(p->dmem + o_work);
     p->ntdet = (int)ntdet;
     p->ntgrow = (int)ntgrow;
 
@@ -699,6 +716,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
                               f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac, f.objlim,
                               f.niter,
                               (f.flags & CRB_FLAG_NO_EARLY_STOP ? kNoEarlyStop : 0) | kFreshMask);
+        hf[i].work = p->d_work + 2 * (size_t)i;
         for (int y = 0; y < f.H; y += kDetectTY)
             for (int x = 0; x < f.W; x += kDetectTX)
                 td.push_back(TileRef{i, y, x, 0});
@@ -707,11 +725,22 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
                 tg.push_back(TileRef{i, y, x, 0});
     }
     p->rgrid = replace_grid(all_pix);
-    e = hipMemcpy(p->d_frames, hf.data(), n * sizeof(DevFrame), hipMemcpyHostToDevice);
+    // Tables and counters are written on the plan's stream and waited for: a
+    // null-stream copy or memset is not ordered before work on a non-blocking stream,
+    // and a pageable copy may return before its data has landed.
+    e = hipMemcpyAsync(p->d_frames, hf.data(), n * sizeof(DevFrame), hipMemcpyHostToDevice,
+                       p->stream);
     if (e == hipSuccess)
-        e = hipMemcpy(p->d_tdet, td.data(), td.size() * sizeof(TileRef), hipMemcpyHostToDevice);
+        e = hipMemsetAsync(p->d_work, 0, 2 * (size_t)n * sizeof(unsigned long long), p->stream);
     if (e == hipSuccess)
-        e = hipMemcpy(p->d_tgrow, tg.data(), tg.size() * sizeof(TileRef), hipMemcpyHostToDevice);
+        e = hipMemcpyAsync(p->d_tdet, td.data(), td.size() * sizeof(TileRef),
+                           hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_tgrow, tg.data(), tg.size() * sizeof(TileRef),
+                           hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(p->stream);
+    p->hframes = hf;
     if (e != hipSuccess) {
         plan_free(p);
         return hip_status(e, "hipMemcpy");
@@ -782,6 +811,44 @@ crb_status crb_plan_set_timing(crb_plan *p, int32_t enable) {
     for (int i = 0; i < kNumKernelKinds; ++i) {
         p->acc_ms[i] = 0.0;
         p->acc_n[i] = 0;
+    }
+    return ok();
+}
+
+crb_status crb_plan_set_counting(crb_plan *p, int32_t enable) {
+    if (!p)
+        return fail(CRB_EINVAL, "null plan");
+    hipError_t e = hipStreamSynchronize(p->stream);
+    for (DevFrame &f : p->hframes)
+        f.flags = enable ? (f.flags | kCountWork) : (f.flags & ~kCountWork);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p->d_frames, p->hframes.data(), p->hframes.size() * sizeof(DevFrame),
+                           hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(p->d_work, 0, 2 * (size_t)p->n * sizeof(unsigned long long),
+                           p->stream);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess)
+        return hip_status(e, "counter setup");
+    p->counting = enable != 0;
+    return ok();
+}
+
+crb_status crb_plan_work_counts(crb_plan *p, int64_t *counts) {
+    if (!p || !counts)
+        return fail(CRB_EINVAL, "null argument");
+    std::vector<unsigned long long> w(2 * (size_t)p->n);
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(w.data(), p->d_work, w.size() * sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return hip_status(e, "counter copy");
+    counts[0] = counts[1] = 0;
+    for (int i = 0; i < p->n; ++i) {
+        counts[0] += (int64_t)w[2 * (size_t)i];
+        counts[1] += (int64_t)w[2 * (size_t)i + 1];
     }
     return ok();
 }
@@ -902,9 +969,13 @@ extern "C" crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int3
     }
     SubRect *d_subs = reinterpret_cast<SubRect *>(tmp + o_tab);
     crb_plan *plan = nullptr;
-    e = hipMemcpy(d_subs, subs.data(), nsub * sizeof(SubRect), hipMemcpyHostToDevice);
+    // the table goes in on the launch stream (ordered before the extraction on any
+    // stream kind) and is waited for before `subs` can go out of scope
+    e = hipMemcpyAsync(d_subs, subs.data(), nsub * sizeof(SubRect), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = launch_extract(img, W, d_subs, nsub, max_sub, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(tmp);
         return hip_status(e, "subimage extraction");

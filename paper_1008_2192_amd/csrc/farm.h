@@ -23,7 +23,9 @@ namespace crb {
 
 constexpr int kWorkLacosmic = 0, kWorkPoisson = 1, kWorkWaiter = 2, kWorkSources = 3;
 constexpr int kMaxWorkRadius = 8;        // largest apron a staged work function may declare
-constexpr size_t kMaxFarmLds = 64 * 1024;
+constexpr size_t kMaxFarmLds = 64 * 1024; // LDS per workgroup: staged tile + record buffer
+constexpr int kFarmQueues = 8;           // ticket counters (one tile range each)
+constexpr int kFarmRecords = 512;        // records a workgroup buffers before moving them
 
 struct WorkArgs {
     unsigned long long seed;   // POISSON: generator key
@@ -42,17 +44,18 @@ struct SourceRec {
 
 // Declared dependency radius of a work function (host side); -1 for an unknown kind.
 int work_radius(int kind, const WorkArgs &a, int niter);
-// LDS bytes one workgroup needs for a tile (0 for unstaged kinds).
+// LDS bytes one workgroup needs: the staged tile and, for list kinds, the record
+// buffer (0 for unstaged image kinds).
 size_t farm_lds_bytes(int kind, const WorkArgs &a, int tile_h, int tile_w);
 
-// Clears the ticket and, if count is not null, the record counter.
-hipError_t launch_farm_reset(unsigned int *ticket, unsigned long long *count, hipStream_t s);
+// Clears the kFarmQueues ticket counters and, if count is not null, the record counter.
+hipError_t launch_farm_reset(unsigned int *tickets, unsigned long long *count, hipStream_t s);
 // Runs work function `kind` over the frame with `workers` persistent workgroups.
 // Image kinds write out_img (H x W); list kinds append to out_list (at most capacity
-// records are stored, *count receives the total).  *ticket (and *count) must be zero.
+// records are stored, *count receives the total).  The tickets (and *count) must be zero.
 hipError_t launch_farm(int kind, const WorkArgs &args, const float *in, int H, int W,
                        int workers, int tile_h, int tile_w, float *out_img,
                        SourceRec *out_list, long long capacity, unsigned long long *count,
-                       unsigned int *ticket, hipStream_t s);
+                       unsigned int *tickets, hipStream_t s);
 
 }  // namespace crb

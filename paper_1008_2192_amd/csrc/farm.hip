@@ -165,122 +165,216 @@ struct WorkSources {
     }
 };
 
-__global__ void k_farm_reset(unsigned int *ticket, unsigned long long *count) {
-    *ticket = 0u;
-    if (count)
+__global__ void k_farm_reset(unsigned int *tickets, unsigned long long *count) {
+    if (threadIdx.x < kFarmQueues)
+        tickets[threadIdx.x] = 0u;
+    if (threadIdx.x == 0 && count)
         *count = 0ull;
 }
 
-// The persistent farm: each workgroup takes the next tile from the ticket, stages it
-// (with its apron) if the work function reads neighbours, and runs the function on
-// every pixel of the tile.  Positions within a tile advance by whole rows of the
-// thread count, so no per-pixel division is needed.  List outputs are compacted per
-// wave: one ballot, one atomic on the counter, contiguous slots.
+// Moves the records buffered in LDS to the caller's list: one atomic on the counter
+// reserves their slots, then the block copies them as 8-byte words.  Block-wide.
+__device__ __forceinline__ void flush_records(SourceRec *__restrict__ sRec, unsigned int *sN,
+                                              unsigned long long *sBase,
+                                              SourceRec *__restrict__ out_list,
+                                              long long capacity,
+                                              unsigned long long *__restrict__ count) {
+    constexpr int kT = 256, kWords = (int)(sizeof(SourceRec) / 8);
+    const unsigned int n = *sN;
+    if (threadIdx.x == 0)
+        *sBase = atomicAdd(count, (unsigned long long)n);
+    __syncthreads();
+    const unsigned long long base = *sBase;
+    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(sRec);
+    unsigned long long *dst = reinterpret_cast<unsigned long long *>(out_list);
+    for (unsigned int i = threadIdx.x; i < n * kWords; i += kT) {
+        const unsigned long long slot = base + i / kWords;
+        if (slot < (unsigned long long)capacity)
+            dst[base * kWords + i] = src[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        *sN = 0u;
+    __syncthreads();
+}
+
+// The persistent farm.  Tiles are numbered row-major and split into kFarmQueues
+// contiguous ranges, one ticket counter each; a workgroup starts on queue
+// blockIdx % kFarmQueues (workgroups are dealt round-robin to the XCDs, so a queue's
+// tiles stay in one XCD's L2) and, when that range is exhausted, moves on to the
+// next.  A ticket is a run of `chunk` consecutive tiles, so counters see few atomics.
+// Each tile is staged (with its apron) if the work function reads neighbours, and
+// the function runs on every pixel of it; positions within a tile advance by whole
+// rows of the thread count, so no per-pixel division is needed.  List outputs are
+// buffered in LDS (wave ballot, one LDS atomic per wave) and moved to the caller's
+// list when the buffer could not take another pass, and at the end.
 template <class WF>
 __global__ __launch_bounds__(256) void k_farm(const float *__restrict__ in, int H, int W,
-                                              WorkArgs args, int tile_h, int tile_w,
+                                              WorkArgs args, int tile_h, int tile_w, int chunk,
                                               float *__restrict__ out_img,
                                               SourceRec *__restrict__ out_list,
                                               long long capacity,
                                               unsigned long long *__restrict__ count,
-                                              unsigned int *__restrict__ ticket) {
+                                              unsigned int *__restrict__ tickets) {
     constexpr int kT = 256;
     extern __shared__ float sTile[];
-    __shared__ unsigned int sTicket;
+    __shared__ long long sTicket, sEnd;
+    __shared__ SourceRec sRec[WF::kList ? kFarmRecords : 1];
+    __shared__ unsigned int sN;
+    __shared__ unsigned long long sBase;
     const int R = WF::kStaged ? WF::radius(args) : 0;
     const int ntx = (W - 1) / tile_w + 1;
     const long long ntiles = (long long)ntx * ((H - 1) / tile_h + 1);
+    if (WF::kList && threadIdx.x == 0)
+        sN = 0u;
+    int queue = blockIdx.x % kFarmQueues;
     for (;;) {
-        if (threadIdx.x == 0)
-            sTicket = atomicAdd(ticket, 1u);
+        if (threadIdx.x < 64) {
+            // the first wave: lane 0 takes a ticket from the current queue; once that
+            // range is exhausted, lanes 0..7 read all counters at once and the wave
+            // moves to the next queue (in cyclic order) that still has tiles
+            long long t = -1, end = 0;
+            for (;;) {
+                long long got = 0;
+                const long long q0 = ntiles * queue / kFarmQueues;
+                const long long q1 = ntiles * (queue + 1) / kFarmQueues;
+                if (threadIdx.x == 0)
+                    got = (long long)atomicAdd(&tickets[queue], (unsigned int)chunk);
+                got = __shfl((int)got, 0);
+                if (q0 + got < q1) {
+                    t = q0 + got;
+                    end = min(q1, t + chunk);
+                    break;
+                }
+                bool open = false;
+                if (threadIdx.x < kFarmQueues) {
+                    const long long a = ntiles * threadIdx.x / kFarmQueues;
+                    const long long b = ntiles * (threadIdx.x + 1) / kFarmQueues;
+                    const unsigned int seen = __hip_atomic_load(&tickets[threadIdx.x],
+                                                                __ATOMIC_RELAXED,
+                                                                __HIP_MEMORY_SCOPE_AGENT);
+                    open = a + (long long)seen < b;
+                }
+                const unsigned long long m = __ballot(open) & ((1ull << kFarmQueues) - 1ull);
+                if (!m)
+                    break;
+                // next open queue after the current one, cyclically
+                const unsigned long long after = m & ~((2ull << queue) - 1ull);
+                queue = __ffsll((long long)(after ? after : m)) - 1;
+            }
+            if (threadIdx.x == 0) {
+                sTicket = t;
+                sEnd = end;
+            }
+        }
         __syncthreads();
-        const long long t = sTicket;
+        const long long t0 = sTicket, t1 = sEnd;
         __syncthreads();
-        if (t >= ntiles)
-            return;
-        const int y0 = (int)(t / ntx) * tile_h, x0 = (int)(t % ntx) * tile_w;
-        const int th = min(tile_h, H - y0), tw = min(tile_w, W - x0);
-        FarmCtx c;
-        c.in = in;
-        c.tile = nullptr;
-        c.pitch = 0;
-        c.H = H;
-        c.W = W;
-        if constexpr (WF::kStaged) {
-            const int pitch = tw + 2 * R, n = (th + 2 * R) * pitch;
-            const int q = kT / pitch, rem = kT - q * pitch;
-            int ly = threadIdx.x / pitch, lx = threadIdx.x - ly * pitch;
-            for (int i = threadIdx.x; i < n; i += kT) {
-                const int gy = y0 - R + ly, gx = x0 - R + lx;
-                sTile[i] = (gy >= 0 && gy < H && gx >= 0 && gx < W) ? in[(size_t)gy * W + gx]
-                                                                     : WF::kOutside;
+        if (t0 < 0)
+            break;
+        for (long long t = t0; t < t1; ++t) {
+            const int y0 = (int)(t / ntx) * tile_h, x0 = (int)(t % ntx) * tile_w;
+            const int th = min(tile_h, H - y0), tw = min(tile_w, W - x0);
+            FarmCtx c;
+            c.in = in;
+            c.tile = nullptr;
+            c.pitch = 0;
+            c.H = H;
+            c.W = W;
+            if constexpr (WF::kStaged) {
+                // batches of kStageBatch elements per thread: a batch's loads are all
+                // issued before its LDS stores, so their latencies overlap
+                constexpr int kStageBatch = 8;
+                const int pitch = tw + 2 * R, n = (th + 2 * R) * pitch;
+                const int q = kT / pitch, rem = kT - q * pitch;
+                int ly = threadIdx.x / pitch, lx = threadIdx.x - ly * pitch;
+                for (int base = threadIdx.x; base < n; base += kStageBatch * kT) {
+                    float v[kStageBatch];
+#pragma unroll
+                    for (int b = 0; b < kStageBatch; ++b) {
+                        const int gy = y0 - R + ly, gx = x0 - R + lx;
+                        v[b] = WF::kOutside;
+                        if (base + b * kT < n && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                            v[b] = in[(size_t)gy * W + gx];
+                        ly += q;
+                        lx += rem;
+                        if (lx >= pitch) {
+                            lx -= pitch;
+                            ++ly;
+                        }
+                    }
+#pragma unroll
+                    for (int b = 0; b < kStageBatch; ++b)
+                        if (base + b * kT < n)
+                            sTile[base + b * kT] = v[b];
+                }
+                c.tile = sTile;
+                c.pitch = pitch;
+                __syncthreads();
+            }
+            const long long n = (long long)th * tw;
+            const int q = kT / tw, rem = kT - q * tw;
+            int ly = threadIdx.x / tw, lx = threadIdx.x - ly * tw;
+            for (long long j0 = 0; j0 < n; j0 += kT) {
+                const bool valid = j0 + (long long)threadIdx.x < n;
+                c.y = y0 + ly;
+                c.x = x0 + lx;
+                c.ly = ly + R;
+                c.lx = lx + R;
+                if constexpr (WF::kList) {
+                    SourceRec rec;
+                    const bool hit = valid && WF::find(c, args, rec);
+                    const unsigned long long m = __ballot(hit);
+                    if (m) {
+                        const int lane = __lane_id();
+                        const int leader = __ffsll((long long)m) - 1;
+                        unsigned int base = 0u;
+                        if (lane == leader)
+                            base = atomicAdd(&sN, (unsigned int)__popcll(m));
+                        base = __shfl(base, leader);
+                        if (hit)
+                            sRec[base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull))] = rec;
+                    }
+                    __syncthreads();
+                    if (sN > (unsigned int)(kFarmRecords - kT))
+                        flush_records(sRec, &sN, &sBase, out_list, capacity, count);
+                } else {
+                    if (valid)
+                        out_img[(size_t)c.y * W + c.x] = WF::pixel(c, args);
+                }
                 ly += q;
                 lx += rem;
-                if (lx >= pitch) {
-                    lx -= pitch;
+                if (lx >= tw) {
+                    lx -= tw;
                     ++ly;
                 }
             }
-            c.tile = sTile;
-            c.pitch = pitch;
-            __syncthreads();
+            __syncthreads();    // the staged tile is reused by the next tile
         }
-        const long long n = (long long)th * tw;
-        const int q = kT / tw, rem = kT - q * tw;
-        int ly = threadIdx.x / tw, lx = threadIdx.x - ly * tw;
-        for (long long j0 = 0; j0 < n; j0 += kT) {
-            const bool valid = j0 + (long long)threadIdx.x < n;
-            c.y = y0 + ly;
-            c.x = x0 + lx;
-            c.ly = ly + R;
-            c.lx = lx + R;
-            if constexpr (WF::kList) {
-                SourceRec rec;
-                const bool hit = valid && WF::find(c, args, rec);
-                const unsigned long long m = __ballot(hit);
-                if (m) {
-                    const int lane = __lane_id();
-                    const int leader = __ffsll((long long)m) - 1;
-                    unsigned long long base = 0;
-                    if (lane == leader)
-                        base = atomicAdd(count, (unsigned long long)__popcll(m));
-                    const unsigned int lo = __shfl((unsigned int)base, leader);
-                    const unsigned int hi = __shfl((unsigned int)(base >> 32), leader);
-                    base = ((unsigned long long)hi << 32) | lo;
-                    if (hit) {
-                        const unsigned long long slot =
-                            base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
-                        if (slot < (unsigned long long)capacity)
-                            out_list[slot] = rec;
-                    }
-                }
-            } else {
-                if (valid)
-                    out_img[(size_t)c.y * W + c.x] = WF::pixel(c, args);
-            }
-            ly += q;
-            lx += rem;
-            if (lx >= tw) {
-                lx -= tw;
-                ++ly;
-            }
-        }
-        __syncthreads();    // the staged tile is reused for the next ticket
+    }
+    if constexpr (WF::kList) {
+        if (sN)
+            flush_records(sRec, &sN, &sBase, out_list, capacity, count);
     }
 }
 
 template <class WF>
 hipError_t launch_kind(const WorkArgs &args, const float *in, int H, int W, int workers,
                        int tile_h, int tile_w, float *out_img, SourceRec *out_list,
-                       long long capacity, unsigned long long *count, unsigned int *ticket,
+                       long long capacity, unsigned long long *count, unsigned int *tickets,
                        hipStream_t s) {
     size_t lds = 0;
     if (WF::kStaged) {
         const int R = WF::radius(args);
         lds = (size_t)(tile_h + 2 * R) * (size_t)(tile_w + 2 * R) * sizeof(float);
     }
-    k_farm<WF><<<workers, 256, lds, s>>>(in, H, W, args, tile_h, tile_w, out_img, out_list,
-                                        capacity, count, ticket);
+    // tickets of `chunk` tiles: about 8 per workgroup, so the dynamic balance keeps
+    // a fine grain while the counters take few atomics
+    const long long ntiles = (long long)((W - 1) / tile_w + 1) * ((H - 1) / tile_h + 1);
+    long long chunk = ntiles / ((long long)workers * 8);
+    chunk = chunk < 1 ? 1 : (chunk > 64 ? 64 : chunk);
+    k_farm<WF><<<workers, 256, lds, s>>>(in, H, W, args, tile_h, tile_w, (int)chunk, out_img,
+                                        out_list, capacity, count, tickets);
     return hipGetLastError();
 }
 
@@ -303,28 +397,29 @@ size_t farm_lds_bytes(int kind, const WorkArgs &a, int tile_h, int tile_w) {
     if (kind != kWorkSources)
         return 0;
     const int R = WorkSources::radius(a);
-    return (size_t)(tile_h + 2 * R) * (size_t)(tile_w + 2 * R) * sizeof(float);
+    return (size_t)(tile_h + 2 * R) * (size_t)(tile_w + 2 * R) * sizeof(float) +
+           kFarmRecords * sizeof(SourceRec);
 }
 
-hipError_t launch_farm_reset(unsigned int *ticket, unsigned long long *count, hipStream_t s) {
-    k_farm_reset<<<1, 1, 0, s>>>(ticket, count);
+hipError_t launch_farm_reset(unsigned int *tickets, unsigned long long *count, hipStream_t s) {
+    k_farm_reset<<<1, 64, 0, s>>>(tickets, count);
     return hipGetLastError();
 }
 
 hipError_t launch_farm(int kind, const WorkArgs &args, const float *in, int H, int W,
                        int workers, int tile_h, int tile_w, float *out_img,
                        SourceRec *out_list, long long capacity, unsigned long long *count,
-                       unsigned int *ticket, hipStream_t s) {
+                       unsigned int *tickets, hipStream_t s) {
     switch (kind) {
     case kWorkPoisson:
         return launch_kind<WorkPoisson>(args, in, H, W, workers, tile_h, tile_w, out_img,
-                                        out_list, capacity, count, ticket, s);
+                                        out_list, capacity, count, tickets, s);
     case kWorkWaiter:
         return launch_kind<WorkWaiter>(args, in, H, W, workers, tile_h, tile_w, out_img,
-                                       out_list, capacity, count, ticket, s);
+                                       out_list, capacity, count, tickets, s);
     case kWorkSources:
         return launch_kind<WorkSources>(args, in, H, W, workers, tile_h, tile_w, out_img,
-                                        out_list, capacity, count, ticket, s);
+                                        out_list, capacity, count, tickets, s);
     default:
         return hipErrorInvalidValue;
     }

@@ -24,8 +24,10 @@ constexpr int kNumKernelKinds = 4;
 
 // DevFrame::flags bits.  kNoEarlyStop has the value of CRB_FLAG_NO_EARLY_STOP;
 // kFreshMask: the mask is uninitialised before iteration 1, which then writes all of it.
+// kCountWork: detection adds its work-set size and contrast-test count to f.work.
 constexpr int kNoEarlyStop = 1;
 constexpr int kFreshMask = 1 << 8;
+constexpr int kCountWork = 1 << 9;
 
 // Everything a kernel needs to know about one frame.  All pointers are device
 // pointers; J is the image being cleaned in place (out_clean).
@@ -38,6 +40,7 @@ struct DevFrame {
     uint32_t *list;               // indices of flagged pixels, H x W capacity (workspace)
     unsigned long long *nnew;     // n_k per iteration [kMaxIter] (workspace)
     unsigned int *listlen;        // list length per iteration [kMaxIter] (workspace)
+    unsigned long long *work;     // with kCountWork: [work-set pixels, contrast tests], or null
     int H, W;
     float gain, readnoise, sky, sigclip, sigfrac, objlim;
     int niter;
@@ -93,6 +96,8 @@ hipError_t launch_stitch(float *out_clean, uint8_t *out_mask, int W, const SubRe
                          int nsub, size_t max_pixels, hipStream_t s);
 
 hipError_t launch_debug_median(const float *in, int H, int W, int r, float *out, hipStream_t s);
+hipError_t launch_debug_median5_f64(const double *in, int H, int W, double *out,
+                                   hipStream_t s);
 hipError_t launch_debug_fp64(const double *x, const double *y, int n, double *out_sqrt,
                              double *out_div, hipStream_t s);
 

@@ -1,12 +1,16 @@
 """Roofline accounting for the detection kernel (the dominant launch).
 
-Algorithmic work is counted per image pixel with every plane computed once (the
-halo recomputation of a tiled execution is overhead, not algorithm):
-  * median networks: the min/max operations of the networks the kernels use,
-    counted from the generator after dead-code elimination, per output;
-    3-input min/max/median instructions count as one operation;
-  * binary64 arithmetic: one operation per IEEE add, subtract, multiply, divide,
-    square root and compare-select.
+Algorithmic work is counted with every plane computed once (the halo recomputation
+of a tiled execution is overhead, not algorithm):
+  * dense, per image pixel: med3 and med5 of J, L+, N and S, and the S > sigclip
+    test that marks the pixels near which the other statistics can matter;
+  * per work-set pixel (within 2 of an S > sigclip pixel, S > sigfrac * sigclip):
+    med5 of S, S' and the two threshold compares;
+  * per contrast test (S' > sigclip): N again, med7 of med3, F^ and S'/F^ > objlim.
+The two sparse counts come from the kernel's own counters (crb_plan_work_counts).
+Median networks count their min/max operations after dead-code elimination, per
+output, from the generator; binary64 arithmetic counts one operation per IEEE add,
+subtract, multiply, divide, square root and compare-select.
 Peak: 256 compute units x 64 lanes x 2.4 GHz = 3.93e13 lane operations per second
 (one non-packed VALU operation per lane per clock; binary64 add/mul/fma issue at
 the same rate on CDNA4, which is how the published 78.6 TFLOP/s FP64 vector peak
@@ -28,10 +32,13 @@ HBM_PEAK = 8.0e12                         # bytes per second
 LPLUS_OPS = 4 * (1 + 4 + 1) + 3 + 1       # 4 sub-pixels: 4c, 4 subtractions, clip; 3 adds, /4
 NOISE_OPS = 1 + 1 + 1 + 1 + 1 + 1         # +sky, floor, g*m, +rn^2, sqrt, /g
 S_OPS = 2                                 # 2N, L+/(2N)
-CENTRE_OPS = 1 + 1 + 1                    # S - med5(S), > sigclip, > sigfrac*sigclip; the contrast
-                                          # F^ and S'/F^ is needed only where S' > sigclip
+HOT_OPS = 1                               # S > sigclip
 MED3_RUN = 14
 MED3_OPS = (3 * (MED3_RUN + 2) + 4 * MED3_RUN) / MED3_RUN   # column sorts of 3 ops + 4 per output
+# per work-set pixel, besides med5(S): S - med5(S), > sigclip, > sigfrac*sigclip
+WORK_OPS = 3
+# per contrast test, besides med7: N (6), m3 - m7, / N, floor, S'/F^, > objlim
+CONTRAST_OPS = NOISE_OPS + 5
 
 
 @functools.lru_cache(maxsize=None)
@@ -50,14 +57,21 @@ def network_ops_per_output(name: str) -> float:
     raise KeyError(name)
 
 
-def detect_ops_per_pixel() -> dict:
-    med5j = network_ops_per_output("med5_t2x5")
-    med5s = network_ops_per_output("med5_t2x4")
-    med7 = network_ops_per_output("med7_t2x4")
-    parts = dict(med3=MED3_OPS, med5_J=med5j, lplus=LPLUS_OPS, noise=NOISE_OPS, s=S_OPS,
-                 med7=med7, med5_S=med5s, centre=CENTRE_OPS)
-    parts["total"] = sum(parts.values())
-    return parts
+def detect_ops() -> dict:
+    """Operations per image pixel (dense), per work-set pixel and per contrast test."""
+    dense = dict(med3=MED3_OPS, med5_J=network_ops_per_output("med5_t2x5"), lplus=LPLUS_OPS,
+                 noise=NOISE_OPS, s=S_OPS, hot=HOT_OPS)
+    dense["total"] = sum(dense.values())
+    return dict(dense=dense,
+                per_work_pixel=network_ops_per_output("med5_t1x1") + WORK_OPS,
+                per_contrast=network_ops_per_output("med7_t1x1") + CONTRAST_OPS)
+
+
+def detect_ops_per_launch(pixels: int, work_pixels: float, contrast_tests: float) -> float:
+    """Algorithmic lane operations of one detection launch."""
+    o = detect_ops()
+    return (o["dense"]["total"] * pixels + o["per_work_pixel"] * work_pixels +
+            o["per_contrast"] * contrast_tests)
 
 
 DETECT_BYTES_PER_PIXEL = 4 + 1            # read J (FP32), write the code byte

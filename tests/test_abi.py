@@ -152,3 +152,12 @@ def test_farm_argument_validation(L):
     assert L.crb_work_run(_lib.CRB_WORK_SOURCES, x, 8, 8, 0, 4, 1, img) == -1
     assert L.crb_lacosmic_partitioned(x, 64, 64, 1.0, 5.0, 0.0, 4.5, 0.3, 4.0, 4, 2, 2, -2,
                                       img, lst) == -1
+
+
+def test_counting_and_debug_entry_validation(L):
+    c = (ctypes.c_int64 * 2)()
+    assert L.crb_plan_set_counting(None, 1) == -1
+    assert L.crb_plan_work_counts(None, c) == -1
+    assert L.crb_debug_median5_f64(None, 4, 4, ctypes.c_void_p(1 << 40)) == -1
+    assert L.crb_debug_median5_f64(ctypes.c_void_p(1 << 41), 0, 4, ctypes.c_void_p(1 << 40)) == -1
+    assert L.crb_debug_median5_f64(ctypes.c_void_p(1 << 40), 4, 4, ctypes.c_void_p((1 << 40) + 8)) == -1

@@ -72,18 +72,88 @@ def test_median_networks_match_oracle(r):
             np.testing.assert_array_equal(g.cpu().numpy(), exp, err_msg=f"{H}x{W} {kind}")
 
 
+def dilate(mask, r):
+    """In-frame (2r+1)^2 dilation, computed by shifting (no library call)."""
+    H, W = mask.shape
+    out = np.zeros_like(mask)
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            ys, ye = max(0, -dy), min(H, H - dy)
+            xs, xe = max(0, -dx), min(W, W - dx)
+            if ys < ye and xs < xe:
+                out[ys:ye, xs:xe] |= mask[ys + dy:ye + dy, xs + dx:xe + dx]
+    return out
+
+
+def grow_from_codes(codes):
+    """G1 and G2 of the method from a code plane (A, hi, lo bits)."""
+    A, hi, lo = (codes & 1) > 0, (codes & 2) > 0, (codes & 4) > 0
+    G1 = dilate(A, 1) & hi
+    return G1, dilate(G1, 1) & lo
+
+
 def test_detection_codes_match_oracle():
+    """Codes equal the full definition within distance 2 of S > sigclip and are 0
+    elsewhere; G1 and G2 built from them equal the oracle's."""
     for f in small_frames():
         p = fparams(f)
         tr = ref.iterate(f.img, np.zeros(f.img.shape, np.uint8), trace=True, **p)
         exp = (tr["first"] | ((tr["sprime"] > p["sigclip"]) << 1) |
                ((tr["sprime"] > p["sigfrac"] * p["sigclip"]) << 2)).astype(np.uint8)
+        near = dilate(tr["s"] > p["sigclip"], 2)
         codes = _lib.debug_detect(torch.from_numpy(f.img).to(DEV), **p)
         torch.cuda.synchronize()
         got = codes.cpu().numpy()
-        log(f"detect {f.img.shape}: {int((got != exp).sum())} code mismatches, "
-            f"{int((exp & 1).sum())} first-selected")
-        np.testing.assert_array_equal(got, exp, err_msg=str(f.img.shape))
+        log(f"detect {f.img.shape}: {int((got[near] != exp[near]).sum())} code mismatches near "
+            f"S > sigclip ({int(near.sum())} px), {int((got[~near] != 0).sum())} nonzero "
+            f"elsewhere, {int((exp & 1).sum())} first-selected")
+        np.testing.assert_array_equal(got[near], exp[near], err_msg=str(f.img.shape))
+        assert not got[~near].any(), f.img.shape
+        G1, G2 = grow_from_codes(got)
+        np.testing.assert_array_equal(G1, tr["g1"] > 0)
+        np.testing.assert_array_equal(G2, tr["g2"] > 0)
+
+
+def test_single_output_med5_network_binary64():
+    rng = np.random.default_rng(5)
+    for (H, W) in [(1, 1), (1, 7), (7, 1), (5, 5), (33, 70)]:
+        for kind in ("ties", "cont"):
+            if kind == "ties":
+                x = rng.integers(0, 4, (H, W)).astype(np.float64)
+            else:
+                x = rng.normal(0, 1, (H, W)) * 10.0 ** rng.integers(-3, 4, (H, W))
+            g = _lib.debug_median5_f64(torch.from_numpy(x).to(DEV))
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(g.cpu().numpy(), ref.median_filter(x, 2),
+                                          err_msg=f"{H}x{W} {kind}")
+
+
+def test_work_counts_match_oracle_sets():
+    """Plan work counters on one iteration: the work set is D2(S > sigclip) &
+    (S > sigfrac*sigclip) and the contrast tests are the pixels with S' > sigclip,
+    both exactly as computed from the oracle's planes."""
+    frames = small_frames()[:2] + [synth.c1_density_frame(300, 400, 77, 2.5, 6.0)]
+    items, exp_w, exp_c = [], 0, 0
+    for f in frames:
+        p = fparams(f)
+        tr = ref.iterate(f.img, np.zeros(f.img.shape, np.uint8), trace=True, **p)
+        lowlim = np.float64(np.float32(p["sigfrac"])) * np.float64(np.float32(p["sigclip"]))
+        exp_w += int((dilate(tr["s"] > p["sigclip"], 2) & (tr["s"] > lowlim)).sum())
+        exp_c += int((tr["sprime"] > p["sigclip"]).sum())
+        img = torch.from_numpy(f.img).to(DEV)
+        items.append(dict(img=img, out_clean=torch.empty_like(img),
+                          out_mask=torch.empty(img.shape, dtype=torch.uint8, device=DEV),
+                          niter=1, early_stop=False, **p))
+    plan = _lib.Plan(items, use_graph=False)
+    plan.set_counting(True)
+    plan.run()
+    got = plan.work_counts()
+    plan.set_counting(False)                  # clears the counters and stops counting
+    plan.run()
+    assert plan.work_counts() == dict(work_pixels=0, contrast_tests=0)
+    plan.close()
+    log(f"work counts {got}, expected {exp_w} / {exp_c}")
+    assert got == dict(work_pixels=exp_w, contrast_tests=exp_c)
 
 
 def test_iterations_teacher_forced():
