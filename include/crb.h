@@ -165,11 +165,12 @@ crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int32_t W, floa
 
 /*
  * The tile farm (the paper's computational framework, Sections 6.3 and 7).  A work
- * function declares its dependency radius; the farm cuts the frame into tile_h x
- * tile_w rectangles, stages each with an apron of that radius when the function
- * reads neighbours (positions outside the frame are never read as pixels), and hands
- * the rectangles to `workers` persistent workgroups through an atomic ticket, as
- * CRBLASTER's director hands subimages to free actors.  Work functions:
+ * function declares its dependency radius: how far from a pixel it reads (positions
+ * outside the frame are never read), and so the border a partition into independent
+ * subimages must give it.  The farm cuts the frame into tile_h x tile_w rectangles
+ * and hands them to `workers` persistent actors through atomic tickets, as
+ * CRBLASTER's director hands subimages to free actors; the whole frame is resident,
+ * so an actor reads a tile's neighbourhood directly.  Work functions:
  *   CRB_WORK_LACOSMIC (radius query only): the cleaning pass; radius 8 * niter, the
  *     border independent subimages need to reproduce a whole-frame run (one iteration
  *     reaches 8 pixels: 4 for the detection statistics, 1 for each of the two grows,
@@ -218,9 +219,10 @@ int32_t crb_work_radius(const crb_work *w);
 
 /*
  * Run a farm work function (POISSON, WAITER or SOURCES) over the H x W FP32 device
- * frame `in`.  workers in [1, 2^20]; tile_h, tile_w >= 1, and for SOURCES the staged
- * tile (tile_h + 2R) x (tile_w + 2R) x 4 bytes (R the radius) and the workgroup's
- * 20 KiB record buffer must fit in 64 KiB together.
+ * frame `in` with `workers` actors, each a wave of 64 lanes (four per workgroup);
+ * workers in [1, 2^22]; tile_h, tile_w >= 1.  SOURCES passes every pixel through the
+ * threshold and runs the peak test and the sums only on the pixels above it, a
+ * wave's candidates compacted so that all its lanes share that work.
  *   Image kinds: out_image (device, H x W FP32; may equal in, must not partially
  *     overlap it); out_list and out_count must be null.
  *   SOURCES: out_count (device int64, 8-byte aligned) receives the number of sources;
@@ -229,7 +231,7 @@ int32_t crb_work_radius(const crb_work *w);
  *     sort by (y, x) for raster order; a count above list_capacity means the list
  *     was truncated and a rerun with a larger list returns all.  out_image must be null.
  * Tiles are handed out through 8 ticket counters, each over a contiguous range of
- * tiles, in runs of several tiles; a workgroup drains its own range first and then
+ * tiles, in runs of several tiles; an actor drains its own range first and then
  * helps with the others.  Asynchronous on the calling thread's stream; uses 32 bytes
  * of that stream's workspace, so calls on one stream are ordered and calls on
  * different streams are independent.

@@ -408,11 +408,12 @@ class SourceList:
 
 
 def farm_sources(x: torch.Tensor, threshold: float, sky: float = 0.0, r: int = 2, a: int = 2,
-                 workers: int = 2048, tile_h: int = 32, tile_w: int = 64,
+                 workers: int = 4096, tile_h: int = 32, tile_w: int = 64,
                  capacity: int = 1 << 20, out: Optional[SourceList] = None,
                  stream: Optional[torch.cuda.Stream] = None) -> SourceList:
     """crb_farm_run with the SOURCES work function: peaks above threshold with their
-    aperture sums; asynchronous (read the result with .numpy())."""
+    aperture sums, by `workers` actors (waves); asynchronous (read the result with
+    .numpy())."""
     _dev2d(x, torch.float32, "x")
     H, W = x.shape
     if out is None:

@@ -343,8 +343,8 @@ crb_status crb_farm_run(const crb_work *w, const float *in, int32_t H, int32_t W
         return fail(CRB_EINVAL, "image size %d x %d: both must be >= 1", H, W);
     if ((int64_t)H * (int64_t)W > (int64_t)INT32_MAX)
         return fail(CRB_ETOOBIG, "image exceeds 2^31-1 pixels");
-    if (workers < 1 || workers > (1 << 20) || tile_h < 1 || tile_w < 1)
-        return fail(CRB_EINVAL, "workers must lie in [1, 2^20] and tiles be at least 1 x 1");
+    if (workers < 1 || workers > (1 << 22) || tile_h < 1 || tile_w < 1)
+        return fail(CRB_EINVAL, "workers must lie in [1, 2^22] and tiles be at least 1 x 1");
     const size_t nbytes = (size_t)H * (size_t)W * 4;
     const bool list = w->kind == CRB_WORK_SOURCES;
     if (list) {
@@ -361,12 +361,6 @@ crb_status crb_farm_run(const crb_work *w, const float *in, int32_t H, int32_t W
             return fail(CRB_EINVAL, "out_list overlaps the frame or the count");
         if (ranges_overlap(out_count, 8, in, nbytes))
             return fail(CRB_EINVAL, "out_count overlaps the frame");
-        if ((size_t)tile_h + 2 * kMaxWorkRadius > (1u << 20) ||
-            (size_t)tile_w + 2 * kMaxWorkRadius > (1u << 20) ||
-            farm_lds_bytes(w->kind, args, tile_h, tile_w) > kMaxFarmLds)
-            return fail(CRB_EINVAL, "staged tile %d x %d with radius %d and the record buffer "
-                                    "exceed %zu bytes of LDS",
-                        tile_h, tile_w, work_radius(w->kind, args, 0), kMaxFarmLds);
     } else {
         if (!out_image)
             return fail(CRB_EINVAL, "null out_image");

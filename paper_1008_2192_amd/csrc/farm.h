@@ -4,15 +4,17 @@
 //   kList        false: one FP32 output per pixel (an image, like a cleaned subimage);
 //                true : a variable number of SourceRec records (the paper's example of
 //                actors returning structures instead of subimages);
-//   kStaged      true : the function reads neighbours, so the farm stages each tile
-//                with an apron of radius() pixels in LDS (out-of-frame positions hold
-//                kOutside); false: it reads its own pixel from global memory only;
-//   radius(args) the dependency radius: the farm's apron, and the border a partition
-//                into independent subimages needs for an exact result.
+//   radius(args) its dependency radius: how far from a pixel it may read, and so the
+//                border a partition into independent subimages must give it for an
+//                exact result (the farm itself reads neighbours straight from the
+//                frame, which is resident in HBM);
+//   pixel() or candidate() + find(): the per-pixel computation (list functions pass
+//                every pixel through the cheap candidate() test and run find() only on
+//                the candidates, compacted, so that whole waves do the expensive part).
 // The farm cuts the frame into tile_h x tile_w rectangles and hands them to a
-// persistent grid of workgroups through an atomic ticket, as CRBLASTER's director
-// hands subimages to free actors; adding a work function means adding one struct and
-// one dispatch line, nothing else in the farm changes.
+// persistent set of waves through atomic tickets, as CRBLASTER's director hands
+// subimages to free actors; adding a work function means adding one struct and one
+// dispatch line, nothing else in the farm changes.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -22,10 +24,10 @@
 namespace crb {
 
 constexpr int kWorkLacosmic = 0, kWorkPoisson = 1, kWorkWaiter = 2, kWorkSources = 3;
-constexpr int kMaxWorkRadius = 8;        // largest apron a staged work function may declare
-constexpr size_t kMaxFarmLds = 64 * 1024; // LDS per workgroup: staged tile + record buffer
+constexpr int kMaxWorkRadius = 8;        // largest radius a work function may declare
 constexpr int kFarmQueues = 8;           // ticket counters (one tile range each)
-constexpr int kFarmRecords = 512;        // records a workgroup buffers before moving them
+constexpr int kFarmCandidates = 1024;    // candidates a wave collects before running them
+constexpr int kFarmWaveRecords = 128;    // records a wave buffers before moving them
 
 struct WorkArgs {
     unsigned long long seed;   // POISSON: generator key
@@ -44,13 +46,10 @@ struct SourceRec {
 
 // Declared dependency radius of a work function (host side); -1 for an unknown kind.
 int work_radius(int kind, const WorkArgs &a, int niter);
-// LDS bytes one workgroup needs: the staged tile and, for list kinds, the record
-// buffer (0 for unstaged image kinds).
-size_t farm_lds_bytes(int kind, const WorkArgs &a, int tile_h, int tile_w);
 
 // Clears the kFarmQueues ticket counters and, if count is not null, the record counter.
 hipError_t launch_farm_reset(unsigned int *tickets, unsigned long long *count, hipStream_t s);
-// Runs work function `kind` over the frame with `workers` persistent workgroups.
+// Runs work function `kind` over the frame with `workers` persistent waves (actors).
 // Image kinds write out_img (H x W); list kinds append to out_list (at most capacity
 // records are stored, *count receives the total).  The tickets (and *count) must be zero.
 hipError_t launch_farm(int kind, const WorkArgs &args, const float *in, int H, int W,

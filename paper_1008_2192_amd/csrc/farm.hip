@@ -75,18 +75,15 @@ __device__ __forceinline__ float poisson_deviate(float mean_f, size_t i, uint32_
     }
 }
 
-// Where a work function finds its pixel: the frame in global memory, and for
-// staged kinds the LDS copy of the tile with its apron.
+// Where a work function finds its pixel: the frame (resident in HBM; neighbours are
+// read through the caches, never beyond the declared radius) and the position.
 struct FarmCtx {
     const float *in;      // frame, H x W
-    const float *tile;    // staged tile (row length pitch), null for unstaged kinds
-    int pitch;
-    int ly, lx;           // the pixel's position in the staged tile (apron included)
     int y, x, H, W;       // the pixel's frame coordinates, frame size
 };
 
 struct WorkPoisson {
-    static constexpr bool kList = false, kStaged = false;
+    static constexpr bool kList = false;
     __host__ __device__ static int radius(const WorkArgs &) { return 0; }
     __device__ static float pixel(const FarmCtx &c, const WorkArgs &a) {
         const size_t i = (size_t)c.y * c.W + c.x;
@@ -96,7 +93,7 @@ struct WorkPoisson {
 
 // WAITER: wait in[i] microseconds (clamped to [0, 1e6]), then copy the pixel.
 struct WorkWaiter {
-    static constexpr bool kList = false, kStaged = false;
+    static constexpr bool kList = false;
     __host__ __device__ static int radius(const WorkArgs &) { return 0; }
     __device__ static float pixel(const FarmCtx &c, const WorkArgs &a) {
         const float v = c.in[(size_t)c.y * c.W + c.x];
@@ -115,53 +112,133 @@ struct WorkWaiter {
 
 // SOURCES: a pixel is a source when it exceeds the threshold and every other pixel
 // of the frame within Chebyshev distance r is smaller, or equal and later in raster
-// order (a plateau reports its first pixel).  Out-of-frame apron positions hold
-// -inf, which every candidate beats, so the peak test needs no bounds checks.  The
-// record's sums run over the in-frame pixels of the (2a+1)^2 box, row by row, in
-// binary64 (no contraction), which fixes their rounding.
-struct WorkSources {
-    static constexpr bool kList = true, kStaged = true;
-    static constexpr float kOutside = -INFINITY;
-    __host__ __device__ static int radius(const WorkArgs &a) { return a.r > a.a ? a.r : a.a; }
-    __device__ static bool find(const FarmCtx &c, const WorkArgs &a, SourceRec &rec) {
-        const float *t = c.tile + c.ly * c.pitch + c.lx;
-        const float v = t[0];
-        if (!(v > a.threshold))
-            return false;
-        for (int dy = -a.r; dy <= a.r; ++dy) {
-            const float *row = t + dy * c.pitch;
-            for (int dx = -a.r; dx <= a.r; ++dx) {
-                const float q = row[dx];
-                const bool later = dy > 0 || (dy == 0 && dx > 0);
-                if (!(q < v) && !(later && q == v) && (dy != 0 || dx != 0))
-                    return false;
-            }
-        }
-        rec.y = c.y;
-        rec.x = c.x;
-        rec.peak = v;
-        int npix = 0;
-        double flux = 0.0, sy = 0.0, sx = 0.0;
-        const double sky = (double)a.sky;
-        for (int dy = -a.a; dy <= a.a; ++dy) {
-            if (c.y + dy < 0 || c.y + dy >= c.H)
+// order (a plateau reports its first pixel).  The record's sums run over the
+// in-frame pixels of the (2a+1)^2 box, row by row, in binary64 (no contraction),
+// which fixes their rounding.  candidate() is the cheap test every pixel takes;
+// find() runs on the candidates only.  The window is read row by row with 2R+1
+// loads per row at clamped columns (R = max(r, a) <= 4, a compile-time bound chosen
+// by a uniform switch), all rows unrolled, so the loads of a candidate overlap instead
+// of each waiting for the one before.
+template <int R>
+__device__ __forceinline__ bool sources_find(const FarmCtx &c, const WorkArgs &a,
+                                             SourceRec &rec) {
+    constexpr int K = 2 * R + 1;
+    const float *p = c.in + (size_t)c.y * c.W + c.x;
+    const float v = p[0];
+    bool peak = true;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+        const int yy = c.y + dy;
+        if (dy < -a.r || dy > a.r || yy < 0 || yy >= c.H)
+            continue;
+        const float *row = c.in + (size_t)yy * c.W;
+        float q[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            q[k] = row[min(max(c.x - R + k, 0), c.W - 1)];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int dx = k - R, xx = c.x + dx;
+            if (dx < -a.r || dx > a.r || xx < 0 || xx >= c.W || (dy == 0 && dx == 0))
                 continue;
-            const float *row = t + dy * c.pitch;
-            for (int dx = -a.a; dx <= a.a; ++dx) {
-                if (c.x + dx < 0 || c.x + dx >= c.W)
-                    continue;
-                const double d = (double)row[dx] - sky;
-                flux = flux + d;
-                sy = sy + (double)dy * d;
-                sx = sx + (double)dx * d;
-                ++npix;
-            }
+            const bool later = dy > 0 || (dy == 0 && dx > 0);
+            if (!(q[k] < v) && !(later && q[k] == v))
+                peak = false;
         }
-        rec.npix = npix;
-        rec.flux = flux;
-        rec.sy = sy;
-        rec.sx = sx;
-        return true;
+    }
+    if (!peak)
+        return false;
+    rec.y = c.y;
+    rec.x = c.x;
+    rec.peak = v;
+    int npix = 0;
+    double flux = 0.0, sy = 0.0, sx = 0.0;
+    const double sky = (double)a.sky;
+#pragma unroll
+    for (int dy = -R; dy <= R; ++dy) {
+        const int yy = c.y + dy;
+        if (dy < -a.a || dy > a.a || yy < 0 || yy >= c.H)
+            continue;
+        const float *row = c.in + (size_t)yy * c.W;
+        float q[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            q[k] = row[min(max(c.x - R + k, 0), c.W - 1)];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int dx = k - R, xx = c.x + dx;
+            if (dx < -a.a || dx > a.a || xx < 0 || xx >= c.W)
+                continue;
+            const double d = (double)q[k] - sky;
+            flux = flux + d;
+            sy = sy + (double)dy * d;
+            sx = sx + (double)dx * d;
+            ++npix;
+        }
+    }
+    rec.npix = npix;
+    rec.flux = flux;
+    rec.sy = sy;
+    rec.sx = sx;
+    return true;
+}
+
+// The same test and sums with run-time loops, for radii above 4 (larger unrolled
+// windows would not fit in registers).
+__device__ __forceinline__ bool sources_find_loops(const FarmCtx &c, const WorkArgs &a,
+                                                   SourceRec &rec) {
+    const float *p = c.in + (size_t)c.y * c.W + c.x;
+    const float v = p[0];
+    const int ya = max(c.y - a.r, 0), yb = min(c.y + a.r, c.H - 1);
+    const int xa = max(c.x - a.r, 0), xb = min(c.x + a.r, c.W - 1);
+    for (int yy = ya; yy <= yb; ++yy) {
+        const float *row = c.in + (size_t)yy * c.W;
+        for (int xx = xa; xx <= xb; ++xx) {
+            const float q = row[xx];
+            const bool later = yy > c.y || (yy == c.y && xx > c.x);
+            if (!(q < v) && !(later && q == v) && (yy != c.y || xx != c.x))
+                return false;
+        }
+    }
+    rec.y = c.y;
+    rec.x = c.x;
+    rec.peak = v;
+    int npix = 0;
+    double flux = 0.0, sy = 0.0, sx = 0.0;
+    const double sky = (double)a.sky;
+    for (int dy = -a.a; dy <= a.a; ++dy) {
+        if (c.y + dy < 0 || c.y + dy >= c.H)
+            continue;
+        const float *row = p + (ptrdiff_t)dy * c.W;
+        for (int dx = -a.a; dx <= a.a; ++dx) {
+            if (c.x + dx < 0 || c.x + dx >= c.W)
+                continue;
+            const double d = (double)row[dx] - sky;
+            flux = flux + d;
+            sy = sy + (double)dy * d;
+            sx = sx + (double)dx * d;
+            ++npix;
+        }
+    }
+    rec.npix = npix;
+    rec.flux = flux;
+    rec.sy = sy;
+    rec.sx = sx;
+    return true;
+}
+
+struct WorkSources {
+    static constexpr bool kList = true;
+    __host__ __device__ static int radius(const WorkArgs &a) { return a.r > a.a ? a.r : a.a; }
+    __device__ static bool candidate(float v, const WorkArgs &a) { return v > a.threshold; }
+    __device__ static bool find(const FarmCtx &c, const WorkArgs &a, SourceRec &rec) {
+        switch (radius(a)) {
+        case 1: return sources_find<1>(c, a, rec);
+        case 2: return sources_find<2>(c, a, rec);
+        case 3: return sources_find<3>(c, a, rec);
+        case 4: return sources_find<4>(c, a, rec);
+        default: return sources_find_loops(c, a, rec);
+        }
     }
 };
 
@@ -172,189 +249,186 @@ __global__ void k_farm_reset(unsigned int *tickets, unsigned long long *count) {
         *count = 0ull;
 }
 
-// Moves the records buffered in LDS to the caller's list: one atomic on the counter
-// reserves their slots, then the block copies them as 8-byte words.  Block-wide.
-__device__ __forceinline__ void flush_records(SourceRec *__restrict__ sRec, unsigned int *sN,
-                                              unsigned long long *sBase,
+// The next run of tiles for the calling wave, or t0 = -1 when every queue is drained.
+// Lane 0 takes a ticket from the wave's current queue; once that range is exhausted,
+// lanes 0..7 read all counters at once and the wave moves to the next queue (in
+// cyclic order) that still has tiles.
+__device__ __forceinline__ void next_tiles(unsigned int *__restrict__ tickets, long long ntiles,
+                                           int chunk, int &queue, long long &t0, long long &t1) {
+    const int lane = __lane_id();
+    for (;;) {
+        const long long q0 = ntiles * queue / kFarmQueues;
+        const long long q1 = ntiles * (queue + 1) / kFarmQueues;
+        int got = 0;
+        if (lane == 0)
+            got = (int)atomicAdd(&tickets[queue], (unsigned int)chunk);
+        got = __shfl(got, 0);
+        if (q0 + got < q1) {
+            t0 = q0 + got;
+            t1 = min(q1, t0 + chunk);
+            return;
+        }
+        bool open = false;
+        if (lane < kFarmQueues) {
+            const long long a = ntiles * lane / kFarmQueues;
+            const long long b = ntiles * (lane + 1) / kFarmQueues;
+            const unsigned int seen = __hip_atomic_load(&tickets[lane], __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            open = a + (long long)seen < b;
+        }
+        const unsigned long long m = __ballot(open) & ((1ull << kFarmQueues) - 1ull);
+        if (!m) {
+            t0 = t1 = -1;
+            return;
+        }
+        const unsigned long long after = m & ~((2ull << queue) - 1ull);
+        queue = __ffsll((long long)(after ? after : m)) - 1;
+    }
+}
+
+// Moves a wave's buffered records to the caller's list: one atomic on the counter
+// reserves their slots, then the wave copies them as 8-byte words.
+__device__ __forceinline__ void flush_records(const SourceRec *__restrict__ buf, int n,
                                               SourceRec *__restrict__ out_list,
                                               long long capacity,
                                               unsigned long long *__restrict__ count) {
-    constexpr int kT = 256, kWords = (int)(sizeof(SourceRec) / 8);
-    const unsigned int n = *sN;
-    if (threadIdx.x == 0)
-        *sBase = atomicAdd(count, (unsigned long long)n);
-    __syncthreads();
-    const unsigned long long base = *sBase;
-    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(sRec);
+    constexpr int kWords = (int)(sizeof(SourceRec) / 8);
+    const int lane = __lane_id();
+    unsigned long long base = 0ull;
+    if (lane == 0)
+        base = atomicAdd(count, (unsigned long long)n);
+    const unsigned int lo = __shfl((unsigned int)base, 0);
+    const unsigned int hi = __shfl((unsigned int)(base >> 32), 0);
+    base = ((unsigned long long)hi << 32) | lo;
+    const unsigned long long *src = reinterpret_cast<const unsigned long long *>(buf);
     unsigned long long *dst = reinterpret_cast<unsigned long long *>(out_list);
-    for (unsigned int i = threadIdx.x; i < n * kWords; i += kT) {
-        const unsigned long long slot = base + i / kWords;
-        if (slot < (unsigned long long)capacity)
+    for (int i = lane; i < n * kWords; i += 64)
+        if (base + (unsigned long long)(i / kWords) < (unsigned long long)capacity)
             dst[base * kWords + i] = src[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        *sN = 0u;
-    __syncthreads();
 }
 
-// The persistent farm.  Tiles are numbered row-major and split into kFarmQueues
-// contiguous ranges, one ticket counter each; a workgroup starts on queue
-// blockIdx % kFarmQueues (workgroups are dealt round-robin to the XCDs, so a queue's
-// tiles stay in one XCD's L2) and, when that range is exhausted, moves on to the
-// next.  A ticket is a run of `chunk` consecutive tiles, so counters see few atomics.
-// Each tile is staged (with its apron) if the work function reads neighbours, and
-// the function runs on every pixel of it; positions within a tile advance by whole
-// rows of the thread count, so no per-pixel division is needed.  List outputs are
-// buffered in LDS (wave ballot, one LDS atomic per wave) and moved to the caller's
-// list when the buffer could not take another pass, and at the end.
+// The farm.  Every wave is an actor: it takes runs of `chunk` tiles from the tickets
+// (tiles numbered row-major, split into kFarmQueues contiguous ranges; a wave starts
+// on the queue of its global wave index modulo kFarmQueues -- workgroups are dealt
+// round-robin to the XCDs, so a queue's tiles mostly stay in one XCD's L2) and works
+// through each tile 64 pixels at a time, with no workgroup barrier.
+//   Image work functions compute every pixel of the tile.
+//   List work functions first scan the tile with kScanBatch loads in flight per lane
+//   and compact the pixels that pass candidate() into a per-wave LDS list; all lanes
+//   then run find() on the list (one candidate per lane) and buffer the records they
+//   find per wave, moving them to the caller's list when the buffer could not take
+//   another pass and at the end.
 template <class WF>
 __global__ __launch_bounds__(256) void k_farm(const float *__restrict__ in, int H, int W,
                                               WorkArgs args, int tile_h, int tile_w, int chunk,
-                                              float *__restrict__ out_img,
+                                              int waves, float *__restrict__ out_img,
                                               SourceRec *__restrict__ out_list,
                                               long long capacity,
                                               unsigned long long *__restrict__ count,
                                               unsigned int *__restrict__ tickets) {
-    constexpr int kT = 256;
-    extern __shared__ float sTile[];
-    __shared__ long long sTicket, sEnd;
-    __shared__ SourceRec sRec[WF::kList ? kFarmRecords : 1];
-    __shared__ unsigned int sN;
-    __shared__ unsigned long long sBase;
-    const int R = WF::kStaged ? WF::radius(args) : 0;
+    constexpr int kScanBatch = 16;
+    __shared__ int sCand[WF::kList ? 4 * kFarmCandidates : 1];
+    __shared__ SourceRec sRec[WF::kList ? 4 * kFarmWaveRecords : 1];
+    const int wave = threadIdx.x >> 6, lane = __lane_id();
+    const int gwave = blockIdx.x * 4 + wave;
+    if (gwave >= waves)
+        return;
+    int *cand = sCand + (WF::kList ? wave * kFarmCandidates : 0);
+    SourceRec *rbuf = sRec + (WF::kList ? wave * kFarmWaveRecords : 0);
+    int nrec = 0;
     const int ntx = (W - 1) / tile_w + 1;
     const long long ntiles = (long long)ntx * ((H - 1) / tile_h + 1);
-    if (WF::kList && threadIdx.x == 0)
-        sN = 0u;
-    int queue = blockIdx.x % kFarmQueues;
+    int queue = gwave % kFarmQueues;
+    FarmCtx c;
+    c.in = in;
+    c.H = H;
+    c.W = W;
     for (;;) {
-        if (threadIdx.x < 64) {
-            // the first wave: lane 0 takes a ticket from the current queue; once that
-            // range is exhausted, lanes 0..7 read all counters at once and the wave
-            // moves to the next queue (in cyclic order) that still has tiles
-            long long t = -1, end = 0;
-            for (;;) {
-                long long got = 0;
-                const long long q0 = ntiles * queue / kFarmQueues;
-                const long long q1 = ntiles * (queue + 1) / kFarmQueues;
-                if (threadIdx.x == 0)
-                    got = (long long)atomicAdd(&tickets[queue], (unsigned int)chunk);
-                got = __shfl((int)got, 0);
-                if (q0 + got < q1) {
-                    t = q0 + got;
-                    end = min(q1, t + chunk);
-                    break;
-                }
-                bool open = false;
-                if (threadIdx.x < kFarmQueues) {
-                    const long long a = ntiles * threadIdx.x / kFarmQueues;
-                    const long long b = ntiles * (threadIdx.x + 1) / kFarmQueues;
-                    const unsigned int seen = __hip_atomic_load(&tickets[threadIdx.x],
-                                                                __ATOMIC_RELAXED,
-                                                                __HIP_MEMORY_SCOPE_AGENT);
-                    open = a + (long long)seen < b;
-                }
-                const unsigned long long m = __ballot(open) & ((1ull << kFarmQueues) - 1ull);
-                if (!m)
-                    break;
-                // next open queue after the current one, cyclically
-                const unsigned long long after = m & ~((2ull << queue) - 1ull);
-                queue = __ffsll((long long)(after ? after : m)) - 1;
-            }
-            if (threadIdx.x == 0) {
-                sTicket = t;
-                sEnd = end;
-            }
-        }
-        __syncthreads();
-        const long long t0 = sTicket, t1 = sEnd;
-        __syncthreads();
+        long long t0, t1;
+        next_tiles(tickets, ntiles, chunk, queue, t0, t1);
         if (t0 < 0)
             break;
         for (long long t = t0; t < t1; ++t) {
             const int y0 = (int)(t / ntx) * tile_h, x0 = (int)(t % ntx) * tile_w;
             const int th = min(tile_h, H - y0), tw = min(tile_w, W - x0);
-            FarmCtx c;
-            c.in = in;
-            c.tile = nullptr;
-            c.pitch = 0;
-            c.H = H;
-            c.W = W;
-            if constexpr (WF::kStaged) {
-                // batches of kStageBatch elements per thread: a batch's loads are all
-                // issued before its LDS stores, so their latencies overlap
-                constexpr int kStageBatch = 8;
-                const int pitch = tw + 2 * R, n = (th + 2 * R) * pitch;
-                const int q = kT / pitch, rem = kT - q * pitch;
-                int ly = threadIdx.x / pitch, lx = threadIdx.x - ly * pitch;
-                for (int base = threadIdx.x; base < n; base += kStageBatch * kT) {
-                    float v[kStageBatch];
+            const long long n = (long long)th * tw;
+            const int q = 64 / tw, rem = 64 - q * tw;
+            int ly = lane / tw, lx = lane - ly * tw;
+            if constexpr (!WF::kList) {
+                for (long long j0 = 0; j0 < n; j0 += 64) {
+                    if (j0 + lane < n) {
+                        c.y = y0 + ly;
+                        c.x = x0 + lx;
+                        out_img[(size_t)c.y * W + c.x] = WF::pixel(c, args);
+                    }
+                    ly += q;
+                    lx += rem;
+                    if (lx >= tw) {
+                        lx -= tw;
+                        ++ly;
+                    }
+                }
+            } else {
+                int ncand = 0;
+                long long j0 = 0;
+                while (j0 < n) {
+                    // scan up to kScanBatch passes, all loads first
+                    float v[kScanBatch];
+                    int pos[kScanBatch];
 #pragma unroll
-                    for (int b = 0; b < kStageBatch; ++b) {
-                        const int gy = y0 - R + ly, gx = x0 - R + lx;
-                        v[b] = WF::kOutside;
-                        if (base + b * kT < n && gy >= 0 && gy < H && gx >= 0 && gx < W)
-                            v[b] = in[(size_t)gy * W + gx];
+                    for (int b = 0; b < kScanBatch; ++b) {
+                        // unconditional loads (a lane past the tile's end rereads the
+                        // tile's first pixel and ignores it), so none waits for another
+                        const bool in_tile = j0 + b * 64 + lane < n;
+                        const int yy = in_tile ? y0 + ly : y0, xx = in_tile ? x0 + lx : x0;
+                        v[b] = in[(size_t)yy * W + xx];
+                        pos[b] = in_tile ? ly * tw + lx : -1;
                         ly += q;
                         lx += rem;
-                        if (lx >= pitch) {
-                            lx -= pitch;
+                        if (lx >= tw) {
+                            lx -= tw;
                             ++ly;
                         }
                     }
 #pragma unroll
-                    for (int b = 0; b < kStageBatch; ++b)
-                        if (base + b * kT < n)
-                            sTile[base + b * kT] = v[b];
-                }
-                c.tile = sTile;
-                c.pitch = pitch;
-                __syncthreads();
-            }
-            const long long n = (long long)th * tw;
-            const int q = kT / tw, rem = kT - q * tw;
-            int ly = threadIdx.x / tw, lx = threadIdx.x - ly * tw;
-            for (long long j0 = 0; j0 < n; j0 += kT) {
-                const bool valid = j0 + (long long)threadIdx.x < n;
-                c.y = y0 + ly;
-                c.x = x0 + lx;
-                c.ly = ly + R;
-                c.lx = lx + R;
-                if constexpr (WF::kList) {
-                    SourceRec rec;
-                    const bool hit = valid && WF::find(c, args, rec);
-                    const unsigned long long m = __ballot(hit);
-                    if (m) {
-                        const int lane = __lane_id();
-                        const int leader = __ffsll((long long)m) - 1;
-                        unsigned int base = 0u;
-                        if (lane == leader)
-                            base = atomicAdd(&sN, (unsigned int)__popcll(m));
-                        base = __shfl(base, leader);
+                    for (int b = 0; b < kScanBatch; ++b) {
+                        const bool hit = pos[b] >= 0 && WF::candidate(v[b], args);
+                        const unsigned long long m = __ballot(hit);
                         if (hit)
-                            sRec[base + (unsigned int)__popcll(m & ((1ull << lane) - 1ull))] = rec;
+                            cand[ncand + __popcll(m & ((1ull << lane) - 1ull))] = pos[b];
+                        ncand += __popcll(m);
                     }
-                    __syncthreads();
-                    if (sN > (unsigned int)(kFarmRecords - kT))
-                        flush_records(sRec, &sN, &sBase, out_list, capacity, count);
-                } else {
-                    if (valid)
-                        out_img[(size_t)c.y * W + c.x] = WF::pixel(c, args);
-                }
-                ly += q;
-                lx += rem;
-                if (lx >= tw) {
-                    lx -= tw;
-                    ++ly;
+                    j0 += kScanBatch * 64;
+                    // run the candidates when the list could not take another batch,
+                    // and at the end of the tile
+                    if (ncand > kFarmCandidates - kScanBatch * 64 || j0 >= n) {
+                        for (int i0 = 0; i0 < ncand; i0 += 64) {
+                            SourceRec rec;
+                            bool found = false;
+                            if (i0 + lane < ncand) {
+                                const int p = cand[i0 + lane];
+                                c.y = y0 + p / tw;
+                                c.x = x0 + p % tw;
+                                found = WF::find(c, args, rec);
+                            }
+                            const unsigned long long m = __ballot(found);
+                            if (found)
+                                rbuf[nrec + __popcll(m & ((1ull << lane) - 1ull))] = rec;
+                            nrec += __popcll(m);
+                            if (nrec > kFarmWaveRecords - 64) {
+                                flush_records(rbuf, nrec, out_list, capacity, count);
+                                nrec = 0;
+                            }
+                        }
+                        ncand = 0;
+                    }
                 }
             }
-            __syncthreads();    // the staged tile is reused by the next tile
         }
     }
     if constexpr (WF::kList) {
-        if (sN)
-            flush_records(sRec, &sN, &sBase, out_list, capacity, count);
+        if (nrec)
+            flush_records(rbuf, nrec, out_list, capacity, count);
     }
 }
 
@@ -363,18 +437,14 @@ hipError_t launch_kind(const WorkArgs &args, const float *in, int H, int W, int 
                        int tile_h, int tile_w, float *out_img, SourceRec *out_list,
                        long long capacity, unsigned long long *count, unsigned int *tickets,
                        hipStream_t s) {
-    size_t lds = 0;
-    if (WF::kStaged) {
-        const int R = WF::radius(args);
-        lds = (size_t)(tile_h + 2 * R) * (size_t)(tile_w + 2 * R) * sizeof(float);
-    }
-    // tickets of `chunk` tiles: about 8 per workgroup, so the dynamic balance keeps
-    // a fine grain while the counters take few atomics
+    // tickets of `chunk` tiles: about 8 per wave, so the dynamic balance keeps a fine
+    // grain while the counters take few atomics
     const long long ntiles = (long long)((W - 1) / tile_w + 1) * ((H - 1) / tile_h + 1);
     long long chunk = ntiles / ((long long)workers * 8);
     chunk = chunk < 1 ? 1 : (chunk > 64 ? 64 : chunk);
-    k_farm<WF><<<workers, 256, lds, s>>>(in, H, W, args, tile_h, tile_w, (int)chunk, out_img,
-                                        out_list, capacity, count, tickets);
+    const int blocks = (workers + 3) / 4;
+    k_farm<WF><<<blocks, 256, 0, s>>>(in, H, W, args, tile_h, tile_w, (int)chunk, workers,
+                                      out_img, out_list, capacity, count, tickets);
     return hipGetLastError();
 }
 
@@ -391,14 +461,6 @@ int work_radius(int kind, const WorkArgs &a, int niter) {
     default:
         return -1;
     }
-}
-
-size_t farm_lds_bytes(int kind, const WorkArgs &a, int tile_h, int tile_w) {
-    if (kind != kWorkSources)
-        return 0;
-    const int R = WorkSources::radius(a);
-    return (size_t)(tile_h + 2 * R) * (size_t)(tile_w + 2 * R) * sizeof(float) +
-           kFarmRecords * sizeof(SourceRec);
 }
 
 hipError_t launch_farm_reset(unsigned int *tickets, unsigned long long *count, hipStream_t s) {

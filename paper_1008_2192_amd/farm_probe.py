@@ -3,8 +3,8 @@
 The paper measures CRBLASTER's efficiency on 1..57 TILE64 tiles with two work
 functions of near-uniform per-pixel cost and no border (Section 6.3.2: POISSON on a
 750x750 image of 24.3; Section 6.3.3: WAITER on a 750x750 image of 137, i.e. 137 us
-per pixel).  Here the actors are workgroups of a persistent farm pulling bands of
-rows from an atomic ticket; speedup S_n = t_1 / t_n and efficiency S_n / n.
+per pixel).  Here the actors are the waves of a persistent farm pulling bands of
+rows from atomic tickets; speedup S_n = t_1 / t_n and efficiency S_n / n.
 
   python -m paper_1008_2192_amd.farm_probe [--band-rows 1]
 """
@@ -17,7 +17,7 @@ import torch
 
 from . import _lib
 
-WORKERS = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048]
+WORKERS = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096]
 
 
 def time_run(kind, x, workers, band_rows, reps=3):
@@ -58,8 +58,8 @@ def main():
     if a.json:
         print(json.dumps(rows))
         return
-    print(f"750x750 images, bands of {a.band_rows} row(s), 256-thread workgroups")
-    print("| workers | POISSON ms | POISSON efficiency | WAITER ms | WAITER efficiency |")
+    print(f"750x750 images, bands of {a.band_rows} row(s), one wave (64 lanes) per actor")
+    print("| actors | POISSON ms | POISSON efficiency | WAITER ms | WAITER efficiency |")
     print("|---|---|---|---|---|")
     for n in WORKERS:
         p = next(r for r in rows if r["work"] == "POISSON" and r["workers"] == n)

@@ -7,9 +7,9 @@ its roofline is HBM bandwidth: algorithmic bytes per launch = 4 B x pixels +
 40 B x sources.  The probe times the farm on the crowded 4096 x 4096 field (20,000
 stars, 1.5% cosmic-ray coverage; peaks 5 sigma above the sky, r = 2, 7 x 7
 apertures) and on that field tiled 4 x 4 into a 16384 x 16384 frame (1 GiB), over
-tile shapes and worker counts, with HIP events on the launch stream.
+tile shapes and actor counts (waves), with HIP events on the launch stream.
 
-  python -m paper_1008_2192_amd.sources_probe [--json] [--tile 32x64] [--workers 2048]
+  python -m paper_1008_2192_amd.sources_probe [--json] [--tile 32x64] [--workers 4096]
                                                [--frame 16384x16384]
 """
 from __future__ import annotations
@@ -24,7 +24,7 @@ from . import _lib, synth
 
 HBM_PEAK_GBS = 8000.0
 TILES = [(16, 64), (32, 64), (64, 64), (32, 128), (8, 256)]
-WORKERS = [256, 1024, 2048, 4096, 8192]
+WORKERS = [1024, 2048, 4096, 8192, 16384]
 
 
 def field():

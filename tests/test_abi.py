@@ -138,6 +138,7 @@ def test_farm_argument_validation(L):
     assert run(b(poi), x, 0, 8, 4, 8, 8, img, None, 0, None) == -1
     assert run(b(poi), x, 65536, 65536, 4, 8, 8, img, None, 0, None) == -4
     assert run(b(poi), x, 8, 8, 0, 8, 8, img, None, 0, None) == -1
+    assert run(b(poi), x, 8, 8, (1 << 22) + 1, 8, 8, img, None, 0, None) == -1
     assert run(b(poi), x, 8, 8, 4, 0, 8, img, None, 0, None) == -1
     assert run(b(poi), x, 8, 8, 4, 8, 8, None, None, 0, None) == -1
     assert run(b(poi), x, 8, 8, 4, 8, 8, img, lst, 4, cnt) == -1
@@ -147,7 +148,6 @@ def test_farm_argument_validation(L):
     assert run(b(src), x, 8, 8, 4, 8, 8, None, lst, 4, ctypes.c_void_p((1 << 43) + 4)) == -1
     assert run(b(src), x, 8, 8, 4, 8, 8, None, None, 4, cnt) == -1     # capacity, no list
     assert run(b(src), x, 8, 8, 4, 8, 8, None, lst, -1, cnt) == -1
-    assert run(b(src), x, 8, 8, 4, 200, 200, None, lst, 4, cnt) == -1  # staged tile > 64 KiB
     assert run(b(src), x, 8, 8, 4, 8, 8, None, x, 4, cnt) == -1        # list overlaps frame
     assert L.crb_work_run(_lib.CRB_WORK_SOURCES, x, 8, 8, 0, 4, 1, img) == -1
     assert L.crb_lacosmic_partitioned(x, 64, 64, 1.0, 5.0, 0.0, 4.5, 0.3, 4.0, 4, 2, 2, -2,
