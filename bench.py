@@ -67,7 +67,7 @@ def describe(name, frames):
             "frames": 1, "pixels": px, "niter": 4}
 
 
-KERNEL_SOURCES = ("csrc/kernels.hip", "csrc/kernels.h", "csrc/medtile.inc")
+KERNEL_SOURCES = ("csrc/detect.hip", "csrc/device_common.h", "csrc/kernels.h", "csrc/medtile.inc")
 COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_detect_batch64_counters.md")
 
 

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libcrb.so")
-SOURCES = ["kernels.hip", "farm.hip", "api.hip", "server.hip"]
+SOURCES = ["detect.hip", "kernels.hip", "farm.hip", "api.hip", "server.hip"]
 ARCH = os.environ.get("CRB_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

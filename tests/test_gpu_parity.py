@@ -198,6 +198,36 @@ def test_end_to_end_small(early_stop):
         compare_end_to_end(f, clean, mask, r)
 
 
+EXTREMES = [
+    dict(sigclip=1.5),                       # many hot pixels: a dense work set
+    dict(sigclip=50.0),                      # none
+    dict(sigfrac=0.0), dict(sigfrac=1.0),
+    dict(objlim=0.01), dict(objlim=1e4),
+    dict(readnoise=0.0, sky=-300.0),         # m <= 0 everywhere: the 1e-4 noise floor
+    dict(readnoise=0.0, sky=0.0),
+    dict(gain=0.05), dict(gain=50.0),
+    dict(niter=1), dict(niter=2), dict(niter=7),
+]
+
+
+@pytest.mark.parametrize("over", EXTREMES, ids=[",".join(f"{k}={v}" for k, v in o.items())
+                                               for o in EXTREMES])
+def test_parameter_extremes(over):
+    frames = [synth.c1_density_frame(97, 130, 91, 2.0, 5.0)]
+    neg = synth.c1_density_frame(70, 90, 92, 1.0, 4.0)
+    neg.img = (neg.img - np.float32(100.0)).astype(np.float32)     # sky-subtracted frame
+    frames.append(neg)
+    for f in frames:
+        p = fparams(f)
+        niter = over.get("niter", 4)
+        p.update({k: f32(v) for k, v in over.items() if k != "niter"})
+        img = torch.from_numpy(f.img).to(DEV)
+        clean, mask = _lib.lacosmic(img, niter=niter, early_stop=False, **p)
+        torch.cuda.synchronize()
+        r = ref.lacosmic(f.img, niter=niter, early_stop=False, **p)
+        compare_end_to_end(f, clean, mask, r)
+
+
 def test_niter_zero_constant_and_in_place():
     f = synth.c1()
     img = torch.from_numpy(f.img).to(DEV)
