@@ -290,23 +290,32 @@ __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ 
 // replacement
 // ---------------------------------------------------------------------------
 
-// Unflagged pixels are never written and flagged ones are never read as values, so
-// the update in place is race-free within the launch.
+// Unflagged pixels are never written and flagged ones are never used as values, so
+// the update in place is correct within the launch.  All 25 mask bytes and all 25 J
+// values of the window are loaded unconditionally (clamped addresses are always
+// valid), so the 50 loads are in flight together; a flagged neighbour's J may be
+// rewritten meanwhile by another thread, and that value is discarded.
 __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p) {
     const int W = f.W, H = f.H;
     const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * (uint32_t)W);
     float v[25];
-    int cnt = 0;
+    uint8_t mk[25];
 #pragma unroll
     for (int dy = -2; dy <= 2; ++dy) {
         const size_t row = (size_t)clampi(y + dy, H) * W;
 #pragma unroll
         for (int dx = -2; dx <= 2; ++dx) {
             const size_t q = row + clampi(x + dx, W);
-            const bool m = f.mask[q] != 0;
-            v[(dy + 2) * 5 + dx + 2] = m ? INFINITY : f.J[q];
-            cnt += m ? 0 : 1;
+            mk[(dy + 2) * 5 + dx + 2] = f.mask[q];
+            v[(dy + 2) * 5 + dx + 2] = f.J[q];
         }
+    }
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < 25; ++j) {
+        const bool m = mk[j] != 0;
+        v[j] = m ? INFINITY : v[j];
+        cnt += m ? 0 : 1;
     }
     if (cnt == 0)
         return;
