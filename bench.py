@@ -301,9 +301,11 @@ def main():
     ops_launch = roofline.detect_ops_per_launch(total_px, work_px, contrast)
     achieved = ops_launch / det_avg_s                      # lane-ops per second
     o = roofline.detect_ops()
-    roof = {"bound": "alu", "kernel": "k_detect (detection: med3 and med5 networks, L+, N, S "
-                                      "everywhere; med5(S), S' and the threshold bits on the "
-                                      "work set; med7 and F^ where S' > sigclip)",
+    roof = {"bound": "alu", "kernel": "k_detect (detection: med3 and med5 networks, L+ and an "
+                                      "FP32 estimate of S with its error bound everywhere; "
+                                      "med5(S), S' and the threshold bits on the work set; med7 "
+                                      "and F^ where S' > sigclip; binary64 re-evaluation where "
+                                      "the bound cannot decide)",
             "achieved": round(achieved / 1e12, 3), "peak": round(roofline.ALU_PEAK / 1e12, 3),
             "unit": "Tlane-op/s", "frac": round(achieved / roofline.ALU_PEAK, 4),
             "traffic": profiled_traffic() if args.workload == "c4" else None,
@@ -313,6 +315,7 @@ def main():
             "ops_per_work_pixel": round(o["per_work_pixel"], 2),
             "ops_per_contrast_test": round(o["per_contrast"], 2),
             "work_pixels_per_launch": round(work_px), "contrast_tests_per_launch": round(contrast),
+            "reevaluated_per_launch": round(work["reevaluated"] / 4.0, 2),
             "pixels_per_launch": total_px, "avg_launch_ms": round(det_avg_s * 1e3, 4),
             "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}}
 

@@ -133,13 +133,17 @@ crb_status crb_plan_set_timing(crb_plan *plan, int32_t enable);
 crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
 /* Work counters of the detection kernel (for roofline accounting).  The detection
  * evaluates med5(S), S' and the threshold bits only on its work set, the pixels
- * within 2 of a pixel with S > sigclip whose own S exceeds sigfrac * sigclip, and the
- * fine-structure contrast (med7 of med3, F^, S'/F^) only where S' > sigclip.  With
- * counting enabled every detection launch adds, per frame, the size of its work set
- * and its number of contrast tests; crb_plan_set_counting (which waits for the
+ * within 2 of a pixel with S > sigclip whose own S exceeds sigfrac * sigclip (taken
+ * from an FP32 estimate of S widened by its error bound, so the set can hold a few
+ * more pixels), and the fine-structure contrast (med7 of med3, F^, S'/F^) only where
+ * S' > sigclip.  A work-set pixel whose S' interval from the estimate straddles a
+ * threshold is re-evaluated in binary64 from J.  With counting enabled every
+ * detection launch adds, per frame, the size of its work set, its number of contrast
+ * tests and its number of re-evaluations; crb_plan_set_counting (which waits for the
  * plan's stream) clears the counters, crb_plan_work_counts waits for the stream and
  * returns the totals over all frames since then: counts[0] work-set pixels,
- * counts[1] contrast tests. */
+ * counts[1] contrast tests, counts[2] binary64 re-evaluations (counts has 3
+ * elements). */
 crb_status crb_plan_set_counting(crb_plan *plan, int32_t enable);
 crb_status crb_plan_work_counts(crb_plan *plan, int64_t *counts);
 
@@ -298,11 +302,22 @@ crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_fr
                              uint8_t *out_G2, uint8_t *out_M, float *out_J_next,
                              int64_t *out_n_new);
 /* Detection stage only: code = A | [S' > sigclip] << 1 | [S' > sigfrac sigclip] << 2
- * on the pixels within distance 2 (8-connected) of a pixel with S > sigclip, 0
- * elsewhere.  The grow reads a code only through its two 3x3 dilations of A, and A
- * lies inside {S' > sigclip}, which lies inside {S > sigclip}; so the codes equal the
- * full definition wherever they can change G1 or G2. */
+ * on the pixels within distance 2 (8-connected) of a pixel with S > sigclip; elsewhere
+ * either 0 or that same code (the detection's work set may hold a few more pixels,
+ * see crb_plan_work_counts).  The grow reads a code only through its two 3x3
+ * dilations of A, and A lies inside {S' > sigclip}, which lies inside {S > sigclip};
+ * so the codes equal the full definition wherever they can change G1 or G2. */
 crb_status crb_debug_detect(const float *J, const crb_frame *params, uint8_t *out_codes);
+/* As crb_debug_detect, with S' of every work-set pixel evaluated in binary64 from J
+ * (the path the detection takes where the FP32 estimate cannot decide). */
+crb_status crb_debug_detect_exact(const float *J, const crb_frame *params,
+                                  uint8_t *out_codes);
+/* The detection's FP32 estimate of S (Section 5: S = L+ / (2N)) and its error bound
+ * at every pixel of J (device pointers, H x W each, no overlap): |out_s - S| <=
+ * out_err, S being the binary64 value; out_s = out_err = +inf where the bound is not
+ * established (then the detection decides in binary64). */
+crb_status crb_debug_s_estimate(const float *J, const crb_frame *params, float *out_s,
+                                float *out_err);
 /* Clamped (2r+1)^2 median filter, r in {1, 2, 3}, by the kernels' networks (3x3 by
  * sorted columns, 5x5 by the 2 x 5 output network, 7x7 by the single-output one). */
 crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out);

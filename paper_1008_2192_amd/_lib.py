@@ -26,7 +26,8 @@ EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned", "
            "crb_server_create", "crb_server_submit", "crb_server_poll", "crb_server_pending",
            "crb_server_destroy", "crb_debug_iterate", "crb_debug_detect", "crb_debug_median",
            "crb_debug_fp64", "crb_work_run", "crb_work_radius", "crb_farm_run",
-           "crb_plan_set_counting", "crb_plan_work_counts", "crb_debug_median5_f64"]
+           "crb_plan_set_counting", "crb_plan_work_counts", "crb_debug_median5_f64",
+           "crb_debug_detect_exact", "crb_debug_s_estimate"]
 CRB_WORK_LACOSMIC = 0
 CRB_WORK_POISSON = 1
 CRB_WORK_WAITER = 2
@@ -107,6 +108,8 @@ def lib():
     L.crb_server_destroy.restype = None
     L.crb_debug_iterate.argtypes = [vp, vp, ctypes.POINTER(Frame), vp, vp, vp, vp]
     L.crb_debug_detect.argtypes = [vp, ctypes.POINTER(Frame), vp]
+    L.crb_debug_detect_exact.argtypes = [vp, ctypes.POINTER(Frame), vp]
+    L.crb_debug_s_estimate.argtypes = [vp, ctypes.POINTER(Frame), vp, vp]
     L.crb_debug_median.argtypes = [vp, i32, i32, i32, vp]
     L.crb_debug_fp64.argtypes = [vp, vp, i32, vp, vp]
     L.crb_work_run.argtypes = [i32, vp, i32, i32, ctypes.c_uint64, i32, i32, vp]
@@ -119,7 +122,7 @@ def lib():
                  "crb_server_create", "crb_server_submit", "crb_server_poll",
                  "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64",
                  "crb_work_run", "crb_farm_run", "crb_plan_set_counting", "crb_plan_work_counts",
-                 "crb_debug_median5_f64"):
+                 "crb_debug_median5_f64", "crb_debug_detect_exact", "crb_debug_s_estimate"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -251,10 +254,11 @@ class Plan:
 
     def work_counts(self) -> dict:
         """Detection work since counting was enabled: work-set pixels (med5 of S and
-        the threshold bits) and contrast tests (med7 of med3 and F^)."""
-        c = (ctypes.c_int64 * 2)()
+        the threshold bits), contrast tests (med7 of med3 and F^) and binary64
+        re-evaluations (work-set pixels the FP32 estimate of S could not decide)."""
+        c = (ctypes.c_int64 * 3)()
         check("crb_plan_work_counts", lib().crb_plan_work_counts(self.handle, c))
-        return dict(work_pixels=int(c[0]), contrast_tests=int(c[1]))
+        return dict(work_pixels=int(c[0]), contrast_tests=int(c[1]), reevaluated=int(c[2]))
 
     def close(self) -> None:
         if self.handle:
@@ -295,15 +299,31 @@ def debug_iterate(J: torch.Tensor, M_prev: torch.Tensor, gain, readnoise, sky=0.
 
 
 def debug_detect(J: torch.Tensor, gain, readnoise, sky=0.0, sigclip=4.5, sigfrac=0.3,
-                 objlim=4.0, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+                 objlim=4.0, exact: bool = False,
+                 stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Detection codes (crb_debug_detect; crb_debug_detect_exact with exact=True)."""
     _dev2d(J, torch.float32, "J")
     H, W = J.shape
     codes = torch.empty((H, W), dtype=torch.uint8, device=J.device)
     p = _params_frame(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim)
     set_stream(stream)
-    check("crb_debug_detect", lib().crb_debug_detect(J.data_ptr(), ctypes.byref(p),
-                                                     codes.data_ptr()))
+    name = "crb_debug_detect_exact" if exact else "crb_debug_detect"
+    check(name, getattr(lib(), name)(J.data_ptr(), ctypes.byref(p), codes.data_ptr()))
     return codes
+
+
+def debug_s_estimate(J: torch.Tensor, gain, readnoise, sky=0.0, sigclip=4.5, sigfrac=0.3,
+                     objlim=4.0, stream: Optional[torch.cuda.Stream] = None):
+    """The detection's FP32 estimate of S and its error bound (crb_debug_s_estimate)."""
+    _dev2d(J, torch.float32, "J")
+    H, W = J.shape
+    s = torch.empty((H, W), dtype=torch.float32, device=J.device)
+    err = torch.empty_like(s)
+    p = _params_frame(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim)
+    set_stream(stream)
+    check("crb_debug_s_estimate", lib().crb_debug_s_estimate(J.data_ptr(), ctypes.byref(p),
+                                                             s.data_ptr(), err.data_ptr()))
+    return s, err
 
 
 def debug_median(x: torch.Tensor, r: int, stream: Optional[torch.cuda.Stream] = None

@@ -445,7 +445,8 @@ crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_fr
     return ok();
 }
 
-crb_status crb_debug_detect(const float *J, const crb_frame *p, uint8_t *out_codes) {
+static crb_status debug_detect(const float *J, const crb_frame *p, uint8_t *out_codes,
+                               int flags) {
     if (!p || !J || !out_codes)
         return fail(CRB_EINVAL, "null pointer");
     crb_status st = check_frame_args(p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
@@ -454,7 +455,7 @@ crb_status crb_debug_detect(const float *J, const crb_frame *p, uint8_t *out_cod
         return st;
     DevFrame f = make_devframe(J, const_cast<float *>(J), nullptr, nullptr, ws_layout(1, 1),
                                p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
-                               p->sigfrac, p->objlim, 1, kNoEarlyStop);
+                               p->sigfrac, p->objlim, 1, kNoEarlyStop | flags);
     f.codes = out_codes;
     f.nnew = nullptr;
     f.listlen = nullptr;
@@ -463,6 +464,33 @@ crb_status crb_debug_detect(const float *J, const crb_frame *p, uint8_t *out_cod
                    CRB_OK
                ? ok()
                : CRB_EDEVICE;
+}
+
+crb_status crb_debug_detect(const float *J, const crb_frame *p, uint8_t *out_codes) {
+    return debug_detect(J, p, out_codes, 0);
+}
+
+crb_status crb_debug_detect_exact(const float *J, const crb_frame *p, uint8_t *out_codes) {
+    return debug_detect(J, p, out_codes, kExactDetect);
+}
+
+crb_status crb_debug_s_estimate(const float *J, const crb_frame *p, float *out_s,
+                                float *out_err) {
+    if (!p || !J || !out_s || !out_err)
+        return fail(CRB_EINVAL, "null pointer");
+    crb_status st = check_frame_args(p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
+                                     p->sigfrac, p->objlim, 1);
+    if (st != CRB_OK)
+        return st;
+    const size_t bytes = (size_t)p->H * (size_t)p->W * 4;
+    if (ranges_overlap(out_s, bytes, out_err, bytes) || ranges_overlap(J, bytes, out_s, bytes) ||
+        ranges_overlap(J, bytes, out_err, bytes))
+        return fail(CRB_EINVAL, "buffers overlap");
+    DevFrame f = make_devframe(J, const_cast<float *>(J), nullptr, nullptr, ws_layout(1, 1),
+                               p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
+                               p->sigfrac, p->objlim, 1, kNoEarlyStop);
+    st = hip_status(launch_debug_s_estimate(f, out_s, out_err, t_stream), "kernel launch");
+    return st == CRB_OK ? ok() : st;
 }
 
 crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out) {
@@ -521,7 +549,7 @@ struct crb_plan {
     int ntgrow = 0;
     long long *d_stats = nullptr;
     unsigned int *d_prefix = nullptr;   // flat offsets of the frames' flagged lists
-    unsigned long long *d_work = nullptr;   // per frame: work-set pixels, contrast tests
+    unsigned long long *d_work = nullptr;   // per frame: kWorkCounters detection counters
     std::vector<DevFrame> hframes;      // host copy of the frame table
     bool counting = false;
     int rgrid = 1;
@@ -662,7 +690,8 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     const size_t o_stats = o_tgrow + ((ntgrow * sizeof(TileRef) + 255) / 256) * 256;
     const size_t o_prefix = o_stats + ((2 * n * sizeof(long long) + 255) / 256) * 256;
     const size_t o_work = o_prefix + (((n + 1) * sizeof(unsigned int) + 255) / 256) * 256;
-    const size_t bytes = o_work + ((2 * n * sizeof(unsigned long long) + 255) / 256) * 256;
+    const size_t bytes =
+        o_work + ((kWorkCounters * n * sizeof(unsigned long long) + 255) / 256) * 256;
 
     crb_plan *p = new (std::nothrow) crb_plan();
     if (!p)
@@ -710,7 +739,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
                               f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac, f.objlim,
                               f.niter,
                               (f.flags & CRB_FLAG_NO_EARLY_STOP ? kNoEarlyStop : 0) | kFreshMask);
-        hf[i].work = p->d_work + 2 * (size_t)i;
+        hf[i].work = p->d_work + kWorkCounters * (size_t)i;
         for (int y = 0; y < f.H; y += kDetectTY)
             for (int x = 0; x < f.W; x += kDetectTX)
                 td.push_back(TileRef{i, y, x, 0});
@@ -725,7 +754,8 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     e = hipMemcpyAsync(p->d_frames, hf.data(), n * sizeof(DevFrame), hipMemcpyHostToDevice,
                        p->stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(p->d_work, 0, 2 * (size_t)n * sizeof(unsigned long long), p->stream);
+        e = hipMemsetAsync(p->d_work, 0, kWorkCounters * (size_t)n * sizeof(unsigned long long),
+                           p->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->d_tdet, td.data(), td.size() * sizeof(TileRef),
                            hipMemcpyHostToDevice, p->stream);
@@ -819,8 +849,8 @@ crb_status crb_plan_set_counting(crb_plan *p, int32_t enable) {
         e = hipMemcpyAsync(p->d_frames, p->hframes.data(), p->hframes.size() * sizeof(DevFrame),
                            hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(p->d_work, 0, 2 * (size_t)p->n * sizeof(unsigned long long),
-                           p->stream);
+        e = hipMemsetAsync(p->d_work, 0,
+                           kWorkCounters * (size_t)p->n * sizeof(unsigned long long), p->stream);
     if (e == hipSuccess)
         e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess)
@@ -832,18 +862,18 @@ crb_status crb_plan_set_counting(crb_plan *p, int32_t enable) {
 crb_status crb_plan_work_counts(crb_plan *p, int64_t *counts) {
     if (!p || !counts)
         return fail(CRB_EINVAL, "null argument");
-    std::vector<unsigned long long> w(2 * (size_t)p->n);
+    std::vector<unsigned long long> w(kWorkCounters * (size_t)p->n);
     hipError_t e = hipStreamSynchronize(p->stream);
     if (e == hipSuccess)
         e = hipMemcpy(w.data(), p->d_work, w.size() * sizeof(unsigned long long),
                       hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return hip_status(e, "counter copy");
-    counts[0] = counts[1] = 0;
-    for (int i = 0; i < p->n; ++i) {
-        counts[0] += (int64_t)w[2 * (size_t)i];
-        counts[1] += (int64_t)w[2 * (size_t)i + 1];
-    }
+    for (int c = 0; c < kWorkCounters; ++c)
+        counts[c] = 0;
+    for (int i = 0; i < p->n; ++i)
+        for (int c = 0; c < kWorkCounters; ++c)
+            counts[c] += (int64_t)w[kWorkCounters * (size_t)i + c];
     return ok();
 }
 

@@ -5,10 +5,12 @@
 // tiles with the halo each quantity needs, plus the parity-test kernels of its median
 // networks.
 //
-// Numerics: medians are exact selections by min/max networks on FP32 (J, med3) or
-// binary64 (S).  The statistics are binary64, evaluated in the same operation order
-// as the plain definition (no contraction: built with -ffp-contract=off), so a
-// decision on a given J is independent of the tiling and of the launch shape.
+// Numerics: medians are exact selections by min/max networks.  Every decision (a
+// threshold bit, the contrast test) is the one the binary64 definition takes: S is
+// estimated in FP32 with a proven error bound, a decision is taken from the estimate
+// only when the bound settles it, and otherwise from binary64 statistics evaluated in
+// the definition's operation order (no contraction: built with -ffp-contract=off).
+// So the codes for a given J are independent of the tiling and of the launch shape.
 #include "kernels.h"
 #include "device_common.h"
 
@@ -58,10 +60,139 @@ __device__ __forceinline__ double lplus(double c, double u, double d, double l, 
 // detection
 // ---------------------------------------------------------------------------
 
+// FP32 parameters of the S estimate; ok is false for gains outside [2^-100, 2^100]
+// (where g/8 could round), which leaves every decision to the binary64 evaluation.
+struct SEstParams {
+    float gain, g8, sky, rn2;
+    bool ok;
+};
+
+__device__ __forceinline__ SEstParams sest_params(const DevFrame &f) {
+    SEstParams p;
+    p.gain = f.gain;
+    p.g8 = f.gain * 0.125f;
+    p.sky = f.sky;
+    p.rn2 = f.readnoise * f.readnoise;
+    p.ok = f.gain >= 0x1p-100f && f.gain <= 0x1p100f;
+    return p;
+}
+
+// FP32 estimate s of S at a pixel of value c with 4-neighbours up, dn, lf, rt and
+// med5(J) = m5, and a bound err >= |s - S|, S being the binary64 value of the
+// definition (S = L+ / (2N), L+ = a quarter of the sum over the four sub-pixels of
+// max(2c - v1 - v2, 0), N = sqrt(g m + rn^2) / g).  Error analysis, u = 2^-24,
+// round to nearest with FP32 denormals preserved, M = 4|c| + |up| + |dn| + |lf| + |rt|:
+//   the sub-pixel sum l4 (two roundings per term, three in the sum) is 4 L+ within
+//     10.1 u M;
+//   t = g m + rn^2 (positive terms, m itself rounded once) carries at most 3.03 u
+//     relative error; the reciprocal square root (v_rsq_f32, within 1 ulp), the
+//     scaling by g/8 (exact) and the product with l4 add at most 2u + 2u;
+//   the binary64 evaluation is within 2^-49 (M R + S) of the exact value;
+// so |s - S| <= 10.3 u M R + 7 u s with R = g/(8 sqrt t), which err = 2^-18 (M R + s)
+// overstates six-fold.  Outside t in [2^-100, 2^100] and M <= 2^100 (where the
+// analysis has no overflow, underflow or domain edge) s = err = +inf, which sends every
+// decision that reads the pixel to the binary64 evaluation.
+__device__ __forceinline__ float s_estimate(float c, float up, float dn, float lf, float rt,
+                                            float m5, const SEstParams &p, float &err) {
+    const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
+    const float l4 = (fmaxf(a - lf, 0.0f) + fmaxf(a - rt, 0.0f)) +
+                     (fmaxf(b - lf, 0.0f) + fmaxf(b - rt, 0.0f));
+    float m = m5 + p.sky;
+    m = (m <= 0.0f) ? 1e-4f : m;
+    const float t = fmaf(p.gain, m, p.rn2);
+    const float R = p.g8 * __builtin_amdgcn_rsqf(t);
+    const float s = l4 * R;
+    const float M = fmaf(4.0f, fabsf(c), fabsf(up)) + fabsf(dn) + (fabsf(lf) + fabsf(rt));
+    const bool sane = __builtin_amdgcn_fmed3f(t, 0x1p-100f, 0x1p100f) == t && M <= 0x1p100f && p.ok;
+    err = sane ? (M * R + s) * 0x1p-18f : INFINITY;
+    return sane ? s : INFINITY;
+}
+
+// S exactly as the definition evaluates it (binary64, in its operation order), at the
+// pixel whose staged-J cell is p (the staged J holds clamped values beyond the frame).
+__device__ __forceinline__ double s_exact(const float *p, int pitch, double gain, double sky,
+                                          double rn2) {
+    float w[25], m5[1];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            w[i * 5 + j] = p[(i - 2) * pitch + (j - 2)];
+    med5_t1x1(w, m5);
+    const double lp = lplus(w[12], w[7], w[17], w[11], w[13]);
+    double m = (double)m5[0] + sky;
+    if (m <= 0.0)
+        m = 1e-4;
+    const double N = sqrt(gain * m + rn2) / gain;
+    return lp / (2.0 * N);
+}
+
+// F^ = max((med3 - med7(med3)) / N, 0.01) at a tile pixel: pj is its staged-J cell,
+// pm its med3 cell; N from med5(J) as in S.
+__device__ __forceinline__ double fine_structure(const float *pj, int jpitch, const float *pm,
+                                                 int mpitch, double gain, double sky,
+                                                 double rn2) {
+    float w[25], m5[1];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            w[i * 5 + j] = pj[(i - 2) * jpitch + (j - 2)];
+    med5_t1x1(w, m5);
+    double m = (double)m5[0] + sky;
+    if (m <= 0.0)
+        m = 1e-4;
+    const double N = sqrt(gain * m + rn2) / gain;
+    float w7[49], m7[1];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            w7[i * 7 + j] = pm[(i - 3) * mpitch + (j - 3)];
+    med7_t1x1(w7, m7);
+    double fh = ((double)w7[24] - (double)m7[0]) / N;
+    return fh < 0.01 ? 0.01 : fh;
+}
+
+// Wave 0: exclusive prefix sums of the set-bit counts of 64 bitmap words (one per
+// lane) into pre[0..63], the total into pre[64].
+__device__ __forceinline__ void bitmap_prefix64(const uint32_t *bits, uint32_t *pre) {
+    const int lane = threadIdx.x;
+    const int c = __popc(bits[lane]);
+    int v = c;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int u = __shfl_up(v, off);
+        if (lane >= off)
+            v += u;
+    }
+    pre[lane] = (uint32_t)(v - c);
+    if (lane == 63)
+        pre[64] = (uint32_t)v;
+}
+
+// Position (word * 32 + bit) of the q-th set bit of a 64-word bitmap with prefix pre.
+__device__ __forceinline__ int bitmap_select64(const uint32_t *bits, const uint32_t *pre, int q) {
+    int lo = 0, hi = 63;    // last word whose prefix is <= q
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int)pre[mid] <= q)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    uint32_t b = bits[lo];
+    for (int n = q - (int)pre[lo]; n > 0; --n)
+        b &= b - 1u;
+    return lo * 32 + __ffs(b) - 1;
+}
+
 // Work shapes inside a detection block: med3 in runs of kRun3 outputs; med5(J) with
-// L+, N, S in 2 x 5 thread tiles over the whole tile and its 2-pixel apron.  The
-// remaining statistics are evaluated only where a code bit can matter (below).
+// L+ and the S estimate in 2 x 5 thread tiles over the whole tile and its 2-pixel
+// apron.  The remaining statistics are evaluated only where a code bit can matter.
 constexpr int kRun3 = 14;
+// pixels per round of the binary64 re-evaluation (25 threads each)
+constexpr int kExactBatch = kThreads / 25;
 
 template <int TY, int TX>
 struct DetectLayout {
@@ -69,15 +200,13 @@ struct DetectLayout {
     // stage-1 and stage-2 scalar accesses over the LDS banks
     static constexpr int JH = TY + 8, JW = TX + 8, JWP = TX + 11;   // J, apron 4
     static constexpr int MH = TY + 6, MW = TX + 6, MWP = TX + 12;   // med3(J), apron 3
-    static constexpr int SH = TY + 4, SW = TX + 4, SWP = TX + 6;    // S (binary64), apron 2
-    static constexpr int HW = (SW + 31) / 32;   // words per row of the S > sigclip bitmap
-    static constexpr int QW = TX / 32;          // words per row of the work bitmap
-    // after stage 2 the J buffer holds the code tile, the work bitmap and its prefix
-    static constexpr int kCodeWords = TY * TX / 4;
-    static constexpr int kWorkWords = TY * QW;
-    static_assert(TX % 32 == 0 && kWorkWords == 64, "one wave builds the work bitmap");
+    static constexpr int SH = TY + 4, SW = TX + 4, SWP = TX + 6;    // S estimate, apron 2
+    static constexpr int HW = (SW + 31) / 32;   // words per row of the hot bitmap
+    static constexpr int QW = TX / 32;          // words per row of the tile bitmaps
+    static constexpr int kTileWords = TY * QW;
+    static_assert(TX % 32 == 0 && kTileWords == 64, "one wave scans a tile bitmap");
     static_assert(QW + 1 <= HW, "dilation reads two bitmap words per work word");
-    static_assert(JH * JWP >= kCodeWords + 2 * kWorkWords + 1, "J buffer reuse");
+    static_assert(SH * SWP * 4 >= kExactBatch * 25 * 8, "re-evaluation buffer in the S plane");
 };
 
 // Which pixels need S', F^ and the threshold bits.  With H = {S > sigclip} (S' > t
@@ -85,25 +214,30 @@ struct DetectLayout {
 //   first(p) can be 1 only on H;
 //   G1(p) needs an A pixel within distance 1, so hi(p) matters only on D1(H);
 //   G2(p) needs a G1 pixel within distance 1, so lo(p) matters only on D2(H);
-// and lo(p) = hi(p) = 0 wherever S(p) <= sigfrac * sigclip (sigfrac <= 1).  The
-// block therefore evaluates med5(S) and the bits on Q = D2(H) & {S > sigfrac*sigclip}
-// (the work set), med7(med3) and the contrast test on Q & {S' > sigclip}, and writes
-// code 0 elsewhere; the codes agree with the full definition wherever the grow reads
-// them through its two dilations.
+// and lo(p) = hi(p) = 0 wherever S(p) <= sigfrac * sigclip (sigfrac <= 1).  The block
+// computes the FP32 estimate s of S with its error bound on the tile and its apron,
+// H' = {s + err > sigclip (less a margin)} (a superset of H), and evaluates the codes on
+// Q' = D2(H') & {s + max err > sigfrac * sigclip (less a margin)}, a superset of
+// Q = D2(H) & {S > sigfrac*sigclip}: med5 of the estimates gives S' within twice the
+// block's largest error (the median moves no more than its inputs), which decides the
+// two bits, and F^ (binary64) with the interval of S' decides the contrast test; a
+// pixel where an interval straddles a threshold is re-evaluated in binary64 from J.  So
+// every code written is the full definition's, codes outside Q' are 0, and the grow,
+// which reads codes only through its two dilations, sees the full definition.
 template <int TY, int TX>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
               DevFrame single, int kiter) {
     using L = DetectLayout<TY, TX>;
-    __shared__ __align__(16) float sJ[L::JH * L::JWP];     // J, later codes + work bitmap
+    __shared__ __align__(16) float sJ[L::JH * L::JWP];
     __shared__ __align__(16) float sM3[L::MH * L::MWP];
-    __shared__ __align__(16) double sS[L::SH * L::SWP];
-    __shared__ float sM5[TY * TX];                          // med5(J) at the outputs
-    __shared__ uint32_t sHot[L::SH * L::HW];                // S > sigclip, apron 2, in-frame
-    __shared__ unsigned int sContrast;                      // contrast tests (work counting)
-    uint8_t *const sCode = reinterpret_cast<uint8_t *>(sJ);
-    uint32_t *const sQ = reinterpret_cast<uint32_t *>(sJ) + L::kCodeWords;
-    uint32_t *const sQpre = sQ + L::kWorkWords;
+    __shared__ __align__(16) float sS[L::SH * L::SWP];      // later: re-evaluation buffer
+    __shared__ __align__(16) uint8_t sCode[TY * TX];
+    __shared__ uint32_t sHot[L::SH * L::HW];                // H', apron 2, in-frame
+    __shared__ uint32_t sQ[L::kTileWords], sQpre[L::kTileWords + 1];
+    __shared__ uint32_t sU[L::kTileWords], sUpre[L::kTileWords + 1];
+    __shared__ unsigned int sErrBits, sContrast, sUncertain;
+    double *const sX = reinterpret_cast<double *>(sS);
 
     DevFrame f;
     int y0, x0;
@@ -123,13 +257,21 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     const int H = f.H, W = f.W, tid = threadIdx.x;
     // iteration 1 reads the input frame and initialises J with the tile's own pixels
     const float *__restrict__ J = (k == 1) ? f.img : f.J;
-    const double sigclip = f.sigclip;
-    const double lowlim = (double)f.sigfrac * (double)f.sigclip;
+    const float sc = f.sigclip, ll = f.sigfrac * f.sigclip;
+    // thresholds widened by 2^-20 relative: fl(x) beyond them decides the real x
+    // against the binary64 thresholds sigclip and sigfrac * sigclip (exact products)
+    const float sc_lo = sc * (1.0f - 0x1p-20f), sc_hi = sc * (1.0f + 0x1p-20f);
+    const float ll_lo = ll * (1.0f - 0x1p-20f), ll_hi = ll * (1.0f + 0x1p-20f);
 
     for (int i = tid; i < L::SH * L::HW; i += kThreads)
         sHot[i] = 0u;
-    if (tid == 0)
+    if (tid < L::kTileWords)
+        sU[tid] = 0u;
+    if (tid == 0) {
+        sErrBits = 0u;
         sContrast = 0u;
+        sUncertain = 0u;
+    }
     // J over [y0-4, y0+TY+4) x [x0-4, x0+TX+4), clamped reads: all of a thread's
     // loads are issued before the first LDS store, so their latencies overlap
     {
@@ -181,12 +323,13 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         }
     }
 
-    // med5(J), L+, N and S over [y0-2, y0+TY+2) x [x0-2, x0+TX+2); marks H
+    // med5(J), L+ and the S estimate over [y0-2, y0+TY+2) x [x0-2, x0+TX+2); marks
+    // H' and takes the block's largest error bound
     {
         constexpr int TTY = 2, TTX = 5, PW = TTX + 4;
         constexpr int NTY = (L::SH + TTY - 1) / TTY, NTX = (L::SW + TTX - 1) / TTX;
-        const double gain = f.gain, sky = f.sky, rn = f.readnoise;
-        const double rn2 = rn * rn;
+        const SEstParams sp = sest_params(f);
+        float emax = 0.0f;
         for (int t = tid; t < NTY * NTX; t += kThreads) {
             const int ty = t / NTX;
             const int r = min(ty * TTY, L::SH - TTY);
@@ -203,22 +346,22 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
 #pragma unroll
                 for (int j = 0; j < TTX; ++j) {
                     const int pc = (i + 2) * PW + (j + 2);
-                    const double lp = lplus(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1]);
-                    double m = (double)m5[i * TTX + j] + sky;
-                    if (m <= 0.0)
-                        m = 1e-4;
-                    const double N = sqrt(gain * m + rn2) / gain;
-                    const double S = lp / (2.0 * N);
-                    sS[(r + i) * L::SWP + c + j] = S;
-                    const int cy = r + i - 2, cxx = c + j - 2;
-                    if (cy >= 0 && cy < TY && cxx >= 0 && cxx < TX)
-                        sM5[cy * TX + cxx] = m5[i * TTX + j];
-                    const int gy = y0 + cy, gx = x0 + cxx;
-                    if (S > sigclip && gy >= 0 && gy < H && gx >= 0 && gx < W)
+                    float err;
+                    const float s = s_estimate(v[pc], v[pc - PW], v[pc + PW], v[pc - 1],
+                                               v[pc + 1], m5[i * TTX + j], sp, err);
+                    sS[(r + i) * L::SWP + c + j] = s;
+                    emax = fmaxf(emax, err);
+                    const int gy = y0 - 2 + r + i, gx = x0 - 2 + c + j;
+                    if (s + err > sc_lo && gy >= 0 && gy < H && gx >= 0 && gx < W)
                         atomicOr(&sHot[(r + i) * L::HW + ((c + j) >> 5)], 1u << ((c + j) & 31));
                 }
             }
         }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            emax = fmaxf(emax, __shfl_xor(emax, off));
+        if ((tid & 63) == 0)     // non-negative floats order as their bit patterns
+            atomicMax(&sErrBits, __float_as_uint(emax));
     }
     __syncthreads();
 
@@ -240,12 +383,14 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                     sS[(clampi(gy, H) - (y0 - 2)) * L::SWP + (clampi(gx, W) - (x0 - 2))];
         }
     }
-    // the J buffer is free: clear the code tile
-    for (int i = tid; i < L::kCodeWords; i += kThreads)
-        reinterpret_cast<uint32_t *>(sJ)[i] = 0u;
-    // work bitmap Q = D2(H) & {S > sigfrac*sigclip} on the tile's in-frame pixels, one
-    // 32-pixel word per lane of the first wave, and its prefix sum of pixel counts
-    if (tid < L::kWorkWords) {
+    for (int i = tid; i < TY * TX / 4; i += kThreads)
+        reinterpret_cast<uint32_t *>(sCode)[i] = 0u;
+    const float emax = __uint_as_float(sErrBits);
+    // no estimate of the block is usable: every work pixel is re-evaluated
+    const bool all_exact = !(emax < INFINITY) || (f.flags & kExactDetect);
+    // work bitmap Q' on the tile's in-frame pixels, one 32-pixel word per lane of the
+    // first wave, and its prefix sum of pixel counts
+    if (tid < L::kTileWords) {
         const int r = tid / L::QW, w = tid - r * L::QW;
         unsigned long long x = 0ull;
 #pragma unroll
@@ -261,104 +406,145 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             q = 0u;
         else if (vc < 32)
             q &= (1u << vc) - 1u;
-        for (uint32_t m = q; m; m &= m - 1u) {
-            const int b = __ffs(m) - 1;
-            if (!(sS[(r + 2) * L::SWP + 32 * w + b + 2] > lowlim))
-                q &= ~(1u << b);
+        if (!all_exact) {
+            for (uint32_t m = q; m; m &= m - 1u) {
+                const int b = __ffs(m) - 1;
+                if (!(sS[(r + 2) * L::SWP + 32 * w + b + 2] + emax > ll_lo))
+                    q &= ~(1u << b);
+            }
         }
         sQ[tid] = q;
-        int v = __popc(q);
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int u = __shfl_up(v, off);
-            if (tid >= off)
-                v += u;
-        }
-        sQpre[tid + 1] = (uint32_t)v;
-        if (tid == 0)
-            sQpre[0] = 0u;
+        bitmap_prefix64(sQ, sQpre);
     }
     __syncthreads();
 
-    // the work set, compacted: thread t takes the t-th, (t+256)-th, ... pixel of Q
-    {
-        const int total = (int)sQpre[L::kWorkWords];
-        const double objlim = f.objlim;
-        const double gain = f.gain, sky = f.sky, rn = f.readnoise;
-        const double rn2 = rn * rn;
-        unsigned int ncontrast = 0u;
+    const double gain = f.gain, sky = f.sky, rn = f.readnoise;
+    const double rn2 = rn * rn, sigclip = f.sigclip, objlim = f.objlim;
+    const double lowlim = (double)f.sigfrac * (double)f.sigclip;
+    const int total = (int)sQpre[L::kTileWords];
+    // the work set, compacted: thread t takes the t-th, (t+256)-th, ... pixel of Q'.
+    // S' from the estimates lies within B of the binary64 S' (B covers twice the
+    // block's largest error and the FP32 rounding of the difference)
+    if (!all_exact) {
+        const float b2 = 2.02f * emax;
+        unsigned int ncontrast = 0u, nunc = 0u;
         for (int qi = tid; qi < total; qi += kThreads) {
-            int lo = 0, hi = L::kWorkWords - 1;    // last word whose prefix is <= qi
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if ((int)sQpre[mid] <= qi)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            uint32_t bits = sQ[lo];
-            for (int n = qi - (int)sQpre[lo]; n > 0; --n)
-                bits &= bits - 1u;
-            const int r = lo / L::QW, c = (lo - r * L::QW) * 32 + (__ffs(bits) - 1);
-            double v[25], ms[1];
+            const int pos = bitmap_select64(sQ, sQpre, qi);
+            const int r = pos / TX, c = pos - r * TX;
+            float w[25], ms[1];
 #pragma unroll
             for (int i = 0; i < 5; ++i)
 #pragma unroll
                 for (int j = 0; j < 5; ++j)
-                    v[i * 5 + j] = sS[(r + i) * L::SWP + c + j];
-            med5_t1x1(v, ms);
-            const double sp = v[12] - ms[0];
-            const bool hbit = sp > sigclip;
-            const bool lbit = sp > lowlim;
+                    w[i * 5 + j] = sS[(r + i) * L::SWP + c + j];
+            med5_t1x1(w, ms);
+            const float spr = w[12] - ms[0];
+            const float B = fmaf(fabsf(spr), 0x1p-20f, b2);
+            const float lo = spr - B, hi = spr + B;
+            const bool h1 = lo > sc_hi, h0 = hi <= sc_lo, l1 = lo > ll_hi, l0 = hi <= ll_lo;
+            bool unc = !((h1 || h0) && (l1 || l0));
             bool first = false;
-            if (hbit) {
-                // N as in the S stage, from the stored med5(J)
-                double m = (double)sM5[r * TX + c] + sky;
-                if (m <= 0.0)
-                    m = 1e-4;
-                const double N = sqrt(gain * m + rn2) / gain;
-                float w7[49], m7[1];
-#pragma unroll
-                for (int i = 0; i < 7; ++i)
-#pragma unroll
-                    for (int j = 0; j < 7; ++j)
-                        w7[i * 7 + j] = sM3[(r + i) * L::MWP + c + j];
-                med7_t1x1(w7, m7);
-                double fh = ((double)w7[24] - (double)m7[0]) / N;
-                if (fh < 0.01)
-                    fh = 0.01;
-                first = sp / fh > objlim;
-                ++ncontrast;
+            if (!unc && h1) {
+                const double fh = fine_structure(&sJ[(r + 4) * L::JWP + c + 4], L::JWP,
+                                                 &sM3[(r + 3) * L::MWP + c + 3], L::MWP, gain,
+                                                 sky, rn2);
+                // S'/F^ rounds monotonically in S'
+                if ((double)lo / fh > objlim)
+                    first = true;
+                else if (!((double)hi / fh <= objlim))
+                    unc = true;
+                ncontrast += unc ? 0u : 1u;
             }
-            sCode[r * TX + c] = (uint8_t)((first ? 1 : 0) | (hbit ? 2 : 0) | (lbit ? 4 : 0));
+            if (unc) {
+                atomicOr(&sU[pos >> 5], 1u << (pos & 31));
+                ++nunc;
+            } else {
+                sCode[pos] = (uint8_t)((first ? 1 : 0) | (h1 ? 2 : 0) | (l1 ? 4 : 0));
+            }
         }
-        if ((f.flags & kCountWork) && ncontrast)
+        if (ncontrast && (f.flags & kCountWork))
+            atomicAdd(&sContrast, ncontrast);
+        if (nunc)
+            atomicAdd(&sUncertain, nunc);
+    } else {
+        for (int i = tid; i < L::kTileWords; i += kThreads)
+            sU[i] = sQ[i];
+        if (tid == 0)
+            sUncertain = (unsigned int)total;
+    }
+    __syncthreads();
+
+    // binary64 re-evaluation of the undecided pixels from J, kExactBatch per round:
+    // 25 threads compute the S window of a pixel, then one thread its codes
+    const int nunc = (int)sUncertain;
+    if (nunc) {
+        if (tid < L::kTileWords)
+            bitmap_prefix64(sU, sUpre);
+        __syncthreads();
+        unsigned int ncontrast = 0u;
+        for (int base = 0; base < nunc; base += kExactBatch) {
+            const int slot = tid / 25, cell = tid - slot * 25;
+            if (slot < kExactBatch && base + slot < nunc) {
+                const int pos = bitmap_select64(sU, sUpre, base + slot);
+                const int r = pos / TX, c = pos - r * TX;
+                const int i = cell / 5, j = cell - i * 5;
+                // window cell in frame coordinates, clamped; its staged-J cell
+                const int gy = clampi(y0 + r + i - 2, H), gx = clampi(x0 + c + j - 2, W);
+                sX[slot * 25 + cell] = s_exact(&sJ[(gy - y0 + 4) * L::JWP + gx - x0 + 4],
+                                               L::JWP, gain, sky, rn2);
+            }
+            __syncthreads();
+            if (tid < kExactBatch && base + tid < nunc) {
+                const int pos = bitmap_select64(sU, sUpre, base + tid);
+                const int r = pos / TX, c = pos - r * TX;
+                double v[25], ms[1];
+#pragma unroll
+                for (int i = 0; i < 25; ++i)
+                    v[i] = sX[tid * 25 + i];
+                med5_t1x1(v, ms);
+                const double spr = v[12] - ms[0];
+                const bool hbit = spr > sigclip, lbit = spr > lowlim;
+                bool first = false;
+                if (hbit) {
+                    const double fh = fine_structure(&sJ[(r + 4) * L::JWP + c + 4], L::JWP,
+                                                     &sM3[(r + 3) * L::MWP + c + 3], L::MWP,
+                                                     gain, sky, rn2);
+                    first = spr / fh > objlim;
+                    ++ncontrast;
+                }
+                sCode[pos] = (uint8_t)((first ? 1 : 0) | (hbit ? 2 : 0) | (lbit ? 4 : 0));
+            }
+            __syncthreads();
+        }
+        if (ncontrast && (f.flags & kCountWork))
             atomicAdd(&sContrast, ncontrast);
         __syncthreads();
+    }
 
-        // codes of the tile, 8 per thread
-        uint8_t *__restrict__ codes = f.codes;
-        for (int i = tid; i < TY * TX / 8; i += kThreads) {
-            const int r = i / (TX / 8), c = (i - r * (TX / 8)) * 8;
-            const int gy = y0 + r, gx = x0 + c;
-            if (gy >= H || gx >= W)
-                continue;
-            uint8_t *dst = codes + (size_t)gy * W + gx;
-            const uint2 word = *reinterpret_cast<const uint2 *>(&sCode[r * TX + c]);
-            if (gx + 8 <= W && ((uintptr_t)dst & 7u) == 0u) {
-                *reinterpret_cast<uint2 *>(dst) = word;
-            } else {
-                const int nb = min(8, W - gx);
-                for (int b = 0; b < nb; ++b)
-                    dst[b] = sCode[r * TX + c + b];
-            }
+    // codes of the tile, 8 per thread
+    uint8_t *__restrict__ codes = f.codes;
+    for (int i = tid; i < TY * TX / 8; i += kThreads) {
+        const int r = i / (TX / 8), c = (i - r * (TX / 8)) * 8;
+        const int gy = y0 + r, gx = x0 + c;
+        if (gy >= H || gx >= W)
+            continue;
+        uint8_t *dst = codes + (size_t)gy * W + gx;
+        const uint2 word = *reinterpret_cast<const uint2 *>(&sCode[r * TX + c]);
+        if (gx + 8 <= W && ((uintptr_t)dst & 7u) == 0u) {
+            *reinterpret_cast<uint2 *>(dst) = word;
+        } else {
+            const int nb = min(8, W - gx);
+            for (int b = 0; b < nb; ++b)
+                dst[b] = sCode[r * TX + c + b];
         }
-        if ((f.flags & kCountWork) && tid == 0 && f.work) {
-            if (total)
-                atomicAdd(&f.work[0], (unsigned long long)total);
-            if (sContrast)
-                atomicAdd(&f.work[1], (unsigned long long)sContrast);
-        }
+    }
+    if ((f.flags & kCountWork) && tid == 0 && f.work) {
+        if (total)
+            atomicAdd(&f.work[0], (unsigned long long)total);
+        if (sContrast)
+            atomicAdd(&f.work[1], (unsigned long long)sContrast);
+        if (nunc)
+            atomicAdd(&f.work[2], (unsigned long long)nunc);
     }
 }
 
@@ -423,9 +609,39 @@ __global__ __launch_bounds__(kThreads) void k_debug_median5_f64(const double *__
     out[t] = o[0];
 }
 
+// The detection kernel's FP32 estimate of S and its error bound, one pixel per thread
+// (clamped neighbours and med5(J) from a single-output network).
+__global__ __launch_bounds__(kThreads) void k_debug_s_estimate(DevFrame f,
+                                                               float *__restrict__ out_s,
+                                                               float *__restrict__ out_err) {
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const int H = f.H, W = f.W;
+    if (t >= (long long)H * W)
+        return;
+    const int y = (int)(t / W), x = (int)(t - (long long)y * W);
+    float w[25], m5[1];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            w[i * 5 + j] = f.img[(size_t)clampi(y - 2 + i, H) * W + clampi(x - 2 + j, W)];
+    med5_t1x1(w, m5);
+    float err;
+    out_s[t] = s_estimate(w[12], w[7], w[17], w[11], w[13], m5[0], sest_params(f), err);
+    out_err[t] = err;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_debug_s_estimate(const DevFrame &f, float *out_s, float *out_err,
+                                   hipStream_t s) {
+    const size_t n = (size_t)f.H * (size_t)f.W;
+    k_debug_s_estimate<<<(unsigned int)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+        f, out_s, out_err);
+    return hipGetLastError();
+}
 
 hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
                          const DevFrame &single, int k, hipStream_t s) {

@@ -24,10 +24,15 @@ constexpr int kNumKernelKinds = 4;
 
 // DevFrame::flags bits.  kNoEarlyStop has the value of CRB_FLAG_NO_EARLY_STOP;
 // kFreshMask: the mask is uninitialised before iteration 1, which then writes all of it.
-// kCountWork: detection adds its work-set size and contrast-test count to f.work.
+// kCountWork: detection adds its work-set size, contrast-test count and number of
+// binary64 re-evaluations to f.work[0..2].
+// kExactDetect: detection evaluates S' of every work-set pixel in binary64 from J
+// (parity tests of that path).
 constexpr int kNoEarlyStop = 1;
 constexpr int kFreshMask = 1 << 8;
 constexpr int kCountWork = 1 << 9;
+constexpr int kExactDetect = 1 << 10;
+constexpr int kWorkCounters = 3;
 
 // Everything a kernel needs to know about one frame.  All pointers are device
 // pointers; J is the image being cleaned in place (out_clean).
@@ -40,7 +45,7 @@ struct DevFrame {
     uint32_t *list;               // indices of flagged pixels, H x W capacity (workspace)
     unsigned long long *nnew;     // n_k per iteration [kMaxIter] (workspace)
     unsigned int *listlen;        // list length per iteration [kMaxIter] (workspace)
-    unsigned long long *work;     // with kCountWork: [work-set pixels, contrast tests], or null
+    unsigned long long *work;     // with kCountWork: kWorkCounters counters, or null
     int H, W;
     float gain, readnoise, sky, sigclip, sigfrac, objlim;
     int niter;
@@ -96,6 +101,10 @@ hipError_t launch_stitch(float *out_clean, uint8_t *out_mask, int W, const SubRe
                          int nsub, size_t max_pixels, hipStream_t s);
 
 hipError_t launch_debug_median(const float *in, int H, int W, int r, float *out, hipStream_t s);
+// FP32 estimate of S and its error bound at every pixel of one frame (the detection
+// kernel's estimate, for parity tests of the bound).
+hipError_t launch_debug_s_estimate(const DevFrame &f, float *out_s, float *out_err,
+                                   hipStream_t s);
 hipError_t launch_debug_median5_f64(const double *in, int H, int W, double *out,
                                    hipStream_t s);
 hipError_t launch_debug_fp64(const double *x, const double *y, int n, double *out_sqrt,

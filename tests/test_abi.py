@@ -155,9 +155,19 @@ def test_farm_argument_validation(L):
 
 
 def test_counting_and_debug_entry_validation(L):
-    c = (ctypes.c_int64 * 2)()
+    c = (ctypes.c_int64 * 3)()
     assert L.crb_plan_set_counting(None, 1) == -1
     assert L.crb_plan_work_counts(None, c) == -1
     assert L.crb_debug_median5_f64(None, 4, 4, ctypes.c_void_p(1 << 40)) == -1
     assert L.crb_debug_median5_f64(ctypes.c_void_p(1 << 41), 0, 4, ctypes.c_void_p(1 << 40)) == -1
     assert L.crb_debug_median5_f64(ctypes.c_void_p(1 << 40), 4, 4, ctypes.c_void_p((1 << 40) + 8)) == -1
+    from paper_1008_2192_amd import _lib
+    fr = _lib.Frame()
+    fr.H, fr.W, fr.gain, fr.readnoise, fr.sigclip, fr.sigfrac, fr.objlim, fr.niter = \
+        8, 8, 1.0, 5.0, 4.5, 0.3, 4.0, 1
+    a, b = ctypes.c_void_p(1 << 40), ctypes.c_void_p(1 << 41)
+    assert L.crb_debug_detect_exact(None, ctypes.byref(fr), a) == -1
+    assert L.crb_debug_s_estimate(a, ctypes.byref(fr), None, b) == -1
+    assert L.crb_debug_s_estimate(a, ctypes.byref(fr), b, ctypes.c_void_p((1 << 41) + 4)) == -1
+    fr.gain = 0.0
+    assert L.crb_debug_s_estimate(a, ctypes.byref(fr), b, ctypes.c_void_p(1 << 42)) == -1
