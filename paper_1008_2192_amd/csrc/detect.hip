@@ -60,6 +60,10 @@ __device__ __forceinline__ double lplus(double c, double u, double d, double l, 
 // detection
 // ---------------------------------------------------------------------------
 
+// Fourth word of a raw buffer resource on gfx9-family GPUs: 32-bit data format, no
+// swizzle, range-checked against the byte count given with the base.
+constexpr int kBufferWord3 = 0x00020000;
+
 // FP32 parameters of the S estimate; ok is false for gains outside [2^-100, 2^100]
 // (where g/8 could round), which leaves every decision to the binary64 evaluation.
 struct SEstParams {
@@ -272,34 +276,59 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         sContrast = 0u;
         sUncertain = 0u;
     }
-    // J over [y0-4, y0+TY+4) x [x0-4, x0+TX+4), clamped reads: all of a thread's
-    // loads are issued before the first LDS store, so their latencies overlap
+    // J over [y0-4, y0+TY+4) x [x0-4, x0+TX+4), clamped reads.  Thread t loads column
+    // t % JW of rows t / JW + kJStep * b, so its clamped column is computed once and, on
+    // tiles whose rows are all inside the frame, each further row costs one address
+    // step.  All of a thread's loads are issued before the first LDS store, so their
+    // latencies overlap.
     {
-        constexpr int NJ = L::JH * L::JW, NB = (NJ + kThreads - 1) / kThreads;
-        float v[NB];
+        constexpr int kJStep = kThreads / L::JW;
+        constexpr int NB = (L::JH + kJStep - 1) / kJStep;
+        const int c = tid % L::JW, r0 = tid / L::JW;
+        if (r0 < kJStep) {
+            const int cc = clampi(x0 - 4 + c, W);
+            float v[NB];
+            if (y0 >= 4 && y0 + TY + 4 <= H && W <= (1 << 24)) {
+                // buffer loads over the JH staged rows (below 2^32 bytes: at most 2^24
+                // pixels per row): a per-lane byte offset and a uniform row step, so a
+                // further row costs no vector instruction
+                const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(J + (size_t)(y0 - 4) * W), (short)0, L::JH * W * 4, kBufferWord3);
+                const int boff = (r0 * W + cc) * 4;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int i = tid + b * kThreads;
-            if (i < NJ) {
-                const int r = i / L::JW, c = i - r * L::JW;
-                v[b] = J[(size_t)clampi(y0 - 4 + r, H) * W + clampi(x0 - 4 + c, W)];
-            }
-        }
+                for (int b = 0; b < NB; ++b)
+                    if (r0 + kJStep * b < L::JH)
+                        v[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                            rows, boff, kJStep * b * W * 4, 0));
+            } else {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const int i = tid + b * kThreads;
-            if (i < NJ) {
-                const int r = i / L::JW, c = i - r * L::JW;
-                sJ[r * L::JWP + c] = v[b];
+                for (int b = 0; b < NB; ++b)
+                    if (r0 + kJStep * b < L::JH)
+                        v[b] = J[(size_t)clampi(y0 - 4 + r0 + kJStep * b, H) * W + cc];
             }
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (r0 + kJStep * b < L::JH)
+                    sJ[(r0 + kJStep * b) * L::JWP + c] = v[b];
         }
     }
     __syncthreads();
+    // iteration 1: the tile's own pixels of the input become J, 8 per thread
     if (k == 1 && f.img != f.J) {
-        for (int i = tid; i < TY * TX; i += kThreads) {
-            const int r = i / TX, c = i - r * TX;
-            if (y0 + r < H && x0 + c < W)
-                f.J[(size_t)(y0 + r) * W + x0 + c] = sJ[(r + 4) * L::JWP + c + 4];
+        static_assert(TY * TX == 8 * kThreads, "one 8-pixel row segment per thread");
+        const int r = tid / (TX / 8), cs = (tid - r * (TX / 8)) * 8;
+        const int gy = y0 + r, gx = x0 + cs;
+        if (gy < H && gx < W) {
+            const float *src = &sJ[(r + 4) * L::JWP + cs + 4];
+            float *dst = f.J + (size_t)gy * W + gx;
+            if (gx + 8 <= W && ((uintptr_t)dst & 15u) == 0u) {
+                reinterpret_cast<float4 *>(dst)[0] = make_float4(src[0], src[1], src[2], src[3]);
+                reinterpret_cast<float4 *>(dst)[1] = make_float4(src[4], src[5], src[6], src[7]);
+            } else {
+                const int nb = min(8, W - gx);
+                for (int j = 0; j < nb; ++j)
+                    dst[j] = src[j];
+            }
         }
     }
 
