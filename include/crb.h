@@ -135,7 +135,8 @@ crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
  * evaluates med5(S), S' and the threshold bits only on its work set, the pixels
  * within 2 of a pixel with S > sigclip whose own S exceeds sigfrac * sigclip (taken
  * from an FP32 estimate of S widened by its error bound, so the set can hold a few
- * more pixels), and the fine-structure contrast (med7 of med3, F^, S'/F^) only where
+ * more pixels), and the fine-structure contrast test (S'/F^ > objlim, decided by
+ * counting the med7 window of med3 against the test's switching value) only where
  * S' > sigclip.  A work-set pixel whose S' interval from the estimate straddles a
  * threshold is re-evaluated in binary64 from J.  With counting enabled every
  * detection launch adds, per frame, the size of its work set, its number of contrast

@@ -254,7 +254,7 @@ class Plan:
 
     def work_counts(self) -> dict:
         """Detection work since counting was enabled: work-set pixels (med5 of S and
-        the threshold bits), contrast tests (med7 of med3 and F^) and binary64
+        the threshold bits), contrast tests (S'/F^ > objlim) and binary64
         re-evaluations (work-set pixels the FP32 estimate of S could not decide)."""
         c = (ctypes.c_int64 * 3)()
         check("crb_plan_work_counts", lib().crb_plan_work_counts(self.handle, c))

@@ -86,14 +86,15 @@ __device__ __forceinline__ SEstParams sest_params(const DevFrame &f) {
 // definition (S = L+ / (2N), L+ = a quarter of the sum over the four sub-pixels of
 // max(2c - v1 - v2, 0), N = sqrt(g m + rn^2) / g).  Error analysis, u = 2^-24,
 // round to nearest with FP32 denormals preserved, M = 4|c| + |up| + |dn| + |lf| + |rt|:
-//   the sub-pixel sum l4 (two roundings per term, three in the sum) is 4 L+ within
-//     10.1 u M;
+//   each clipped sub-pixel term (one FMA, one subtraction) is within 2u of its
+//     M-part, the four M-parts sum to 2M, and the three additions add 4u M: the
+//     sub-pixel sum l4 is 4 L+ within 8.01 u M;
 //   t = g m + rn^2 (positive terms, m itself rounded once) carries at most 3.03 u
-//     relative error; the reciprocal square root (v_rsq_f32, within 1 ulp), the
-//     scaling by g/8 (exact) and the product with l4 add at most 2u + 2u;
+//     relative error, so t^-1/2 at most 1.52 u; the reciprocal square root (v_rsq_f32,
+//     within 1 ulp = 2u), the scaling by g/8 (exact) and the two products add 2u + 2u;
 //   the binary64 evaluation is within 2^-49 (M R + S) of the exact value;
-// so |s - S| <= 10.3 u M R + 7 u s with R = g/(8 sqrt t), which err = 2^-18 (M R + s)
-// overstates six-fold.  Outside t in [2^-100, 2^100] and M <= 2^100 (where the
+// so |s - S| <= 8.01 u M R + 5.52 u s with R = g/(8 sqrt t), which err = 2^-19 (M R + s)
+// overstates four-fold (the s-term tolerates a reciprocal square root 14 ulp off).  Outside t in [2^-100, 2^100] and M <= 2^100 (where the
 // analysis has no overflow, underflow or domain edge) s = err = +inf, which sends every
 // decision that reads the pixel to the binary64 evaluation.
 __device__ __forceinline__ float s_estimate(float c, float up, float dn, float lf, float rt,
@@ -108,20 +109,20 @@ __device__ __forceinline__ float s_estimate(float c, float up, float dn, float l
     const float s = l4 * R;
     const float M = fmaf(4.0f, fabsf(c), fabsf(up)) + fabsf(dn) + (fabsf(lf) + fabsf(rt));
     const bool sane = __builtin_amdgcn_fmed3f(t, 0x1p-100f, 0x1p100f) == t && M <= 0x1p100f && p.ok;
-    err = sane ? (M * R + s) * 0x1p-18f : INFINITY;
+    err = sane ? (M * R + s) * 0x1p-19f : INFINITY;
     return sane ? s : INFINITY;
 }
 
 // S exactly as the definition evaluates it (binary64, in its operation order), at the
-// pixel whose staged-J cell is p (the staged J holds clamped values beyond the frame).
-__device__ __forceinline__ double s_exact(const float *p, int pitch, double gain, double sky,
-                                          double rn2) {
+// in-frame pixel (y, x) of J (clamped neighbours), read from global memory.
+__device__ __forceinline__ double s_exact(const float *__restrict__ J, int H, int W, int y, int x,
+                                          double gain, double sky, double rn2) {
     float w[25], m5[1];
 #pragma unroll
     for (int i = 0; i < 5; ++i)
 #pragma unroll
         for (int j = 0; j < 5; ++j)
-            w[i * 5 + j] = p[(i - 2) * pitch + (j - 2)];
+            w[i * 5 + j] = J[(size_t)clampi(y + i - 2, H) * W + clampi(x + j - 2, W)];
     med5_t1x1(w, m5);
     const double lp = lplus(w[12], w[7], w[17], w[11], w[13]);
     double m = (double)m5[0] + sky;
@@ -131,22 +132,16 @@ __device__ __forceinline__ double s_exact(const float *p, int pitch, double gain
     return lp / (2.0 * N);
 }
 
-// F^ = max((med3 - med7(med3)) / N, 0.01) at a tile pixel: pj is its staged-J cell,
-// pm its med3 cell; N from med5(J) as in S.
-__device__ __forceinline__ double fine_structure(const float *pj, int jpitch, const float *pm,
-                                                 int mpitch, double gain, double sky,
-                                                 double rn2) {
-    float w[25], m5[1];
-#pragma unroll
-    for (int i = 0; i < 5; ++i)
-#pragma unroll
-        for (int j = 0; j < 5; ++j)
-            w[i * 5 + j] = pj[(i - 2) * jpitch + (j - 2)];
-    med5_t1x1(w, m5);
-    double m = (double)m5[0] + sky;
+// N of the definition (binary64) from med5(J).
+__device__ __forceinline__ double noise_exact(float m5, double gain, double sky, double rn2) {
+    double m = (double)m5 + sky;
     if (m <= 0.0)
         m = 1e-4;
-    const double N = sqrt(gain * m + rn2) / gain;
+    return sqrt(gain * m + rn2) / gain;
+}
+
+// F^ = max((med3 - med7(med3)) / N, 0.01) at a tile pixel whose med3 cell is pm.
+__device__ __forceinline__ double fine_structure(const float *pm, int mpitch, double N) {
     float w7[49], m7[1];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
@@ -156,6 +151,42 @@ __device__ __forceinline__ double fine_structure(const float *pj, int jpitch, co
     med7_t1x1(w7, m7);
     double fh = ((double)w7[24] - (double)m7[0]) / N;
     return fh < 0.01 ? 0.01 : fh;
+}
+
+// The contrast test S'/F^ > objlim at a tile pixel whose med3 cell is pm, for every S'
+// in [lo, hi] (0 < lo), without selecting med7: 1 if it holds for all of them, 0 if it
+// fails for all, -1 if undecided.
+//   F^ does not increase with med7 (m3 - med7, the division by N > 0, the floor at 0.01
+//   and their roundings are monotone), so at fixed S' the test, as a function of the
+//   value x taken by med7, holds above a switching value and nowhere below it; med7 is
+//   the 25th smallest of the 49 window values, so the test holds at med7 iff it holds
+//   at 25 or more of them.
+//   If fl(S'/0.01) <= objlim the test fails whatever x (F^ >= 0.01).  Otherwise it holds
+//   at x iff fl(S'/fl(fl(m3 - x)/N)) > objlim or the floor is reached, i.e. iff
+//   m3 - x < (N S'/objlim)(1 + e) with |e| <= 4 * 2^-53: x above T = m3 - N S'/objlim up
+//   to a band far narrower than delta = 2^-40 (|m3| + N S'/objlim).  The test is larger
+//   for larger S', so lo bounds its certain holding and hi its possible holding.
+__device__ __forceinline__ int contrast_by_count(const float *pm, int mpitch, double N, float lo,
+                                                 float hi, double objlim) {
+    if ((double)hi / 0.01 <= objlim)
+        return 0;
+    if (!((double)lo / 0.01 > objlim))
+        return -1;
+    const double m3 = pm[0];
+    const double klo = N * (double)lo / objlim, khi = N * (double)hi / objlim;
+    // x > t_sure: holds for every S' >= lo; x >= t_maybe: may hold for some S' <= hi
+    const float t_sure = __double2float_ru((m3 - klo) + 0x1p-40 * (fabs(m3) + klo));
+    const float t_maybe = __double2float_rd((m3 - khi) - 0x1p-40 * (fabs(m3) + khi));
+    int sure = 0, maybe = 0;
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            const float x = pm[(i - 3) * mpitch + (j - 3)];
+            sure += x > t_sure ? 1 : 0;
+            maybe += x >= t_maybe ? 1 : 0;
+        }
+    return sure >= 25 ? 1 : (maybe < 25 ? 0 : -1);
 }
 
 // Wave 0: exclusive prefix sums of the set-bit counts of 64 bitmap words (one per
@@ -233,7 +264,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
               DevFrame single, int kiter) {
     using L = DetectLayout<TY, TX>;
-    __shared__ __align__(16) float sJ[L::JH * L::JWP];
+    __shared__ __align__(16) float sJ[L::JH * L::JWP];      // later: med5(J) of the tile
     __shared__ __align__(16) float sM3[L::MH * L::MWP];
     __shared__ __align__(16) float sS[L::SH * L::SWP];      // later: re-evaluation buffer
     __shared__ __align__(16) uint8_t sCode[TY * TX];
@@ -242,6 +273,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     __shared__ uint32_t sU[L::kTileWords], sUpre[L::kTileWords + 1];
     __shared__ unsigned int sErrBits, sContrast, sUncertain;
     double *const sX = reinterpret_cast<double *>(sS);
+    float *const sM5 = sJ;      // med5(J) of the tile, once the staged J is consumed
 
     DevFrame f;
     int y0, x0;
@@ -352,23 +384,27 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         }
     }
 
-    // med5(J), L+ and the S estimate over [y0-2, y0+TY+2) x [x0-2, x0+TX+2); marks
-    // H' and takes the block's largest error bound
+    // med5(J), L+ and the S estimate over [y0-2, y0+TY+2) x [x0-2, x0+TX+2) in one
+    // 2 x 5 tile per thread; marks H' and takes the block's largest error bound.  The
+    // tile's med5(J) is kept in registers and stored over J after the barrier.
+    constexpr int TTY = 2, TTX = 5, PW = TTX + 4;
+    constexpr int NTY = (L::SH + TTY - 1) / TTY, NTX = (L::SW + TTX - 1) / TTX;
+    static_assert(NTY * NTX <= kThreads, "one pass of 2 x 5 tiles");
+    float m5[TTY * TTX];
+    int r5 = 0, c5 = 0;
     {
-        constexpr int TTY = 2, TTX = 5, PW = TTX + 4;
-        constexpr int NTY = (L::SH + TTY - 1) / TTY, NTX = (L::SW + TTX - 1) / TTX;
         const SEstParams sp = sest_params(f);
         float emax = 0.0f;
-        for (int t = tid; t < NTY * NTX; t += kThreads) {
-            const int ty = t / NTX;
-            const int r = min(ty * TTY, L::SH - TTY);
-            const int c = min((t - ty * NTX) * TTX, L::SW - TTX);
-            float v[(TTY + 4) * PW], m5[TTY * TTX];
+        if (tid < NTY * NTX) {
+            const int ty = tid / NTX;
+            r5 = min(ty * TTY, L::SH - TTY);
+            c5 = min((tid - ty * NTX) * TTX, L::SW - TTX);
+            float v[(TTY + 4) * PW];
 #pragma unroll
             for (int i = 0; i < TTY + 4; ++i)
 #pragma unroll
                 for (int j = 0; j < PW; ++j)
-                    v[i * PW + j] = sJ[(r + i) * L::JWP + c + j];
+                    v[i * PW + j] = sJ[(r5 + i) * L::JWP + c5 + j];
             med5_t2x5(v, m5);
 #pragma unroll
             for (int i = 0; i < TTY; ++i) {
@@ -378,11 +414,12 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                     float err;
                     const float s = s_estimate(v[pc], v[pc - PW], v[pc + PW], v[pc - 1],
                                                v[pc + 1], m5[i * TTX + j], sp, err);
-                    sS[(r + i) * L::SWP + c + j] = s;
+                    sS[(r5 + i) * L::SWP + c5 + j] = s;
                     emax = fmaxf(emax, err);
-                    const int gy = y0 - 2 + r + i, gx = x0 - 2 + c + j;
+                    const int gy = y0 - 2 + r5 + i, gx = x0 - 2 + c5 + j;
                     if (s + err > sc_lo && gy >= 0 && gy < H && gx >= 0 && gx < W)
-                        atomicOr(&sHot[(r + i) * L::HW + ((c + j) >> 5)], 1u << ((c + j) & 31));
+                        atomicOr(&sHot[(r5 + i) * L::HW + ((c5 + j) >> 5)],
+                                 1u << ((c5 + j) & 31));
                 }
             }
         }
@@ -393,6 +430,17 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             atomicMax(&sErrBits, __float_as_uint(emax));
     }
     __syncthreads();
+    // med5(J) at the tile's pixels, over the staged J (no longer read)
+    if (tid < NTY * NTX) {
+#pragma unroll
+        for (int i = 0; i < TTY; ++i)
+#pragma unroll
+            for (int j = 0; j < TTX; ++j) {
+                const int ty = r5 + i - 2, tx = c5 + j - 2;
+                if (ty >= 0 && ty < TY && tx >= 0 && tx < TX)
+                    sM5[ty * TX + tx] = m5[i * TTX + j];
+            }
+    }
 
     // Region cells outside the image must hold the value of their clamped cell:
     // the windows of the work set read med3 and S at clamped neighbour positions.
@@ -453,7 +501,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     const int total = (int)sQpre[L::kTileWords];
     // the work set, compacted: thread t takes the t-th, (t+256)-th, ... pixel of Q'.
     // S' from the estimates lies within B of the binary64 S' (B covers twice the
-    // block's largest error and the FP32 rounding of the difference)
+    // block's largest error and, with 4u, the roundings of the differences)
     if (!all_exact) {
         const float b2 = 2.02f * emax;
         unsigned int ncontrast = 0u, nunc = 0u;
@@ -468,20 +516,17 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                     w[i * 5 + j] = sS[(r + i) * L::SWP + c + j];
             med5_t1x1(w, ms);
             const float spr = w[12] - ms[0];
-            const float B = fmaf(fabsf(spr), 0x1p-20f, b2);
+            const float B = fmaf(fabsf(spr), 0x1p-22f, b2);
             const float lo = spr - B, hi = spr + B;
             const bool h1 = lo > sc_hi, h0 = hi <= sc_lo, l1 = lo > ll_hi, l0 = hi <= ll_lo;
             bool unc = !((h1 || h0) && (l1 || l0));
             bool first = false;
             if (!unc && h1) {
-                const double fh = fine_structure(&sJ[(r + 4) * L::JWP + c + 4], L::JWP,
-                                                 &sM3[(r + 3) * L::MWP + c + 3], L::MWP, gain,
-                                                 sky, rn2);
-                // S'/F^ rounds monotonically in S'
-                if ((double)lo / fh > objlim)
-                    first = true;
-                else if (!((double)hi / fh <= objlim))
-                    unc = true;
+                const int t = contrast_by_count(&sM3[(r + 3) * L::MWP + c + 3], L::MWP,
+                                                noise_exact(sM5[pos], gain, sky, rn2), lo, hi,
+                                                objlim);
+                first = t > 0;
+                unc = t < 0;
                 ncontrast += unc ? 0u : 1u;
             }
             if (unc) {
@@ -517,10 +562,9 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 const int pos = bitmap_select64(sU, sUpre, base + slot);
                 const int r = pos / TX, c = pos - r * TX;
                 const int i = cell / 5, j = cell - i * 5;
-                // window cell in frame coordinates, clamped; its staged-J cell
+                // window cell in frame coordinates, clamped
                 const int gy = clampi(y0 + r + i - 2, H), gx = clampi(x0 + c + j - 2, W);
-                sX[slot * 25 + cell] = s_exact(&sJ[(gy - y0 + 4) * L::JWP + gx - x0 + 4],
-                                               L::JWP, gain, sky, rn2);
+                sX[slot * 25 + cell] = s_exact(J, H, W, gy, gx, gain, sky, rn2);
             }
             __syncthreads();
             if (tid < kExactBatch && base + tid < nunc) {
@@ -535,9 +579,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 const bool hbit = spr > sigclip, lbit = spr > lowlim;
                 bool first = false;
                 if (hbit) {
-                    const double fh = fine_structure(&sJ[(r + 4) * L::JWP + c + 4], L::JWP,
-                                                     &sM3[(r + 3) * L::MWP + c + 3], L::MWP,
-                                                     gain, sky, rn2);
+                    const double fh = fine_structure(&sM3[(r + 3) * L::MWP + c + 3], L::MWP,
+                                                     noise_exact(sM5[pos], gain, sky, rn2));
                     first = spr / fh > objlim;
                     ++ncontrast;
                 }

@@ -6,7 +6,10 @@ of a tiled execution is overhead, not algorithm):
     test that marks the pixels near which the other statistics can matter;
   * per work-set pixel (within 2 of an S > sigclip pixel, S > sigfrac * sigclip):
     med5 of S, S' and the two threshold compares;
-  * per contrast test (S' > sigclip): N again, med7 of med3, F^ and S'/F^ > objlim.
+  * per contrast test (S' > sigclip): N again and the test S'/F^ > objlim, decided by
+    comparing the 49 med3 values of the med7 window with the test's switching value
+    and counting them (the test holds at med7 iff it holds at 25 or more of them), which
+    is less work than selecting med7.
 The two sparse counts come from the kernel's own counters (crb_plan_work_counts).
 Median networks count their min/max operations after dead-code elimination, per
 output, from the generator; binary64 arithmetic counts one operation per IEEE add,
@@ -37,8 +40,10 @@ MED3_RUN = 14
 MED3_OPS = (3 * (MED3_RUN + 2) + 4 * MED3_RUN) / MED3_RUN   # column sorts of 3 ops + 4 per output
 # per work-set pixel, besides med5(S): S - med5(S), > sigclip, > sigfrac*sigclip
 WORK_OPS = 3
-# per contrast test, besides med7: N (6), m3 - m7, / N, floor, S'/F^, > objlim
-CONTRAST_OPS = NOISE_OPS + 5
+# per contrast test: N (6); the floor test S'/0.01 > objlim, N S'/objlim, the switching
+# value and its band (6); two comparisons and two counts per window value (4 x 49); the
+# two count tests (2)
+CONTRAST_OPS = NOISE_OPS + 6 + 4 * 49 + 2
 
 
 @functools.lru_cache(maxsize=None)
@@ -64,7 +69,7 @@ def detect_ops() -> dict:
     dense["total"] = sum(dense.values())
     return dict(dense=dense,
                 per_work_pixel=network_ops_per_output("med5_t1x1") + WORK_OPS,
-                per_contrast=network_ops_per_output("med7_t1x1") + CONTRAST_OPS)
+                per_contrast=CONTRAST_OPS)
 
 
 def detect_ops_per_launch(pixels: int, work_pixels: float, contrast_tests: float) -> float:

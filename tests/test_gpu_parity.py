@@ -127,6 +127,24 @@ def test_detection_codes_match_oracle(exact):
                     f"detect {f.img.shape} exact={exact}")
 
 
+@pytest.mark.parametrize("objlim", [0.02, 0.5, 1.0, 2.0, 3.0, 4.0, 6.0, 10.0, 30.0])
+def test_contrast_decisions_across_objlim(objlim):
+    """The contrast test decided by counting the med7 window against its switching
+    value, at objlim values that move that value through the window: codes equal the
+    oracle's near S > sigclip on a frame dense in hits and stars."""
+    f = synth.c2()
+    img = np.ascontiguousarray(f.img[:160, :200])
+    p = fparams(f)
+    p["objlim"] = f32(objlim)
+    tr = ref.iterate(img, np.zeros(img.shape, np.uint8), trace=True, **p)
+    near = dilate(tr["s"] > p["sigclip"], 2)
+    exp = expected_codes(tr, p)
+    codes = _lib.debug_detect(torch.from_numpy(img).to(DEV), **p)
+    torch.cuda.synchronize()
+    check_codes(codes.cpu().numpy(), exp, near, tr, f"objlim {objlim}")
+    assert 0 < int((exp & 1).sum()) < int((exp & 2).sum()) or objlim in (0.02, 30.0)
+
+
 # Frames whose statistics span many binades: gains, sky levels and signal scales
 # far from the synthetic workloads, negative skies (the floor of m), a zero read noise.
 SCALES = [(1.0, 5.0, 0.0, 1.0), (1e-3, 0.5, 0.0, 1e3), (1e3, 50.0, 0.0, 1e-3),
