@@ -423,10 +423,10 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 }
             }
         }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            emax = fmaxf(emax, __shfl_xor(emax, off));
-        if ((tid & 63) == 0)     // non-negative floats order as their bit patterns
+        // non-negative floats order as their bit patterns: the device library's
+        // cross-lane (DPP) maximum, then one LDS atomic per wave
+        emax = __uint_as_float(__ockl_wfred_max_u32(__float_as_uint(emax)));
+        if ((tid & 63) == 0)
             atomicMax(&sErrBits, __float_as_uint(emax));
     }
     __syncthreads();
