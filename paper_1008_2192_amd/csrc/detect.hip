@@ -67,7 +67,7 @@ constexpr int kBufferWord3 = 0x00020000;
 // FP32 parameters of the S estimate; ok is false for gains outside [2^-100, 2^100]
 // (where g/8 could round), which leaves every decision to the binary64 evaluation.
 struct SEstParams {
-    float gain, g8, sky, rn2;
+    float gain, g8, inv_gain, sky, rn2;
     bool ok;
 };
 
@@ -75,6 +75,7 @@ __device__ __forceinline__ SEstParams sest_params(const DevFrame &f) {
     SEstParams p;
     p.gain = f.gain;
     p.g8 = f.gain * 0.125f;
+    p.inv_gain = 1.0f / f.gain;
     p.sky = f.sky;
     p.rn2 = f.readnoise * f.readnoise;
     p.ok = f.gain >= 0x1p-100f && f.gain <= 0x1p100f;
@@ -153,30 +154,39 @@ __device__ __forceinline__ double fine_structure(const float *pm, int mpitch, do
     return fh < 0.01 ? 0.01 : fh;
 }
 
-// The contrast test S'/F^ > objlim at a tile pixel whose med3 cell is pm, for every S'
-// in [lo, hi] (0 < lo), without selecting med7: 1 if it holds for all of them, 0 if it
-// fails for all, -1 if undecided.
+// The contrast test S'/F^ > objlim at a tile pixel whose med3 cell is pm and whose
+// med5(J) is m5, for every S' in [lo, hi] (0 < lo), without selecting med7: 1 if it
+// holds for all of them, 0 if it fails for all, -1 if undecided.
 //   F^ does not increase with med7 (m3 - med7, the division by N > 0, the floor at 0.01
 //   and their roundings are monotone), so at fixed S' the test, as a function of the
 //   value x taken by med7, holds above a switching value and nowhere below it; med7 is
 //   the 25th smallest of the 49 window values, so the test holds at med7 iff it holds
 //   at 25 or more of them.
-//   If fl(S'/0.01) <= objlim the test fails whatever x (F^ >= 0.01).  Otherwise it holds
-//   at x iff fl(S'/fl(fl(m3 - x)/N)) > objlim or the floor is reached, i.e. iff
-//   m3 - x < (N S'/objlim)(1 + e) with |e| <= 4 * 2^-53: x above T = m3 - N S'/objlim up
-//   to a band far narrower than delta = 2^-40 (|m3| + N S'/objlim).  The test is larger
-//   for larger S', so lo bounds its certain holding and hi its possible holding.
-__device__ __forceinline__ int contrast_by_count(const float *pm, int mpitch, double N, float lo,
-                                                 float hi, double objlim) {
-    if ((double)hi / 0.01 <= objlim)
+//   If fl(S'/0.01) <= objlim the test fails whatever x (F^ >= 0.01); 100 S' in FP32 is
+//   within 1.01u of that binary64 quotient (u = 2^-24), so comparing it with objlim
+//   widened or narrowed by 2^-21 relative decides this for the whole interval.
+//   Otherwise the test holds at x iff m3 - x < K (1 + e), K = N S'/objlim, |e| <=
+//   4 * 2^-53.  K from N in FP32 (within 8u: t = g m + rn^2 to 3.03u, its reciprocal
+//   square root to 1 ulp, two products) and two more products is within 11u, so x above
+//   T = m3 - K up to a band of 2^-19 (|m3| + K) + 2^-126 (three-fold the roundings)
+//   decides the test.  The test is larger for larger S', so lo bounds its certain
+//   holding and hi its possible holding.
+__device__ __forceinline__ int contrast_by_count(const float *pm, int mpitch, float m5,
+                                                 const SEstParams &p, float lo, float hi,
+                                                 float olim_lo, float olim_hi, float inv_olim) {
+    if (hi * 100.0f <= olim_lo)
         return 0;
-    if (!((double)lo / 0.01 > objlim))
+    if (!(lo * 100.0f > olim_hi))
         return -1;
-    const double m3 = pm[0];
-    const double klo = N * (double)lo / objlim, khi = N * (double)hi / objlim;
+    float m = m5 + p.sky;
+    m = (m <= 0.0f) ? 1e-4f : m;
+    const float t = fmaf(p.gain, m, p.rn2);
+    const float N = t * __builtin_amdgcn_rsqf(t) * p.inv_gain;
+    const float m3 = pm[0];
+    const float klo = N * lo * inv_olim, khi = N * hi * inv_olim;
     // x > t_sure: holds for every S' >= lo; x >= t_maybe: may hold for some S' <= hi
-    const float t_sure = __double2float_ru((m3 - klo) + 0x1p-40 * (fabs(m3) + klo));
-    const float t_maybe = __double2float_rd((m3 - khi) - 0x1p-40 * (fabs(m3) + khi));
+    const float t_sure = (m3 - klo) + fmaf(0x1p-19f, fabsf(m3) + klo, 0x1p-126f);
+    const float t_maybe = (m3 - khi) - fmaf(0x1p-19f, fabsf(m3) + khi, 0x1p-126f);
     int sure = 0, maybe = 0;
 #pragma unroll
     for (int i = 0; i < 7; ++i)
@@ -239,6 +249,8 @@ struct DetectLayout {
     static constexpr int HW = (SW + 31) / 32;   // words per row of the hot bitmap
     static constexpr int QW = TX / 32;          // words per row of the tile bitmaps
     static constexpr int kTileWords = TY * QW;
+    // the J buffer later holds med5(J) of the tile and a list of up to TY*TX positions
+    static constexpr int kJBuf = (JH * JWP > TY * TX * 3 / 2) ? JH * JWP : TY * TX * 3 / 2;
     static_assert(TX % 32 == 0 && kTileWords == 64, "one wave scans a tile bitmap");
     static_assert(QW + 1 <= HW, "dilation reads two bitmap words per work word");
     static_assert(SH * SWP * 4 >= kExactBatch * 25 * 8, "re-evaluation buffer in the S plane");
@@ -264,16 +276,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
 void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
               DevFrame single, int kiter) {
     using L = DetectLayout<TY, TX>;
-    __shared__ __align__(16) float sJ[L::JH * L::JWP];      // later: med5(J) of the tile
+    // J; later med5(J) of the tile followed by the work list
+    __shared__ __align__(16) float sJ[L::kJBuf];
     __shared__ __align__(16) float sM3[L::MH * L::MWP];
     __shared__ __align__(16) float sS[L::SH * L::SWP];      // later: re-evaluation buffer
     __shared__ __align__(16) uint8_t sCode[TY * TX];
     __shared__ uint32_t sHot[L::SH * L::HW];                // H', apron 2, in-frame
-    __shared__ uint32_t sQ[L::kTileWords], sQpre[L::kTileWords + 1];
     __shared__ uint32_t sU[L::kTileWords], sUpre[L::kTileWords + 1];
-    __shared__ unsigned int sErrBits, sContrast, sUncertain;
+    __shared__ unsigned int sErrBits, sContrast, sUncertain, sQcount;
     double *const sX = reinterpret_cast<double *>(sS);
     float *const sM5 = sJ;      // med5(J) of the tile, once the staged J is consumed
+    uint16_t *const sList = reinterpret_cast<uint16_t *>(sJ + TY * TX);   // work set Q'
 
     DevFrame f;
     int y0, x0;
@@ -305,6 +318,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         sU[tid] = 0u;
     if (tid == 0) {
         sErrBits = 0u;
+        sQcount = 0u;
         sContrast = 0u;
         sUncertain = 0u;
     }
@@ -465,8 +479,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     const float emax = __uint_as_float(sErrBits);
     // no estimate of the block is usable: every work pixel is re-evaluated
     const bool all_exact = !(emax < INFINITY) || (f.flags & kExactDetect);
-    // work bitmap Q' on the tile's in-frame pixels, one 32-pixel word per lane of the
-    // first wave, and its prefix sum of pixel counts
+    // work set Q' on the tile's in-frame pixels, one 32-pixel word per lane of the
+    // first wave, appended to a compact list of tile positions (in any order)
     if (tid < L::kTileWords) {
         const int r = tid / L::QW, w = tid - r * L::QW;
         unsigned long long x = 0ull;
@@ -490,23 +504,31 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                     q &= ~(1u << b);
             }
         }
-        sQ[tid] = q;
-        bitmap_prefix64(sQ, sQpre);
+        if (all_exact)
+            sU[tid] = q;
+        if (q) {
+            int at = (int)atomicAdd(&sQcount, (unsigned int)__popc(q));
+            for (uint32_t m = q; m; m &= m - 1u)
+                sList[at++] = (uint16_t)(tid * 32 + __ffs(m) - 1);   // = r * TX + column
+        }
     }
     __syncthreads();
 
     const double gain = f.gain, sky = f.sky, rn = f.readnoise;
     const double rn2 = rn * rn, sigclip = f.sigclip, objlim = f.objlim;
     const double lowlim = (double)f.sigfrac * (double)f.sigclip;
-    const int total = (int)sQpre[L::kTileWords];
+    const int total = (int)sQcount;
     // the work set, compacted: thread t takes the t-th, (t+256)-th, ... pixel of Q'.
     // S' from the estimates lies within B of the binary64 S' (B covers twice the
     // block's largest error and, with 4u, the roundings of the differences)
     if (!all_exact) {
         const float b2 = 2.02f * emax;
+        const SEstParams sp = sest_params(f);
+        const float olim = f.objlim, inv_olim = 1.0f / olim;
+        const float olim_lo = olim * (1.0f - 0x1p-21f), olim_hi = olim * (1.0f + 0x1p-21f);
         unsigned int ncontrast = 0u, nunc = 0u;
         for (int qi = tid; qi < total; qi += kThreads) {
-            const int pos = bitmap_select64(sQ, sQpre, qi);
+            const int pos = sList[qi];
             const int r = pos / TX, c = pos - r * TX;
             float w[25], ms[1];
 #pragma unroll
@@ -523,8 +545,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             bool first = false;
             if (!unc && h1) {
                 const int t = contrast_by_count(&sM3[(r + 3) * L::MWP + c + 3], L::MWP,
-                                                noise_exact(sM5[pos], gain, sky, rn2), lo, hi,
-                                                objlim);
+                                                sM5[pos], sp, lo, hi, olim_lo, olim_hi,
+                                                inv_olim);
                 first = t > 0;
                 unc = t < 0;
                 ncontrast += unc ? 0u : 1u;
@@ -540,11 +562,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             atomicAdd(&sContrast, ncontrast);
         if (nunc)
             atomicAdd(&sUncertain, nunc);
-    } else {
-        for (int i = tid; i < L::kTileWords; i += kThreads)
-            sU[i] = sQ[i];
-        if (tid == 0)
-            sUncertain = (unsigned int)total;
+    } else if (tid == 0) {
+        sUncertain = (unsigned int)total;     // sU holds Q'
     }
     __syncthreads();
 
