@@ -103,13 +103,6 @@ __device__ __forceinline__ void store16(uint8_t *__restrict__ p, int y, int x, i
 // bits 0, 8, 16, 24 of v -> bits 0..3 (the four products land on bits 21..24 without carries)
 __device__ __forceinline__ uint32_t squeeze4(uint32_t v) { return ((v * 0x00204081u) >> 21) & 0xFu; }
 
-__device__ __forceinline__ unsigned int wave_sum(unsigned int v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1)
-        v += (unsigned int)__shfl_xor((int)v, o);
-    return v;
-}
-
 __device__ __forceinline__ unsigned int wave_incl_scan(unsigned int v, int lane) {
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -225,34 +218,31 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
         hi1 = hi2;
         hG0 = hG1; hG1 = hG2;
     }
-    // one atomic per wave for the count and one for the list space
-    const unsigned int tn = wave_sum(nnew);
-    const unsigned int total = wave_sum(nm);
+    // one atomic per wave for the count and one for the list space; one scan of the
+    // lanes' counts places each lane's entries (its rows in order) in the wave's space
+    const unsigned int tn = __ockl_wfred_add_u32(nnew);
+    const unsigned int incl = wave_incl_scan(nm, lane);
+    const unsigned int total = (unsigned int)__builtin_amdgcn_readlane((int)incl, 63);
+    if (!total) {
+        if (tn && lane == 0)
+            atomicAdd(&f.nnew[k - 1], (unsigned long long)tn);
+        return;
+    }
     unsigned int base = 0;
     if (lane == 0) {
         if (tn)
             atomicAdd(&f.nnew[k - 1], (unsigned long long)tn);
-        if (total)
-            base = atomicAdd(&f.listlen[k - 1], total);
+        base = atomicAdd(&f.listlen[k - 1], total);
     }
-    base = (unsigned int)__shfl((int)base, 0);
-    if (!total)
-        return;
-    // entries row by row across the wave, each lane's pixels in order
+    unsigned int off = (unsigned int)__builtin_amdgcn_readfirstlane((int)base) + incl - nm;
 #pragma unroll
     for (int r = 0; r < TYG; ++r) {
         uint32_t m16 = (mbits[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
-        if (__ballot(m16 != 0) == 0ull)
-            continue;
-        const unsigned int cnt = (unsigned int)__popc(m16);
-        const unsigned int incl = wave_incl_scan(cnt, lane);
-        unsigned int off = base + incl - cnt;
         while (m16) {
             const int b = __ffs(m16) - 1;
             f.list[off++] = (uint32_t)(y0 + r) * (uint32_t)W + (uint32_t)(px + b);
             m16 &= m16 - 1;
         }
-        base += (unsigned int)__shfl((int)incl, 63);
     }
 }
 
