@@ -200,7 +200,8 @@ static crb_status ws_reserve(Workspace *ws, size_t bytes) {
 // enqueue niter iterations for one frame whose DevFrame is complete
 static crb_status enqueue_single(const DevFrame &f, hipStream_t s) {
     const size_t npix = (size_t)f.H * (size_t)f.W;
-    hipError_t e = launch_init(nullptr, 1, f, npix, s);
+    // the init kernel touches pixels only for niter == 0 (a copy); else just counters
+    hipError_t e = launch_init(nullptr, 1, f, f.niter == 0 ? npix : 0, s);
     for (int k = 1; e == hipSuccess && k <= f.niter; ++k) {
         e = launch_detect(nullptr, nullptr, 0, f, k, s);
         if (e == hipSuccess)
@@ -541,6 +542,7 @@ struct crb_plan {
     int n = 0;
     int kmax = 0;
     size_t max_pix = 0;
+    size_t init_pix = 0;                // largest frame with niter == 0 (0 if none)
     char *dmem = nullptr;
     DevFrame *d_frames = nullptr;
     TileRef *d_tdet = nullptr;
@@ -599,7 +601,7 @@ static crb_status plan_enqueue(crb_plan *p) {
     memset(&none, 0, sizeof(none));
     hipError_t e = tmark_begin(p, kKindInit);
     if (e == hipSuccess)
-        e = launch_init(p->d_frames, p->n, none, p->max_pix, s);
+        e = launch_init(p->d_frames, p->n, none, p->init_pix, s);
     if (e == hipSuccess)
         e = tmark_end(p);
     for (int k = 1; e == hipSuccess && k <= p->kmax; ++k) {
@@ -651,7 +653,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     crb_status st;
     std::vector<FrameWs> lay(n);
     std::vector<size_t> off(n);
-    size_t total = 0, max_pix = 0, all_pix = 0;
+    size_t total = 0, max_pix = 0, all_pix = 0, init_pix = 0;
     int kmax = 0;
     size_t ntdet = 0, ntgrow = 0;
     for (int i = 0; i < n; ++i) {
@@ -667,6 +669,8 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
         off[i] = total;
         total += lay[i].total;
         max_pix = npix > max_pix ? npix : max_pix;
+        if (f.niter == 0)      // the init kernel copies these frames
+            init_pix = npix > init_pix ? npix : init_pix;
         all_pix += npix;
         kmax = f.niter > kmax ? f.niter : kmax;
         ntdet += (size_t)((f.H + kDetectTY - 1) / kDetectTY) * ((f.W + kDetectTX - 1) / kDetectTX);
@@ -720,6 +724,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     p->n = n;
     p->kmax = kmax;
     p->max_pix = max_pix;
+    p->init_pix = init_pix;
     p->d_frames = reinterpret_cast<DevFrame *>(p->dmem + o_frames);
     p->d_tdet = reinterpret_cast<TileRef *>(p->dmem + o_tdet);
     p->d_tgrow = reinterpret_cast<TileRef *>(p->dmem + o_tgrow);

@@ -60,7 +60,8 @@ struct TileRef {                  // one (frame, tile origin) work item
 
 // Clears the counters; for frames with niter == 0 also copies img into J and clears
 // the mask (otherwise iteration 1 does both: detection copies img into J, the grow
-// writes the whole mask when kFreshMask is set).
+// writes the whole mask when kFreshMask is set).  max_pixels: the largest frame with
+// niter == 0 (0 if none), which sizes the grid.
 hipError_t launch_init(const DevFrame *d_frames, int nframes, const DevFrame &single,
                        size_t max_pixels, hipStream_t s);
 // Detection (codes) for one frame (d_tiles == null: grid over `single`) or a work list.

@@ -405,12 +405,13 @@ __global__ __launch_bounds__(kThreads) void k_replace(const DevFrame *__restrict
 // init and stats
 // ---------------------------------------------------------------------------
 
+// Grid rows (blockIdx.y) take the frames in turn.
 __global__ __launch_bounds__(kThreads) void k_init(const DevFrame *__restrict__ frames,
                                                    int nframes, DevFrame single) {
-    const int nf = frames ? nframes : 1;
     const size_t gid = (size_t)blockIdx.x * kThreads + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * kThreads;
-    for (int fi = 0; fi < nf; ++fi) {
+    const int nf = frames ? nframes : 1;
+    for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
         const DevFrame f = frames ? frames[fi] : single;
         if (f.niter == 0) {
             const size_t n = (size_t)f.H * (size_t)f.W;
@@ -516,8 +517,10 @@ static unsigned int grid_for(size_t items, unsigned int cap) {
 
 hipError_t launch_init(const DevFrame *d_frames, int nframes, const DevFrame &single,
                        size_t max_pixels, hipStream_t s) {
-    const unsigned int grid = grid_for(max_pixels > (size_t)kMaxIter ? max_pixels : kMaxIter, 4096);
-    k_init<<<grid, kThreads, 0, s>>>(d_frames, nframes, single);
+    const int rows = d_frames ? (nframes < 65535 ? nframes : 65535) : 1;
+    const unsigned int cap = 4096u / (unsigned int)rows > 16u ? 4096u / (unsigned int)rows : 16u;
+    const unsigned int gx = grid_for(max_pixels > (size_t)kMaxIter ? max_pixels : kMaxIter, cap);
+    k_init<<<dim3(gx, rows), kThreads, 0, s>>>(d_frames, nframes, single);
     return hipGetLastError();
 }
 
