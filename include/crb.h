@@ -66,9 +66,18 @@ typedef enum {
 
 /* crb_frame.flags */
 #define CRB_FLAG_NO_EARLY_STOP 1   /* always run niter iterations */
+/* From iteration 2 on, re-run the detection only on the tiles whose codes can change: a
+ * code depends on J within Chebyshev distance 4 (Section 5: S reads J within 2 pixels
+ * through med5(J) and L+, S' reads S within 2 more, F^ reads med3 within 3, and med3
+ * reads J within 1), and an iteration changes J only where its replacement wrote a new
+ * value; the other tiles keep their codes.  The results are identical to the full
+ * re-run. */
+#define CRB_FLAG_INCREMENTAL 2
 
 /* Options for crb_set_option. */
 #define CRB_OPT_EARLY_STOP 1       /* value 1 (default) or 0: early stop in crb_lacosmic */
+#define CRB_OPT_INCREMENTAL 2      /* value 0 (default) or 1: CRB_FLAG_INCREMENTAL for
+                                      crb_lacosmic and crb_lacosmic_partitioned */
 
 /*
  * Clean one frame (the method above).

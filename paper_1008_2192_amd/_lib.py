@@ -16,7 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcrb.so")
 
 CRB_FLAG_NO_EARLY_STOP = 1
+CRB_FLAG_INCREMENTAL = 2
 CRB_OPT_EARLY_STOP = 1
+CRB_OPT_INCREMENTAL = 2
 STATUS = {0: "CRB_OK", -1: "CRB_EINVAL", -2: "CRB_ENOMEM", -3: "CRB_EDEVICE",
           -4: "CRB_ETOOBIG", -5: "CRB_EBUSY"}
 
@@ -154,8 +156,10 @@ def set_stream(stream: Optional[torch.cuda.Stream] = None) -> None:
 def lacosmic(img: torch.Tensor, gain: float, readnoise: float, sky: float = 0.0,
              sigclip: float = 4.5, sigfrac: float = 0.3, objlim: float = 4.0, niter: int = 4,
              out_clean: Optional[torch.Tensor] = None, out_mask: Optional[torch.Tensor] = None,
-             early_stop: bool = True, stream: Optional[torch.cuda.Stream] = None):
-    """crb_lacosmic on device tensors; returns (clean float32, mask uint8)."""
+             early_stop: bool = True, incremental: bool = False,
+             stream: Optional[torch.cuda.Stream] = None):
+    """crb_lacosmic on device tensors; returns (clean float32, mask uint8).
+    incremental: CRB_OPT_INCREMENTAL (identical results, less detection work)."""
     _dev2d(img, torch.float32, "img")
     H, W = img.shape
     if out_clean is None:
@@ -167,6 +171,7 @@ def lacosmic(img: torch.Tensor, gain: float, readnoise: float, sky: float = 0.0,
     L = lib()
     set_stream(stream)
     check("crb_set_option", L.crb_set_option(CRB_OPT_EARLY_STOP, 1 if early_stop else 0))
+    check("crb_set_option", L.crb_set_option(CRB_OPT_INCREMENTAL, 1 if incremental else 0))
     check("crb_lacosmic", L.crb_lacosmic(img.data_ptr(), H, W, gain, readnoise, sky, sigclip,
                                          sigfrac, objlim, niter, out_clean.data_ptr(),
                                          out_mask.data_ptr()))
@@ -176,6 +181,7 @@ def lacosmic(img: torch.Tensor, gain: float, readnoise: float, sky: float = 0.0,
 def lacosmic_partitioned(img: torch.Tensor, gain: float, readnoise: float, ny: int, nx: int,
                          border: int, sky: float = 0.0, sigclip: float = 4.5,
                          sigfrac: float = 0.3, objlim: float = 4.0, niter: int = 4,
+                         incremental: bool = False,
                          stream: Optional[torch.cuda.Stream] = None):
     """crb_lacosmic_partitioned: independent subimages with a border, stitched."""
     _dev2d(img, torch.float32, "img")
@@ -183,6 +189,7 @@ def lacosmic_partitioned(img: torch.Tensor, gain: float, readnoise: float, ny: i
     out_clean = torch.empty_like(img)
     out_mask = torch.empty((H, W), dtype=torch.uint8, device=img.device)
     set_stream(stream)
+    check("crb_set_option", lib().crb_set_option(CRB_OPT_INCREMENTAL, 1 if incremental else 0))
     check("crb_lacosmic_partitioned", lib().crb_lacosmic_partitioned(
         img.data_ptr(), H, W, gain, readnoise, sky, sigclip, sigfrac, objlim, niter, ny, nx,
         border, out_clean.data_ptr(), out_mask.data_ptr()))
@@ -190,7 +197,8 @@ def lacosmic_partitioned(img: torch.Tensor, gain: float, readnoise: float, ny: i
 
 
 def make_frames(items: Sequence[dict]) -> "ctypes.Array[Frame]":
-    """items: dicts with img, out_clean, out_mask tensors and the parameters."""
+    """items: dicts with img, out_clean, out_mask tensors and the parameters
+    (early_stop, default True; incremental, default False)."""
     arr = (Frame * len(items))()
     for i, it in enumerate(items):
         img = _dev2d(it["img"], torch.float32, "img")
@@ -200,7 +208,8 @@ def make_frames(items: Sequence[dict]) -> "ctypes.Array[Frame]":
         arr[i] = Frame(img.data_ptr(), oc.data_ptr(), om.data_ptr(), H, W, it["gain"],
                        it["readnoise"], it.get("sky", 0.0), it.get("sigclip", 4.5),
                        it.get("sigfrac", 0.3), it.get("objlim", 4.0), it.get("niter", 4),
-                       CRB_FLAG_NO_EARLY_STOP if not it.get("early_stop", True) else 0, 0, 0, 0)
+                       (CRB_FLAG_NO_EARLY_STOP if not it.get("early_stop", True) else 0) |
+                       (CRB_FLAG_INCREMENTAL if it.get("incremental", False) else 0), 0, 0, 0)
     return arr
 
 

@@ -19,6 +19,7 @@ namespace crb {
 static thread_local std::string t_err;
 static thread_local hipStream_t t_stream = nullptr;
 static std::atomic<int> g_early_stop{1};
+static std::atomic<int> g_incremental{0};
 
 crb_status fail(crb_status st, const char *fmt, ...) {
     char buf[512];
@@ -91,7 +92,10 @@ FrameWs ws_layout(int32_t H, int32_t W) {
     L.list = align_up(L.codes + n, 256);
     L.nnew = align_up(L.list + 4 * n, 256);
     L.listlen = align_up(L.nnew + 8 * (size_t)kMaxIter, 256);
-    L.total = align_up(L.listlen + 4 * (size_t)kMaxIter, 256);
+    L.dirty = align_up(L.listlen + 4 * (size_t)kMaxIter, 256);
+    const size_t ntiles = (size_t)((H + kDetectTY - 1) / kDetectTY) *
+                          (size_t)((W + kDetectTX - 1) / kDetectTX);
+    L.total = align_up(L.dirty + ntiles, 256);
     return L;
 }
 
@@ -108,6 +112,7 @@ DevFrame make_devframe(const float *img, float *J, uint8_t *mask, char *ws, cons
     f.list = reinterpret_cast<uint32_t *>(ws + L.list);
     f.nnew = reinterpret_cast<unsigned long long *>(ws + L.nnew);
     f.listlen = reinterpret_cast<unsigned int *>(ws + L.listlen);
+    f.dirty = reinterpret_cast<uint8_t *>(ws + L.dirty);
     f.H = H;
     f.W = W;
     f.gain = gain;
@@ -230,6 +235,12 @@ crb_status crb_set_option(int32_t key, int64_t value) {
         g_early_stop.store((int)value);
         return ok();
     }
+    if (key == CRB_OPT_INCREMENTAL) {
+        if (value != 0 && value != 1)
+            return fail(CRB_EINVAL, "CRB_OPT_INCREMENTAL takes 0 or 1");
+        g_incremental.store((int)value);
+        return ok();
+    }
     return fail(CRB_EINVAL, "unknown option %d", key);
 }
 
@@ -282,7 +293,8 @@ crb_status crb_lacosmic(const float *img, int32_t H, int32_t W, float gain, floa
     const FrameWs L = ws_layout(H, W);
     if ((st = ws_reserve(ws, L.total)) != CRB_OK)
         return st;
-    const int flags = (g_early_stop.load() ? 0 : kNoEarlyStop) | kFreshMask;
+    const int flags = (g_early_stop.load() ? 0 : kNoEarlyStop) |
+                      (g_incremental.load() ? kIncremental : 0) | kFreshMask;
     DevFrame f = make_devframe(img, out_clean, out_mask, ws->buf, L, H, W, gain, readnoise, sky,
                                sigclip, sigfrac, objlim, niter, flags);
     if ((st = enqueue_single(f, s)) != CRB_OK)
@@ -743,7 +755,9 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
         hf[i] = make_devframe(f.img, f.out_clean, f.out_mask, p->dmem + off[i], lay[i], f.H, f.W,
                               f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac, f.objlim,
                               f.niter,
-                              (f.flags & CRB_FLAG_NO_EARLY_STOP ? kNoEarlyStop : 0) | kFreshMask);
+                              (f.flags & CRB_FLAG_NO_EARLY_STOP ? kNoEarlyStop : 0) |
+                                  (f.flags & CRB_FLAG_INCREMENTAL ? kIncremental : 0) |
+                                  kFreshMask);
         hf[i].work = p->d_work + kWorkCounters * (size_t)i;
         for (int y = 0; y < f.H; y += kDetectTY)
             for (int x = 0; x < f.W; x += kDetectTX)
@@ -995,6 +1009,7 @@ extern "C" crb_status crb_lacosmic_partitioned(const float *img, int32_t H, int3
         f.sigfrac = sigfrac;
         f.objlim = objlim;
         f.niter = niter;
+        f.flags = g_incremental.load() ? CRB_FLAG_INCREMENTAL : 0;
     }
     SubRect *d_subs = reinterpret_cast<SubRect *>(tmp + o_tab);
     crb_plan *plan = nullptr;
@@ -1031,3 +1046,5 @@ static_assert(sizeof(crb_source) == 40 && sizeof(crb_source) == sizeof(crb::Sour
 static_assert(offsetof(crb_source, flux) == offsetof(crb::SourceRec, flux) &&
               offsetof(crb_source, sx) == offsetof(crb::SourceRec, sx),
               "crb_source layout");
+
+static_assert(CRB_FLAG_INCREMENTAL == crb::kIncremental, "flag values agree");

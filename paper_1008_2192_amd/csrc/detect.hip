@@ -304,6 +304,17 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     if (frame_skips(f, k))
         return;
     const int H = f.H, W = f.W, tid = threadIdx.x;
+    // incremental mode: a tile whose J neighbourhood is unchanged since the previous
+    // iteration keeps its codes; every thread reads the flag before it is consumed
+    if ((f.flags & kIncremental) && f.dirty) {
+        const int ti = (y0 / TY) * ((W + TX - 1) / TX) + x0 / TX;
+        const bool dirty = k == 1 || f.dirty[ti] != 0;
+        __syncthreads();
+        if (!dirty)
+            return;
+        if (tid == 0)
+            f.dirty[ti] = 0;
+    }
     // iteration 1 reads the input frame and initialises J with the tile's own pixels
     const float *__restrict__ J = (k == 1) ? f.img : f.J;
     const float sc = f.sigclip, ll = f.sigfrac * f.sigclip;

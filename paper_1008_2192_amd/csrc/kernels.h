@@ -32,6 +32,10 @@ constexpr int kNoEarlyStop = 1;
 constexpr int kFreshMask = 1 << 8;
 constexpr int kCountWork = 1 << 9;
 constexpr int kExactDetect = 1 << 10;
+// kIncremental (the value of CRB_FLAG_INCREMENTAL): from iteration 2 on, detection
+// re-evaluates only the tiles flagged in f.dirty (replacement flags the tiles whose
+// codes can change); the others keep their codes, which the unchanged J determines.
+constexpr int kIncremental = 2;
 constexpr int kWorkCounters = 3;
 
 // Everything a kernel needs to know about one frame.  All pointers are device
@@ -46,6 +50,7 @@ struct DevFrame {
     unsigned long long *nnew;     // n_k per iteration [kMaxIter] (workspace)
     unsigned int *listlen;        // list length per iteration [kMaxIter] (workspace)
     unsigned long long *work;     // with kCountWork: kWorkCounters counters, or null
+    uint8_t *dirty;               // detection tiles to re-evaluate (kIncremental), row-major
     int H, W;
     float gain, readnoise, sky, sigclip, sigfrac, objlim;
     int niter;

@@ -300,6 +300,7 @@ __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p) {
             v[(dy + 2) * 5 + dx + 2] = f.J[q];
         }
     }
+    const float old = v[12];
     int cnt = 0;
 #pragma unroll
     for (int j = 0; j < 25; ++j) {
@@ -317,7 +318,18 @@ __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p) {
         a = (j == ia) ? v[j] : a;
         b = (j == ib) ? v[j] : b;
     }
-    f.J[p] = (ia == ib) ? a : (float)(((double)a + (double)b) * 0.5);
+    const float nv = (ia == ib) ? a : (float)(((double)a + (double)b) * 0.5);
+    f.J[p] = nv;
+    // incremental detection: a new value dirties every detection tile within
+    // Chebyshev distance 4 (the reach of a code into J)
+    if ((f.flags & kIncremental) && __float_as_uint(nv) != __float_as_uint(old)) {
+        const int tx = (W + kDetectTX - 1) / kDetectTX;
+        const int ty0 = max(y - 4, 0) / kDetectTY, ty1 = min(y + 4, H - 1) / kDetectTY;
+        const int tx0 = max(x - 4, 0) / kDetectTX, tx1 = min(x + 4, W - 1) / kDetectTX;
+        for (int a = ty0; a <= ty1; ++a)
+            for (int b = tx0; b <= tx1; ++b)
+                f.dirty[a * tx + b] = 1;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_list_prefix(const DevFrame *__restrict__ frames,

@@ -171,3 +171,5 @@ def test_counting_and_debug_entry_validation(L):
     assert L.crb_debug_s_estimate(a, ctypes.byref(fr), b, ctypes.c_void_p((1 << 41) + 4)) == -1
     fr.gain = 0.0
     assert L.crb_debug_s_estimate(a, ctypes.byref(fr), b, ctypes.c_void_p(1 << 42)) == -1
+    assert L.crb_set_option(_lib.CRB_OPT_INCREMENTAL, 2) == -1
+    assert L.crb_set_option(_lib.CRB_OPT_INCREMENTAL, 0) == 0
