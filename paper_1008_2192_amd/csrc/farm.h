@@ -10,7 +10,10 @@
 //                frame, which is resident in HBM);
 //   pixel() or candidate() + find(): the per-pixel computation (list functions pass
 //                every pixel through the cheap candidate() test and run find() only on
-//                the candidates, compacted, so that whole waves do the expensive part).
+//                the candidates, compacted, so that whole waves do the expensive part);
+//   kNeighbours + neighbours(): optionally, a necessary condition on the four direct
+//                neighbours that the scan applies where it holds them (others come
+//                as -inf).
 // The farm cuts the frame into tile_h x tile_w rectangles and hands them to a
 // persistent set of waves through atomic tickets, as CRBLASTER's director hands
 // subimages to free actors; adding a work function means adding one struct and one
@@ -25,7 +28,7 @@ namespace crb {
 
 constexpr int kWorkLacosmic = 0, kWorkPoisson = 1, kWorkWaiter = 2, kWorkSources = 3;
 constexpr int kMaxWorkRadius = 8;        // largest radius a work function may declare
-constexpr int kFarmQueues = 8;           // ticket counters (one tile range each)
+constexpr int kFarmQueues = 32;          // ticket counters (one tile range each)
 constexpr int kFarmCandidates = 1024;    // candidates a wave collects before running them
 constexpr int kFarmWaveRecords = 128;    // records a wave buffers before moving them
 

@@ -75,6 +75,12 @@ __device__ __forceinline__ float poisson_deviate(float mean_f, size_t i, uint32_
     }
 }
 
+// A float in the global address space: loads through it are global (not flat) loads.
+typedef __attribute__((address_space(1))) const float GFloat;
+// Fourth word of a raw buffer resource on gfx9-family GPUs: 32-bit data format,
+// range-checked against the byte count given with the base.
+constexpr int kBufWord3 = 0x00020000;
+
 // Where a work function finds its pixel: the frame (resident in HBM; neighbours are
 // read through the caches, never beyond the declared radius) and the position.
 struct FarmCtx {
@@ -84,6 +90,7 @@ struct FarmCtx {
 
 struct WorkPoisson {
     static constexpr bool kList = false;
+    static constexpr bool kNeighbours = false;
     __host__ __device__ static int radius(const WorkArgs &) { return 0; }
     __device__ static float pixel(const FarmCtx &c, const WorkArgs &a) {
         const size_t i = (size_t)c.y * c.W + c.x;
@@ -94,6 +101,7 @@ struct WorkPoisson {
 // WAITER: wait in[i] microseconds (clamped to [0, 1e6]), then copy the pixel.
 struct WorkWaiter {
     static constexpr bool kList = false;
+    static constexpr bool kNeighbours = false;
     __host__ __device__ static int radius(const WorkArgs &) { return 0; }
     __device__ static float pixel(const FarmCtx &c, const WorkArgs &a) {
         const float v = c.in[(size_t)c.y * c.W + c.x];
@@ -123,19 +131,27 @@ template <int R>
 __device__ __forceinline__ bool sources_find(const FarmCtx &c, const WorkArgs &a,
                                              SourceRec &rec) {
     constexpr int K = 2 * R + 1;
-    const float *p = c.in + (size_t)c.y * c.W + c.x;
-    const float v = p[0];
+    const GFloat *in = (const GFloat *)c.in;
+    const float v = in[(size_t)c.y * c.W + c.x];
+    // away from the side edges a row's window is 2R+1 consecutive pixels: one address
+    const bool inner = c.x >= R && c.x + R < c.W;
     bool peak = true;
 #pragma unroll
     for (int dy = -R; dy <= R; ++dy) {
         const int yy = c.y + dy;
         if (dy < -a.r || dy > a.r || yy < 0 || yy >= c.H)
             continue;
-        const float *row = c.in + (size_t)yy * c.W;
+        const GFloat *row = in + (size_t)yy * c.W;
         float q[K];
+        if (inner) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            q[k] = row[min(max(c.x - R + k, 0), c.W - 1)];
+            for (int k = 0; k < K; ++k)
+                q[k] = row[c.x - R + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                q[k] = row[min(max(c.x - R + k, 0), c.W - 1)];
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int dx = k - R, xx = c.x + dx;
@@ -159,11 +175,17 @@ __device__ __forceinline__ bool sources_find(const FarmCtx &c, const WorkArgs &a
         const int yy = c.y + dy;
         if (dy < -a.a || dy > a.a || yy < 0 || yy >= c.H)
             continue;
-        const float *row = c.in + (size_t)yy * c.W;
+        const GFloat *row = in + (size_t)yy * c.W;
         float q[K];
+        if (inner) {
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            q[k] = row[min(max(c.x - R + k, 0), c.W - 1)];
+            for (int k = 0; k < K; ++k)
+                q[k] = row[c.x - R + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                q[k] = row[min(max(c.x - R + k, 0), c.W - 1)];
+        }
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int dx = k - R, xx = c.x + dx;
@@ -229,8 +251,17 @@ __device__ __forceinline__ bool sources_find_loops(const FarmCtx &c, const WorkA
 
 struct WorkSources {
     static constexpr bool kList = true;
+    static constexpr bool kNeighbours = true;
     __host__ __device__ static int radius(const WorkArgs &a) { return a.r > a.a ? a.r : a.a; }
     __device__ static bool candidate(float v, const WorkArgs &a) { return v > a.threshold; }
+    // Necessary for a source when r >= 1: the direct neighbours above and to the left
+    // (earlier in raster order) are smaller, those below and to the right are not
+    // larger.  A neighbour the scan does not know, or that lies outside the frame,
+    // comes as -inf and passes.
+    __device__ static bool neighbours(float v, float up, float dn, float lf, float rt,
+                                      const WorkArgs &a) {
+        return a.r < 1 || (up < v && lf < v && !(dn > v) && !(rt > v));
+    }
     __device__ static bool find(const FarmCtx &c, const WorkArgs &a, SourceRec &rec) {
         switch (radius(a)) {
         case 1: return sources_find<1>(c, a, rec);
@@ -251,8 +282,8 @@ __global__ void k_farm_reset(unsigned int *tickets, unsigned long long *count) {
 
 // The next run of tiles for the calling wave, or t0 = -1 when every queue is drained.
 // Lane 0 takes a ticket from the wave's current queue; once that range is exhausted,
-// lanes 0..7 read all counters at once and the wave moves to the next queue (in
-// cyclic order) that still has tiles.
+// lanes 0..kFarmQueues-1 read all counters at once and the wave moves to the next
+// queue (in cyclic order) that still has tiles.
 __device__ __forceinline__ void next_tiles(unsigned int *__restrict__ tickets, long long ntiles,
                                            int chunk, int &queue, long long &t0, long long &t1) {
     const int lane = __lane_id();
@@ -313,11 +344,15 @@ __device__ __forceinline__ void flush_records(const SourceRec *__restrict__ buf,
 // round-robin to the XCDs, so a queue's tiles mostly stay in one XCD's L2) and works
 // through each tile 64 pixels at a time, with no workgroup barrier.
 //   Image work functions compute every pixel of the tile.
-//   List work functions first scan the tile with kScanBatch loads in flight per lane
-//   and compact the pixels that pass candidate() into a per-wave LDS list; all lanes
-//   then run find() on the list (one candidate per lane) and buffer the records they
-//   find per wave, moving them to the caller's list when the buffer could not take
-//   another pass and at the end.
+//   List work functions first scan the tile with a batch of loads in flight per lane
+//   and compact the pixels that pass candidate() (and, for a function that declares
+//   kNeighbours, neighbours() on the direct neighbours the batch holds) into a
+//   per-wave LDS list; all lanes then run find() on the list (one candidate per lane)
+//   and buffer the records they find per wave, moving them to the caller's list when
+//   the buffer could not take another pass and at the end.  When tile_w is a multiple
+//   of 64 (at most 256, with at most 256 rows) a batch is 16 rows of 64 pixels read by
+//   buffer loads with a uniform row offset, and a tile's candidates gather in one list
+//   (16-bit positions) so that find() runs on full passes.
 template <class WF>
 __global__ __launch_bounds__(256) void k_farm(const float *__restrict__ in, int H, int W,
                                               WorkArgs args, int tile_h, int tile_w, int chunk,
@@ -327,6 +362,7 @@ __global__ __launch_bounds__(256) void k_farm(const float *__restrict__ in, int 
                                               unsigned long long *__restrict__ count,
                                               unsigned int *__restrict__ tickets) {
     constexpr int kScanBatch = 16;
+    constexpr int kBufBatch = 16;   // rows of 64 pixels per batch of the buffer scan
     __shared__ int sCand[WF::kList ? 4 * kFarmCandidates : 1];
     __shared__ SourceRec sRec[WF::kList ? 4 * kFarmWaveRecords : 1];
     const int wave = threadIdx.x >> 6, lane = __lane_id();
@@ -369,7 +405,97 @@ __global__ __launch_bounds__(256) void k_farm(const float *__restrict__ in, int 
                     }
                 }
             } else {
+                // candidates run on one lane each; the find pass over the list
+                uint16_t *const cand16 = reinterpret_cast<uint16_t *>(cand);
+                auto run_candidates = [&](int ncand, bool packed) {
+                    for (int i0 = 0; i0 < ncand; i0 += 64) {
+                        SourceRec rec;
+                        bool found = false;
+                        if (i0 + lane < ncand) {
+                            const int p = packed ? (int)cand16[i0 + lane] : cand[i0 + lane];
+                            c.y = y0 + (packed ? (p >> 8) : p / tw);
+                            c.x = x0 + (packed ? (p & 0xFF) : p % tw);
+                            found = WF::find(c, args, rec);
+                        }
+                        const unsigned long long m = __ballot(found);
+                        if (found)
+                            rbuf[nrec + __popcll(m & ((1ull << lane) - 1ull))] = rec;
+                        nrec += __popcll(m);
+                        if (nrec > kFarmWaveRecords - 64) {
+                            flush_records(rbuf, nrec, out_list, capacity, count);
+                            nrec = 0;
+                        }
+                    }
+                };
                 int ncand = 0;
+                if ((tile_w & 63) == 0 && tile_w <= 256 && th <= 256 &&
+                    (long long)(th - 1) * W + tw < (1ll << 29)) {
+                    // rows of whole 64-pixel segments: buffer loads over the tile's rows
+                    // with the lane's byte offset and a uniform segment offset, so a load
+                    // costs no vector instruction; candidates packed in 16 bits as
+                    // (row << 8) | col, so twice as many wait for a full pass
+                    const int nseg = tile_w >> 6;
+                    const long long steps = (long long)th * nseg;
+                    const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
+                        (void *)(in + (size_t)y0 * W + x0), (short)0,
+                        (int)(((long long)(th - 1) * W + tw) * 4), kBufWord3);
+                    float carry = -INFINITY;        // the row above a batch (nseg == 1)
+                    // batch s0: rows of 64 pixels s0 .. s0+kBufBatch-1 in segment order
+                    auto load_batch = [&](float (&v)[kBufBatch], long long s0) {
+                        int row = (int)(s0 / nseg), seg = (int)(s0 - (long long)row * nseg);
+#pragma unroll
+                        for (int b = 0; b < kBufBatch; ++b) {
+                            v[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                rows, lane * 4, s0 + b < steps ? (row * W + seg * 64) * 4 : 0,
+                                0));
+                            if (++seg == nseg) {
+                                seg = 0;
+                                ++row;
+                            }
+                        }
+                    };
+                    for (long long s0 = 0; s0 < steps; s0 += kBufBatch) {
+                        float v[kBufBatch];
+                        load_batch(v, s0);
+                        int row = (int)(s0 / nseg), seg = (int)(s0 - (long long)row * nseg);
+#pragma unroll
+                        for (int b = 0; b < kBufBatch; ++b) {
+                            const int col = seg * 64 + lane;
+                            bool hit = s0 + b < steps && col < tw && WF::candidate(v[b], args);
+                            if constexpr (WF::kNeighbours) {
+                                // direct neighbours this batch holds (same row: adjacent
+                                // lanes; rows above and below: adjacent batch entries
+                                // when a row is one segment)
+                                const float lf = __shfl_up(v[b], 1), rt = __shfl_down(v[b], 1);
+                                float up = -INFINITY, dn = -INFINITY;
+                                if (nseg == 1) {
+                                    up = b > 0 ? v[b > 0 ? b - 1 : 0] : carry;
+                                    if (b + 1 < kBufBatch && s0 + b + 1 < steps)
+                                        dn = v[b + 1 < kBufBatch ? b + 1 : b];
+                                }
+                                hit = hit && WF::neighbours(v[b], up, dn,
+                                                           lane > 0 ? lf : -INFINITY,
+                                                           lane < 63 && col + 1 < tw
+                                                               ? rt : -INFINITY, args);
+                            }
+                            const unsigned long long m = __ballot(hit);
+                            if (hit)
+                                cand16[ncand + __popcll(m & ((1ull << lane) - 1ull))] =
+                                    (uint16_t)((row << 8) | col);
+                            ncand += __popcll(m);
+                            if (++seg == nseg) {
+                                seg = 0;
+                                ++row;
+                            }
+                        }
+                        carry = v[kBufBatch - 1];
+                        if (ncand > 2 * kFarmCandidates - kBufBatch * 64 ||
+                            s0 + kBufBatch >= steps) {
+                            run_candidates(ncand, true);
+                            ncand = 0;
+                        }
+                    }
+                } else {
                 long long j0 = 0;
                 while (j0 < n) {
                     // scan up to kScanBatch passes, all loads first
@@ -402,26 +528,10 @@ __global__ __launch_bounds__(256) void k_farm(const float *__restrict__ in, int 
                     // run the candidates when the list could not take another batch,
                     // and at the end of the tile
                     if (ncand > kFarmCandidates - kScanBatch * 64 || j0 >= n) {
-                        for (int i0 = 0; i0 < ncand; i0 += 64) {
-                            SourceRec rec;
-                            bool found = false;
-                            if (i0 + lane < ncand) {
-                                const int p = cand[i0 + lane];
-                                c.y = y0 + p / tw;
-                                c.x = x0 + p % tw;
-                                found = WF::find(c, args, rec);
-                            }
-                            const unsigned long long m = __ballot(found);
-                            if (found)
-                                rbuf[nrec + __popcll(m & ((1ull << lane) - 1ull))] = rec;
-                            nrec += __popcll(m);
-                            if (nrec > kFarmWaveRecords - 64) {
-                                flush_records(rbuf, nrec, out_list, capacity, count);
-                                nrec = 0;
-                            }
-                        }
+                        run_candidates(ncand, false);
                         ncand = 0;
                     }
+                }
                 }
             }
         }
@@ -437,10 +547,10 @@ hipError_t launch_kind(const WorkArgs &args, const float *in, int H, int W, int 
                        int tile_h, int tile_w, float *out_img, SourceRec *out_list,
                        long long capacity, unsigned long long *count, unsigned int *tickets,
                        hipStream_t s) {
-    // tickets of `chunk` tiles: about 8 per wave, so the dynamic balance keeps a fine
-    // grain while the counters take few atomics
+    // tickets of `chunk` tiles: about 2 per wave; atomics on a ticket counter serialise
+    // in its L2, so few and spread over kFarmQueues counters keep them off the path
     const long long ntiles = (long long)((W - 1) / tile_w + 1) * ((H - 1) / tile_h + 1);
-    long long chunk = ntiles / ((long long)workers * 8);
+    long long chunk = ntiles / ((long long)workers * 2);
     chunk = chunk < 1 ? 1 : (chunk > 64 ? 64 : chunk);
     const int blocks = (workers + 3) / 4;
     k_farm<WF><<<blocks, 256, 0, s>>>(in, H, W, args, tile_h, tile_w, (int)chunk, workers,
