@@ -299,20 +299,25 @@ def main():
     # per launch: the step's 4 detection launches share the counted work equally on average
     work_px = work["work_pixels"] / 4.0
     contrast = work["contrast_tests"] / 4.0
-    ops_launch = roofline.detect_ops_per_launch(total_px, work_px, contrast)
+    exact_px = work["exact_med5"] / 4.0
+    ops_launch = roofline.detect_ops_per_launch(total_px, exact_px, work_px, contrast)
     achieved = ops_launch / det_avg_s                      # lane-ops per second
     o = roofline.detect_ops()
-    roof = {"bound": "alu", "kernel": "k_detect (detection: med3 and med5 networks, L+ and an "
-                                      "FP32 estimate of S with its error bound everywhere; "
-                                      "med5(S), S' and the threshold bits on the work set; med7 "
-                                      "and F^ where S' > sigclip; binary64 re-evaluation where "
-                                      "the bound cannot decide)",
+    roof = {"bound": "alu", "kernel": "k_detect (detection: med3, a lower bound of med5(J), L+ "
+                                      "and the upper bound of S it gives everywhere; the med5 "
+                                      "network and the FP32 estimate of S with its error bound "
+                                      "within 4 px of where S may exceed sigclip; med5(S), S' "
+                                      "and the threshold bits on the work set; F^ by counting "
+                                      "where S' > sigclip; binary64 re-evaluation where the "
+                                      "bound cannot decide)",
             "achieved": round(achieved / 1e12, 3), "peak": round(roofline.ALU_PEAK / 1e12, 3),
             "unit": "Tlane-op/s", "frac": round(achieved / roofline.ALU_PEAK, 4),
             "traffic": profiled_traffic() if args.workload == "c4" else None,
             "ops_per_launch": round(ops_launch),
             "ops_per_pixel": round(ops_launch / total_px, 2),
             "dense_ops_per_pixel": round(o["dense"]["total"], 2),
+            "ops_per_exact_med5_pixel": round(o["per_exact_pixel"], 2),
+            "exact_med5_pixels_per_launch": round(exact_px),
             "ops_per_work_pixel": round(o["per_work_pixel"], 2),
             "ops_per_contrast_test": round(o["per_contrast"], 2),
             "work_pixels_per_launch": round(work_px), "contrast_tests_per_launch": round(contrast),

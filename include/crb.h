@@ -152,8 +152,12 @@ crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
  * tests and its number of re-evaluations; crb_plan_set_counting (which waits for the
  * plan's stream) clears the counters, crb_plan_work_counts waits for the stream and
  * returns the totals over all frames since then: counts[0] work-set pixels,
- * counts[1] contrast tests, counts[2] binary64 re-evaluations (counts has 3
- * elements). */
+ * counts[1] contrast tests, counts[2] binary64 re-evaluations, counts[3] pixels whose
+ * med5(J) was selected exactly (counts has 4 elements).  med5(J) and the estimate of
+ * S are needed only within 4 pixels of a pixel where S may exceed sigclip; the
+ * detection finds those pixels from a cheap lower bound of med5(J) (S does not grow
+ * with it) and selects med5(J) only in the vertical pixel pairs that meet that
+ * region. */
 crb_status crb_plan_set_counting(crb_plan *plan, int32_t enable);
 crb_status crb_plan_work_counts(crb_plan *plan, int64_t *counts);
 
@@ -329,7 +333,8 @@ crb_status crb_debug_detect_exact(const float *J, const crb_frame *params,
 crb_status crb_debug_s_estimate(const float *J, const crb_frame *params, float *out_s,
                                 float *out_err);
 /* Clamped (2r+1)^2 median filter, r in {1, 2, 3}, by the kernels' networks (3x3 by
- * sorted columns, 5x5 by the 2 x 5 output network, 7x7 by the single-output one). */
+ * sorted columns, 5x5 by the network for a vertical pair of outputs, 7x7 by the
+ * single-output one). */
 crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out);
 /* Clamped 5x5 median filter of binary64 values by the single-output network the
  * detection applies to S. */

@@ -263,11 +263,13 @@ class Plan:
 
     def work_counts(self) -> dict:
         """Detection work since counting was enabled: work-set pixels (med5 of S and
-        the threshold bits), contrast tests (S'/F^ > objlim) and binary64
-        re-evaluations (work-set pixels the FP32 estimate of S could not decide)."""
-        c = (ctypes.c_int64 * 3)()
+        the threshold bits), contrast tests (S'/F^ > objlim), binary64 re-evaluations
+        (work-set pixels the FP32 estimate of S could not decide) and pixels whose
+        med5(J) was selected exactly (those near a pixel where S may exceed sigclip)."""
+        c = (ctypes.c_int64 * 4)()
         check("crb_plan_work_counts", lib().crb_plan_work_counts(self.handle, c))
-        return dict(work_pixels=int(c[0]), contrast_tests=int(c[1]), reevaluated=int(c[2]))
+        return dict(work_pixels=int(c[0]), contrast_tests=int(c[1]), reevaluated=int(c[2]),
+                    exact_med5=int(c[3]))
 
     def close(self) -> None:
         if self.handle:

@@ -114,6 +114,34 @@ __device__ __forceinline__ float s_estimate(float c, float up, float dn, float l
     return sane ? s : INFINITY;
 }
 
+// The factor R = (g/8) t^-1/2 of the S estimate, t = g m + rn^2, for a lower bound x of
+// med5(J): m = x + sky, or 0 where that is at most 1e-4 (N of the definition never falls
+// below rn/g, while above the definition's floor it grows with med5(J)), so the estimate
+// from R, with its error bound, bounds S from above for every med5(J) >= x.  INFINITY
+// where the error analysis of the estimate does not hold.
+__device__ __forceinline__ float r_bound(float x, const SEstParams &p) {
+    float m = x + p.sky;
+    m = (m <= 1e-4f) ? 0.0f : m;
+    const float t = fmaf(p.gain, m, p.rn2);
+    const bool sane = __builtin_amdgcn_fmed3f(t, 0x1p-100f, 0x1p100f) == t && p.ok;
+    return sane ? p.g8 * __builtin_amdgcn_rsqf(t) : INFINITY;
+}
+
+// Whether S may exceed thr at a pixel of value c with 4-neighbours up, dn, lf, rt, given
+// R = r_bound(x) for a lower bound x of its med5(J): the S estimate and its error bound
+// evaluated as s_estimate does; true where R is not finite or M > 2^100 (inputs are
+// finite, so no value here is a NaN once those are excluded).
+__device__ __forceinline__ bool s_may_exceed(float c, float up, float dn, float lf, float rt,
+                                             float R, float thr) {
+    const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
+    const float l4 = (fmaxf(a - lf, 0.0f) + fmaxf(a - rt, 0.0f)) +
+                     (fmaxf(b - lf, 0.0f) + fmaxf(b - rt, 0.0f));
+    const float s = l4 * R;
+    const float M = fmaf(4.0f, fabsf(c), fabsf(up)) + fabsf(dn) + (fabsf(lf) + fabsf(rt));
+    const float err = (M * R + s) * 0x1p-19f;
+    return !(R < INFINITY) || !(M <= 0x1p100f) || s + err > thr;
+}
+
 // S exactly as the definition evaluates it (binary64, in its operation order), at the
 // in-frame pixel (y, x) of J (clamped neighbours), read from global memory.
 __device__ __forceinline__ double s_exact(const float *__restrict__ J, int H, int W, int y, int x,
@@ -141,22 +169,49 @@ __device__ __forceinline__ double noise_exact(float m5, double gain, double sky,
     return sqrt(gain * m + rn2) / gain;
 }
 
-// F^ = max((med3 - med7(med3)) / N, 0.01) at a tile pixel whose med3 cell is pm.
-__device__ __forceinline__ double fine_structure(const float *pm, int mpitch, double N) {
+// med3(J) at the pixel whose staged J cell is p (pitch jp).  The staged plane holds
+// J at clamped positions, so for an in-frame pixel this is the clamped 3 x 3 window:
+// with each column sorted, the median of nine is the median of the largest column
+// minimum, the median of the column medians and the smallest column maximum.
+__device__ __forceinline__ float med3_at(const float *p, int jp) {
+    float lo[3], mi[3], hi[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float a = p[-jp + j - 1], b = p[j - 1], c = p[jp + j - 1];
+        lo[j] = min3f(a, b, c);
+        mi[j] = med3f(a, b, c);
+        hi[j] = max3f(a, b, c);
+    }
+    return med3f(max3f(lo[0], lo[1], lo[2]), med3f(mi[0], mi[1], mi[2]),
+                 min3f(hi[0], hi[1], hi[2]));
+}
+
+// Staged J cell (pitch jp, apron 4 around the tile at (y0, x0)) of the in-frame pixel
+// nearest to tile position (r + dy, c + dx): where med3(J) is read for the 7 x 7 window
+// of a tile pixel (the window is clamped to the frame).
+__device__ __forceinline__ const float *med3_cell(const float *sJ, int jp, int y0, int x0,
+                                                  int H, int W, int r, int c, int dy, int dx) {
+    return &sJ[(clampi(y0 + r + dy, H) - y0 + 4) * jp + (clampi(x0 + c + dx, W) - x0 + 4)];
+}
+
+// F^ = max((med3 - med7(med3)) / N, 0.01) at tile pixel (r, c), binary64, with med3
+// taken from the staged J.
+__device__ __forceinline__ double fine_structure(const float *sJ, int jp, int y0, int x0,
+                                                 int H, int W, int r, int c, double N) {
     float w7[49], m7[1];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
 #pragma unroll
         for (int j = 0; j < 7; ++j)
-            w7[i * 7 + j] = pm[(i - 3) * mpitch + (j - 3)];
+            w7[i * 7 + j] = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, i - 3, j - 3), jp);
     med7_t1x1(w7, m7);
     double fh = ((double)w7[24] - (double)m7[0]) / N;
     return fh < 0.01 ? 0.01 : fh;
 }
 
-// The contrast test S'/F^ > objlim at a tile pixel whose med3 cell is pm and whose
-// med5(J) is m5, for every S' in [lo, hi] (0 < lo), without selecting med7: 1 if it
-// holds for all of them, 0 if it fails for all, -1 if undecided.
+// The contrast test S'/F^ > objlim at tile pixel (r, c), for every S' in [lo, hi]
+// (0 < lo), without selecting med7, by the calling wave (all lanes active, arguments
+// uniform): 1 if it holds for all of them, 0 if it fails for all, -1 if undecided.
 //   F^ does not increase with med7 (m3 - med7, the division by N > 0, the floor at 0.01
 //   and their roundings are monotone), so at fixed S' the test, as a function of the
 //   value x taken by med7, holds above a switching value and nowhere below it; med7 is
@@ -164,38 +219,46 @@ __device__ __forceinline__ double fine_structure(const float *pm, int mpitch, do
 //   at 25 or more of them.
 //   If fl(S'/0.01) <= objlim the test fails whatever x (F^ >= 0.01); 100 S' in FP32 is
 //   within 1.01u of that binary64 quotient (u = 2^-24), so comparing it with objlim
-//   widened or narrowed by 2^-21 relative decides this for the whole interval.
+//   widened or narrowed by 2^-21 relative decides this for the whole interval (the
+//   caller does, before listing the pixel).
 //   Otherwise the test holds at x iff m3 - x < K (1 + e), K = N S'/objlim, |e| <=
 //   4 * 2^-53.  K from N in FP32 (within 8u: t = g m + rn^2 to 3.03u, its reciprocal
 //   square root to 1 ulp, two products) and two more products is within 11u, so x above
 //   T = m3 - K up to a band of 2^-19 (|m3| + K) + 2^-126 (three-fold the roundings)
 //   decides the test.  The test is larger for larger S', so lo bounds its certain
 //   holding and hi its possible holding.
-__device__ __forceinline__ int contrast_by_count(const float *pm, int mpitch, float m5,
+// Lane l < 25 holds the value of med5(J)'s window cell (l / 5 - 2, l % 5 - 2), and the
+// median is the value with at most 12 smaller and at least 13 not larger; lane l < 49
+// takes the med3 value of window cell (l / 7 - 3, l % 7 - 3), and ballots count them.
+__device__ __forceinline__ int contrast_by_count(const float *sJ, int jp, int y0, int x0,
+                                                 int H, int W, int r, int c,
                                                  const SEstParams &p, float lo, float hi,
-                                                 float olim_lo, float olim_hi, float inv_olim) {
-    if (hi * 100.0f <= olim_lo)
-        return 0;
-    if (!(lo * 100.0f > olim_hi))
-        return -1;
+                                                 float inv_olim, int lane) {
+    const int l25 = lane < 25 ? lane : 12;
+    const float jv = sJ[(r + 2 + l25 / 5) * jp + (c + 2 + l25 % 5)];
+    int lt = 0, le = 0;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+        const float u = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(jv), k));
+        lt += u < jv ? 1 : 0;
+        le += u <= jv ? 1 : 0;
+    }
+    const unsigned long long hold = __ballot(lane < 25 && lt <= 12 && le >= 13);
+    const float m5 = __int_as_float(
+        __builtin_amdgcn_readlane(__float_as_int(jv), (int)__ffsll((long long)hold) - 1));
+    const int l49 = lane < 49 ? lane : 24;
+    const float x = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, l49 / 7 - 3, l49 % 7 - 3), jp);
+    const float m3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 24));
     float m = m5 + p.sky;
     m = (m <= 0.0f) ? 1e-4f : m;
     const float t = fmaf(p.gain, m, p.rn2);
     const float N = t * __builtin_amdgcn_rsqf(t) * p.inv_gain;
-    const float m3 = pm[0];
     const float klo = N * lo * inv_olim, khi = N * hi * inv_olim;
     // x > t_sure: holds for every S' >= lo; x >= t_maybe: may hold for some S' <= hi
     const float t_sure = (m3 - klo) + fmaf(0x1p-19f, fabsf(m3) + klo, 0x1p-126f);
     const float t_maybe = (m3 - khi) - fmaf(0x1p-19f, fabsf(m3) + khi, 0x1p-126f);
-    int sure = 0, maybe = 0;
-#pragma unroll
-    for (int i = 0; i < 7; ++i)
-#pragma unroll
-        for (int j = 0; j < 7; ++j) {
-            const float x = pm[(i - 3) * mpitch + (j - 3)];
-            sure += x > t_sure ? 1 : 0;
-            maybe += x >= t_maybe ? 1 : 0;
-        }
+    const int sure = __popcll(__ballot(lane < 49 && x > t_sure));
+    const int maybe = __popcll(__ballot(lane < 49 && x >= t_maybe));
     return sure >= 25 ? 1 : (maybe < 25 ? 0 : -1);
 }
 
@@ -232,25 +295,26 @@ __device__ __forceinline__ int bitmap_select64(const uint32_t *bits, const uint3
     return lo * 32 + __ffs(b) - 1;
 }
 
-// Work shapes inside a detection block: med3 in runs of kRun3 outputs; med5(J) with
-// L+ and the S estimate in 2 x 5 thread tiles over the whole tile and its 2-pixel
-// apron.  The remaining statistics are evaluated only where a code bit can matter.
+// Work shapes inside a detection block: med3 in runs of kRun3 outputs; a lower bound of
+// med5(J), L+ and an upper bound of S in 2 x 5 thread tiles over the whole tile and its
+// 2-pixel apron; med5(J) and the S estimate in vertical pairs near where S may exceed
+// sigclip.  The remaining statistics are evaluated only where a code bit can matter.
 constexpr int kRun3 = 14;
 // pixels per round of the binary64 re-evaluation (25 threads each)
 constexpr int kExactBatch = kThreads / 25;
+// pixels whose contrast test a block lists for its contrast phase (further ones are
+// re-evaluated in binary64)
+constexpr int kConMax = 128;
 
 template <int TY, int TX>
 struct DetectLayout {
     // logical extents of the LDS planes and their row pitches; the pitches spread the
     // stage-1 and stage-2 scalar accesses over the LDS banks
     static constexpr int JH = TY + 8, JW = TX + 8, JWP = TX + 11;   // J, apron 4
-    static constexpr int MH = TY + 6, MW = TX + 6, MWP = TX + 12;   // med3(J), apron 3
     static constexpr int SH = TY + 4, SW = TX + 4, SWP = TX + 6;    // S estimate, apron 2
     static constexpr int HW = (SW + 31) / 32;   // words per row of the hot bitmap
     static constexpr int QW = TX / 32;          // words per row of the tile bitmaps
     static constexpr int kTileWords = TY * QW;
-    // the J buffer later holds med5(J) of the tile and a list of up to TY*TX positions
-    static constexpr int kJBuf = (JH * JWP > TY * TX * 3 / 2) ? JH * JWP : TY * TX * 3 / 2;
     static_assert(TX % 32 == 0 && kTileWords == 64, "one wave scans a tile bitmap");
     static_assert(QW + 1 <= HW, "dilation reads two bitmap words per work word");
     static_assert(SH * SWP * 4 >= kExactBatch * 25 * 8, "re-evaluation buffer in the S plane");
@@ -272,21 +336,22 @@ struct DetectLayout {
 // every code written is the full definition's, codes outside Q' are 0, and the grow,
 // which reads codes only through its two dilations, sees the full definition.
 template <int TY, int TX>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))
 void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
               DevFrame single, int kiter) {
     using L = DetectLayout<TY, TX>;
-    // J; later med5(J) of the tile followed by the work list
-    __shared__ __align__(16) float sJ[L::kJBuf];
-    __shared__ __align__(16) float sM3[L::MH * L::MWP];
+    __shared__ __align__(16) float sJ[L::JH * L::JWP];       // J, clamped extension
     __shared__ __align__(16) float sS[L::SH * L::SWP];      // later: re-evaluation buffer
     __shared__ __align__(16) uint8_t sCode[TY * TX];
     __shared__ uint32_t sHot[L::SH * L::HW];                // H', apron 2, in-frame
     __shared__ uint32_t sU[L::kTileWords], sUpre[L::kTileWords + 1];
-    __shared__ unsigned int sErrBits, sContrast, sUncertain, sQcount;
+    __shared__ unsigned int sErrBits, sContrast, sUncertain, sQcount, sNeedCount, sExactCells,
+        sConCount;
     double *const sX = reinterpret_cast<double *>(sS);
-    float *const sM5 = sJ;      // med5(J) of the tile, once the staged J is consumed
-    uint16_t *const sList = reinterpret_cast<uint16_t *>(sJ + TY * TX);   // work set Q'
+    __shared__ uint16_t sList[TY * TX];                     // work set Q'
+    // pixels whose contrast test is left to the contrast phase: position, S' interval
+    __shared__ uint32_t sConInfo[kConMax];
+    __shared__ float sConLo[kConMax], sConHi[kConMax];
 
     DevFrame f;
     int y0, x0;
@@ -332,6 +397,9 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         sQcount = 0u;
         sContrast = 0u;
         sUncertain = 0u;
+        sNeedCount = 0u;
+        sExactCells = 0u;
+        sConCount = 0u;
     }
     // J over [y0-4, y0+TY+4) x [x0-4, x0+TX+4), clamped reads.  Thread t loads column
     // t % JW of rows t / JW + kJStep * b, so its clamped column is computed once and, on
@@ -389,94 +457,167 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         }
     }
 
-    // med3(J) over [y0-3, y0+TY+3) x [x0-3, x0+TX+3)
-    {
-        constexpr int NRX = (L::MW + kRun3 - 1) / kRun3;
-        for (int t = tid; t < L::MH * NRX; t += kThreads) {
-            const int r = t / NRX;
-            const int cx = min((t - r * NRX) * kRun3, L::MW - kRun3);
-            float a[kRun3 + 2], b[kRun3 + 2], c[kRun3 + 2], o[kRun3];
-#pragma unroll
-            for (int j = 0; j < kRun3 + 2; ++j) {
-                a[j] = sJ[r * L::JWP + cx + j];
-                b[j] = sJ[(r + 1) * L::JWP + cx + j];
-                c[j] = sJ[(r + 2) * L::JWP + cx + j];
-            }
-            med3_run<kRun3>(a, b, c, o);
-#pragma unroll
-            for (int j = 0; j < kRun3; ++j)
-                sM3[r * L::MWP + cx + j] = o[j];
-        }
-    }
-
-    // med5(J), L+ and the S estimate over [y0-2, y0+TY+2) x [x0-2, x0+TX+2) in one
-    // 2 x 5 tile per thread; marks H' and takes the block's largest error bound.  The
-    // tile's med5(J) is kept in registers and stored over J after the barrier.
+    // Over [y0-2, y0+TY+2) x [x0-2, x0+TX+2), in one 2 x 5 cell tile per thread.
+    // Dense pass: a lower bound x of med5(J) shared by the tile's ten windows (the least
+    // of the column medians of its 6 x 9 patch: every window holds five of those columns,
+    // each with three values at or above its median, so 15 of its 25 values are >= x);
+    // S does not increase with med5(J), so the estimate at x with its error bound bounds
+    // S from above, and H' = the in-frame cells where that bound exceeds sigclip (less a
+    // margin) holds H.
     constexpr int TTY = 2, TTX = 5, PW = TTX + 4;
     constexpr int NTY = (L::SH + TTY - 1) / TTY, NTX = (L::SW + TTX - 1) / TTX;
     static_assert(NTY * NTX <= kThreads, "one pass of 2 x 5 tiles");
-    float m5[TTY * TTX];
-    int r5 = 0, c5 = 0;
+    const SEstParams sp = sest_params(f);
+    const int lane = tid & 63;
+    if (tid < NTY * NTX) {
+        const int ty = tid / NTX;
+        const int r5 = min(ty * TTY, L::SH - TTY);
+        const int c5 = min((tid - ty * NTX) * TTX, L::SW - TTX);
+        float v[(TTY + 4) * PW];
+#pragma unroll
+        for (int i = 0; i < TTY + 4; ++i)
+#pragma unroll
+            for (int j = 0; j < PW; ++j)
+                v[i * PW + j] = sJ[(r5 + i) * L::JWP + c5 + j];
+        // column medians of rows 0-4 and 1-5: the median of five values is the median of
+        // the fifth, the larger of the two pair minima and the smaller of the two pair
+        // maxima; rows 1-4 form the pairs of both
+        float x = INFINITY;
+#pragma unroll
+        for (int j = 0; j < PW; ++j) {
+            const float a = v[PW + j], b = v[2 * PW + j], c = v[3 * PW + j], d = v[4 * PW + j];
+            const float lo = fmaxf(fminf(a, b), fminf(c, d)), hi = fminf(fmaxf(a, b), fmaxf(c, d));
+            x = min3f(x, med3f(v[j], lo, hi), med3f(v[5 * PW + j], lo, hi));
+        }
+        const float R = r_bound(x, sp);
+#pragma unroll
+        for (int i = 0; i < TTY; ++i) {
+#pragma unroll
+            for (int j = 0; j < TTX; ++j) {
+                const int pc = (i + 2) * PW + (j + 2);
+                const int gy = y0 - 2 + r5 + i, gx = x0 - 2 + c5 + j;
+                if (s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], R, sc_lo) &&
+                    gy >= 0 && gy < H && gx >= 0 && gx < W)
+                    atomicOr(&sHot[(r5 + i) * L::HW + ((c5 + j) >> 5)], 1u << ((c5 + j) & 31));
+            }
+        }
+    }
+    __syncthreads();
+    // The later stages read S (to within the block's largest error bound) and med5(J)
+    // only within 4 cells of H': the work set lies within 2 of H', and med5(S) at a work
+    // pixel reads 2 further (a clamped neighbour's cell is no farther).  That region, in
+    // 2 x 1 cell pairs (row pair p, column c: a bit per pair, one 32-column word per
+    // thread), is listed by the first wave and the pairs take the exact med5 network in
+    // list order, which spreads them evenly over the block's waves.
+    constexpr int NP = L::SH / 2;
+    static_assert(L::SH % 2 == 0 && NP * L::HW <= 64, "one bitmap word per lane of a wave");
+    static_assert(NP * L::SW <= 2048, "pair index in 16 bits");
+    constexpr int kPairListMax = TY * TX / 2;    // uint16 entries the code plane can hold
+    constexpr int kPairRounds = (NP * L::SW + kThreads - 1) / kThreads;
+    uint16_t *const sPairs = reinterpret_cast<uint16_t *>(sCode);   // codes start later
+    if (tid < 64) {
+        uint32_t m = 0u;
+        if (tid < NP * L::HW) {
+            const int pr = tid / L::HW, w = tid - pr * L::HW;
+            uint32_t a = 0u, b = 0u, c = 0u;        // words w - 1, w, w + 1 of the rows
+            for (int rr = max(2 * pr - 4, 0); rr <= min(2 * pr + 5, L::SH - 1); ++rr) {
+                const uint32_t *row = &sHot[rr * L::HW];
+                b |= row[w];
+                if (w > 0)
+                    a |= row[w - 1];
+                if (w + 1 < L::HW)
+                    c |= row[w + 1];
+            }
+            // column 32w + k is needed when a bit lies in columns 32w + k - 4 .. + 4
+            const unsigned long long hi = ((unsigned long long)c << 32) | b;
+            const unsigned long long lo = ((unsigned long long)b << 32) | a;
+#pragma unroll
+            for (int d = 0; d <= 4; ++d)
+                m |= (uint32_t)(hi >> d);
+#pragma unroll
+            for (int d = 1; d <= 4; ++d)
+                m |= (uint32_t)(lo >> (32 - d));
+            const int valid = L::SW - 32 * w;
+            if (valid < 32)
+                m &= (1u << valid) - 1u;
+        }
+        const unsigned int cnt = (unsigned int)__popc(m);
+        unsigned int incl = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned int u = (unsigned int)__shfl_up((int)incl, o);
+            if (tid >= o)
+                incl += u;
+        }
+        const unsigned int total = (unsigned int)__builtin_amdgcn_readlane((int)incl, 63);
+        if (total <= (unsigned int)kPairListMax) {
+            unsigned int at = incl - cnt;
+            const int pr = tid / L::HW, w = tid - pr * L::HW;
+            for (uint32_t mm = m; mm; mm &= mm - 1u)
+                sPairs[at++] = (uint16_t)(pr * L::SW + 32 * w + __ffs(mm) - 1);
+        }
+        if (tid == 0)
+            sNeedCount = total;
+    }
+    __syncthreads();
+    // Exact pass: med5(J), L+ and the S estimate with its error bound; the block's largest
+    // bound is taken over these cells, the only ones read, and H' drops the cells where
+    // the estimate at med5(J) settles S <= sigclip (so H' is {s + err > sigclip less the
+    // margin} on the in-frame cells, as with the estimate everywhere).  A list too long
+    // for the code plane stands for every pair.
+    const int npairs = (int)sNeedCount;
+    const bool every_pair = npairs > kPairListMax;
+    const int nitems = every_pair ? NP * L::SW : npairs;
     {
-        const SEstParams sp = sest_params(f);
         float emax = 0.0f;
-        if (tid < NTY * NTX) {
-            const int ty = tid / NTX;
-            r5 = min(ty * TTY, L::SH - TTY);
-            c5 = min((tid - ty * NTX) * TTX, L::SW - TTX);
-            float v[(TTY + 4) * PW];
+        unsigned int ncells = 0u;
 #pragma unroll
-            for (int i = 0; i < TTY + 4; ++i)
+        for (int rd = 0; rd < kPairRounds; ++rd) {
+            const int it = tid + rd * kThreads;
+            if (it < nitems) {
+                const int q = every_pair ? it : (int)sPairs[it];
+                const int pr = q / L::SW, cc = q - pr * L::SW, r0 = 2 * pr;
+                float v[6 * 5];
 #pragma unroll
-                for (int j = 0; j < PW; ++j)
-                    v[i * PW + j] = sJ[(r5 + i) * L::JWP + c5 + j];
-            med5_t2x5(v, m5);
+                for (int i = 0; i < 6; ++i)
 #pragma unroll
-            for (int i = 0; i < TTY; ++i) {
+                    for (int j = 0; j < 5; ++j)
+                        v[i * 5 + j] = sJ[(r0 + i) * L::JWP + cc + j];
+                float m5[2];
+                med5_t2x1(v, m5);
 #pragma unroll
-                for (int j = 0; j < TTX; ++j) {
-                    const int pc = (i + 2) * PW + (j + 2);
+                for (int i = 0; i < 2; ++i) {
+                    const int pc = (i + 2) * 5 + 2;
                     float err;
-                    const float s = s_estimate(v[pc], v[pc - PW], v[pc + PW], v[pc - 1],
-                                               v[pc + 1], m5[i * TTX + j], sp, err);
-                    sS[(r5 + i) * L::SWP + c5 + j] = s;
+                    const float s = s_estimate(v[pc], v[pc - 5], v[pc + 5], v[pc - 1], v[pc + 1],
+                                               m5[i], sp, err);
+                    sS[(r0 + i) * L::SWP + cc] = s;
                     emax = fmaxf(emax, err);
-                    const int gy = y0 - 2 + r5 + i, gx = x0 - 2 + c5 + j;
-                    if (s + err > sc_lo && gy >= 0 && gy < H && gx >= 0 && gx < W)
-                        atomicOr(&sHot[(r5 + i) * L::HW + ((c5 + j) >> 5)],
-                                 1u << ((c5 + j) & 31));
+                    // H' keeps the cells whose estimate at med5(J) may exceed sigclip
+                    uint32_t *hw = &sHot[(r0 + i) * L::HW + (cc >> 5)];
+                    const uint32_t hb = 1u << (cc & 31);
+                    if (!(s + err > sc_lo) && (*hw & hb))
+                        atomicAnd(hw, ~hb);
+                    const int cy = r0 + i - 2, cx = cc - 2;
+                    ncells += (cy >= 0 && cy < TY && cx >= 0 && cx < TX) ? 1u : 0u;
                 }
             }
         }
         // non-negative floats order as their bit patterns: the device library's
         // cross-lane (DPP) maximum, then one LDS atomic per wave
         emax = __uint_as_float(__ockl_wfred_max_u32(__float_as_uint(emax)));
-        if ((tid & 63) == 0)
+        if (lane == 0)
             atomicMax(&sErrBits, __float_as_uint(emax));
+        if (f.flags & kCountWork) {
+            ncells = __ockl_wfred_add_u32(ncells);
+            if (lane == 0 && ncells)
+                atomicAdd(&sExactCells, ncells);
+        }
     }
     __syncthreads();
-    // med5(J) at the tile's pixels, over the staged J (no longer read)
-    if (tid < NTY * NTX) {
-#pragma unroll
-        for (int i = 0; i < TTY; ++i)
-#pragma unroll
-            for (int j = 0; j < TTX; ++j) {
-                const int ty = r5 + i - 2, tx = c5 + j - 2;
-                if (ty >= 0 && ty < TY && tx >= 0 && tx < TX)
-                    sM5[ty * TX + tx] = m5[i * TTX + j];
-            }
-    }
-
-    // Region cells outside the image must hold the value of their clamped cell:
-    // the windows of the work set read med3 and S at clamped neighbour positions.
-    if (y0 < 3 || x0 < 3 || y0 + TY + 3 > H || x0 + TX + 3 > W) {
-        for (int i = tid; i < L::MH * L::MW; i += kThreads) {
-            const int r = i / L::MW, c = i - r * L::MW;
-            const int gy = y0 - 3 + r, gx = x0 - 3 + c;
-            if (gy < 0 || gy >= H || gx < 0 || gx >= W)
-                sM3[r * L::MWP + c] =
-                    sM3[(clampi(gy, H) - (y0 - 3)) * L::MWP + (clampi(gx, W) - (x0 - 3))];
-        }
+    // Region cells outside the image must hold the value of their clamped cell: the
+    // windows of the work set read S at clamped neighbour positions.
+    if (y0 < 2 || x0 < 2 || y0 + TY + 2 > H || x0 + TX + 2 > W) {
         for (int i = tid; i < L::SH * L::SW; i += kThreads) {
             const int r = i / L::SW, c = i - r * L::SW;
             const int gy = y0 - 2 + r, gx = x0 - 2 + c;
@@ -534,8 +675,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // block's largest error and, with 4u, the roundings of the differences)
     if (!all_exact) {
         const float b2 = 2.02f * emax;
-        const SEstParams sp = sest_params(f);
-        const float olim = f.objlim, inv_olim = 1.0f / olim;
+        const float olim = f.objlim;
         const float olim_lo = olim * (1.0f - 0x1p-21f), olim_hi = olim * (1.0f + 0x1p-21f);
         unsigned int ncontrast = 0u, nunc = 0u;
         for (int qi = tid; qi < total; qi += kThreads) {
@@ -553,20 +693,30 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             const float lo = spr - B, hi = spr + B;
             const bool h1 = lo > sc_hi, h0 = hi <= sc_lo, l1 = lo > ll_hi, l0 = hi <= ll_lo;
             bool unc = !((h1 || h0) && (l1 || l0));
-            bool first = false;
+            bool listed = false;
             if (!unc && h1) {
-                const int t = contrast_by_count(&sM3[(r + 3) * L::MWP + c + 3], L::MWP,
-                                                sM5[pos], sp, lo, hi, olim_lo, olim_hi,
-                                                inv_olim);
-                first = t > 0;
-                unc = t < 0;
-                ncontrast += unc ? 0u : 1u;
+                // S'/F^ <= S'/0.01 <= objlim for the whole interval: the test fails
+                if (hi * 100.0f <= olim_lo) {
+                    ++ncontrast;
+                } else if (!(lo * 100.0f > olim_hi)) {
+                    unc = true;
+                } else {
+                    const unsigned int slot = atomicAdd(&sConCount, 1u);
+                    if (slot < (unsigned int)kConMax) {
+                        sConInfo[slot] = (uint32_t)pos | (l1 ? 1u << 16 : 0u);
+                        sConLo[slot] = lo;
+                        sConHi[slot] = hi;
+                        listed = true;
+                    } else {
+                        unc = true;
+                    }
+                }
             }
             if (unc) {
                 atomicOr(&sU[pos >> 5], 1u << (pos & 31));
                 ++nunc;
-            } else {
-                sCode[pos] = (uint8_t)((first ? 1 : 0) | (h1 ? 2 : 0) | (l1 ? 4 : 0));
+            } else if (!listed) {
+                sCode[pos] = (uint8_t)((h1 ? 2 : 0) | (l1 ? 4 : 0));
             }
         }
         if (ncontrast && (f.flags & kCountWork))
@@ -577,6 +727,35 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         sUncertain = (unsigned int)total;     // sU holds Q'
     }
     __syncthreads();
+
+    // contrast tests of the listed pixels (S' > sigclip certain), one wave per pixel
+    const int ncon = min((int)sConCount, kConMax);
+    if (ncon) {
+        const SEstParams sp = sest_params(f);
+        const float inv_olim = 1.0f / f.objlim;
+        unsigned int ncontrast = 0u, nunc = 0u;
+        for (int it = tid >> 6; it < ncon; it += kThreads / 64) {
+            const uint32_t info = sConInfo[it];
+            const int pos = (int)(info & 0xFFFFu);
+            const int r = pos / TX, c = pos - r * TX;
+            const int t = contrast_by_count(sJ, L::JWP, y0, x0, H, W, r, c, sp, sConLo[it],
+                                            sConHi[it], inv_olim, lane);
+            if (lane == 0) {
+                if (t < 0) {
+                    atomicOr(&sU[pos >> 5], 1u << (pos & 31));
+                    ++nunc;
+                } else {
+                    sCode[pos] = (uint8_t)((t > 0 ? 1 : 0) | 2 | ((info >> 16) ? 4 : 0));
+                    ++ncontrast;
+                }
+            }
+        }
+        if (ncontrast && (f.flags & kCountWork))
+            atomicAdd(&sContrast, ncontrast);
+        if (nunc)
+            atomicAdd(&sUncertain, nunc);
+        __syncthreads();
+    }
 
     // binary64 re-evaluation of the undecided pixels from J, kExactBatch per round:
     // 25 threads compute the S window of a pixel, then one thread its codes
@@ -609,8 +788,15 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 const bool hbit = spr > sigclip, lbit = spr > lowlim;
                 bool first = false;
                 if (hbit) {
-                    const double fh = fine_structure(&sM3[(r + 3) * L::MWP + c + 3], L::MWP,
-                                                     noise_exact(sM5[pos], gain, sky, rn2));
+                    float w5[25], m5[1];
+#pragma unroll
+                    for (int i = 0; i < 5; ++i)
+#pragma unroll
+                        for (int j = 0; j < 5; ++j)
+                            w5[i * 5 + j] = sJ[(r + 2 + i) * L::JWP + c + 2 + j];
+                    med5_t1x1(w5, m5);
+                    const double fh = fine_structure(sJ, L::JWP, y0, x0, H, W, r, c,
+                                                     noise_exact(m5[0], gain, sky, rn2));
                     first = spr / fh > objlim;
                     ++ncontrast;
                 }
@@ -647,6 +833,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             atomicAdd(&f.work[1], (unsigned long long)sContrast);
         if (nunc)
             atomicAdd(&f.work[2], (unsigned long long)nunc);
+        if (sExactCells)
+            atomicAdd(&f.work[3], (unsigned long long)sExactCells);
     }
 }
 
@@ -654,10 +842,15 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
 // parity-test kernels: the median networks alone
 // ---------------------------------------------------------------------------
 
+// Output tile of one thread of k_debug_median: the shapes the kernels use (med3 in runs,
+// med5 in vertical pairs, med7 single).
+__host__ __device__ constexpr int debug_median_ty(int r) { return r == 2 ? 2 : 1; }
+__host__ __device__ constexpr int debug_median_tx(int r) { return r == 1 ? kRun3 : 1; }
+
 template <int R>
 __global__ __launch_bounds__(kThreads) void k_debug_median(const float *__restrict__ in, int H,
                                                            int W, float *__restrict__ out) {
-    constexpr int TY = (R == 2) ? 2 : 1, TX = (R == 1) ? kRun3 : (R == 2 ? 5 : 1);
+    constexpr int TY = debug_median_ty(R), TX = debug_median_tx(R);
     constexpr int PH = TY + 2 * R, PW = TX + 2 * R;
     const int ntx = (W + TX - 1) / TX, nty = (H + TY - 1) / TY;
     const int t = blockIdx.x * kThreads + threadIdx.x;
@@ -680,7 +873,7 @@ __global__ __launch_bounds__(kThreads) void k_debug_median(const float *__restri
         }
         med3_run<kRun3>(a, b, c, o);
     } else if constexpr (R == 2) {
-        med5_t2x5(v, o);
+        med5_t2x1(v, o);
     } else {
         med7_t1x1(v, o);
     }
@@ -767,7 +960,7 @@ hipError_t launch_debug_median5_f64(const double *in, int H, int W, double *out,
 }
 
 hipError_t launch_debug_median(const float *in, int H, int W, int r, float *out, hipStream_t s) {
-    const int ty = (r == 2) ? 2 : 1, tx = (r == 1) ? kRun3 : (r == 2 ? 5 : 1);
+    const int ty = debug_median_ty(r), tx = debug_median_tx(r);
     const size_t n = (size_t)((H + ty - 1) / ty) * (size_t)((W + tx - 1) / tx);
     const unsigned int grid = (unsigned int)((n + kThreads - 1) / kThreads);
     if (r == 1)

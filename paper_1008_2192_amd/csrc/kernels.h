@@ -36,7 +36,7 @@ constexpr int kExactDetect = 1 << 10;
 // re-evaluates only the tiles flagged in f.dirty (replacement flags the tiles whose
 // codes can change); the others keep their codes, which the unchanged J determines.
 constexpr int kIncremental = 2;
-constexpr int kWorkCounters = 3;
+constexpr int kWorkCounters = 4;
 
 // Everything a kernel needs to know about one frame.  All pointers are device
 // pointers; J is the image being cleaned in place (out_clean).

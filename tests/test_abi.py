@@ -155,7 +155,7 @@ def test_farm_argument_validation(L):
 
 
 def test_counting_and_debug_entry_validation(L):
-    c = (ctypes.c_int64 * 3)()
+    c = (ctypes.c_int64 * 4)()
     assert L.crb_plan_set_counting(None, 1) == -1
     assert L.crb_plan_work_counts(None, c) == -1
     assert L.crb_debug_median5_f64(None, 4, 4, ctypes.c_void_p(1 << 40)) == -1

@@ -116,8 +116,12 @@ def expected_codes(tr, p):
 @pytest.mark.parametrize("exact", [False, True], ids=["estimate", "binary64"])
 def test_detection_codes_match_oracle(exact):
     """Both detection paths: decisions from the FP32 estimate of S where its bound
-    settles them, and every work-set pixel re-evaluated in binary64 from J."""
-    for f in small_frames():
+    settles them, and every work-set pixel re-evaluated in binary64 from J.  The last
+    frame is quantised to steps of 8 ADU, so that windows hold many ties and the lower
+    bound of med5(J) that marks the candidates often equals med5(J)."""
+    ties = synth.c1(seed=11)
+    ties.img = (np.round(ties.img / np.float32(8.0)) * np.float32(8.0)).astype(np.float32)
+    for f in small_frames() + [ties]:
         p = fparams(f)
         tr = ref.iterate(f.img, np.zeros(f.img.shape, np.uint8), trace=True, **p)
         near = dilate(tr["s"] > p["sigclip"], 2)
@@ -217,12 +221,15 @@ def test_work_counts_match_oracle_sets():
     got = plan.work_counts()
     plan.set_counting(False)                  # clears the counters and stops counting
     plan.run()
-    assert plan.work_counts() == dict(work_pixels=0, contrast_tests=0, reevaluated=0)
+    assert plan.work_counts() == dict(work_pixels=0, contrast_tests=0, reevaluated=0,
+                                      exact_med5=0)
     plan.close()
     log(f"work counts {got}, expected {exp_w} / {exp_c}")
     assert exp_w <= got["work_pixels"] <= exp_w + exp_w // 100 + 4
     assert got["contrast_tests"] == exp_c
     assert got["reevaluated"] <= got["work_pixels"] // 100 + 4
+    # every work-set pixel has its med5(J) selected exactly
+    assert got["work_pixels"] <= got["exact_med5"] <= sum(f.img.size for f in frames)
 
 
 def test_iterations_teacher_forced():
