@@ -227,25 +227,12 @@ __device__ __forceinline__ double fine_structure(const float *sJ, int jp, int y0
 //   T = m3 - K up to a band of 2^-19 (|m3| + K) + 2^-126 (three-fold the roundings)
 //   decides the test.  The test is larger for larger S', so lo bounds its certain
 //   holding and hi its possible holding.
-// Lane l < 25 holds the value of med5(J)'s window cell (l / 5 - 2, l % 5 - 2), and the
-// median is the value with at most 12 smaller and at least 13 not larger; lane l < 49
-// takes the med3 value of window cell (l / 7 - 3, l % 7 - 3), and ballots count them.
+// m5 is med5(J) at the pixel; lane l < 49 takes the med3 value of window cell
+// (l / 7 - 3, l % 7 - 3), and ballots count them.
 __device__ __forceinline__ int contrast_by_count(const float *sJ, int jp, int y0, int x0,
-                                                 int H, int W, int r, int c,
+                                                 int H, int W, int r, int c, float m5,
                                                  const SEstParams &p, float lo, float hi,
                                                  float inv_olim, int lane) {
-    const int l25 = lane < 25 ? lane : 12;
-    const float jv = sJ[(r + 2 + l25 / 5) * jp + (c + 2 + l25 % 5)];
-    int lt = 0, le = 0;
-#pragma unroll
-    for (int k = 0; k < 25; ++k) {
-        const float u = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(jv), k));
-        lt += u < jv ? 1 : 0;
-        le += u <= jv ? 1 : 0;
-    }
-    const unsigned long long hold = __ballot(lane < 25 && lt <= 12 && le >= 13);
-    const float m5 = __int_as_float(
-        __builtin_amdgcn_readlane(__float_as_int(jv), (int)__ffsll((long long)hold) - 1));
     const int l49 = lane < 49 ? lane : 24;
     const float x = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, l49 / 7 - 3, l49 % 7 - 3), jp);
     const float m3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 24));
@@ -351,7 +338,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     __shared__ uint16_t sList[TY * TX];                     // work set Q'
     // pixels whose contrast test is left to the contrast phase: position, S' interval
     __shared__ uint32_t sConInfo[kConMax];
-    __shared__ float sConLo[kConMax], sConHi[kConMax];
+    __shared__ float sConLo[kConMax], sConHi[kConMax], sConM5[kConMax];
 
     DevFrame f;
     int y0, x0;
@@ -703,9 +690,18 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 } else {
                     const unsigned int slot = atomicAdd(&sConCount, 1u);
                     if (slot < (unsigned int)kConMax) {
+                        // med5(J) at the pixel, for N
+                        float w5[25], m5[1];
+#pragma unroll
+                        for (int i = 0; i < 5; ++i)
+#pragma unroll
+                            for (int j = 0; j < 5; ++j)
+                                w5[i * 5 + j] = sJ[(r + 2 + i) * L::JWP + c + 2 + j];
+                        med5_t1x1(w5, m5);
                         sConInfo[slot] = (uint32_t)pos | (l1 ? 1u << 16 : 0u);
                         sConLo[slot] = lo;
                         sConHi[slot] = hi;
+                        sConM5[slot] = m5[0];
                         listed = true;
                     } else {
                         unc = true;
@@ -738,8 +734,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             const uint32_t info = sConInfo[it];
             const int pos = (int)(info & 0xFFFFu);
             const int r = pos / TX, c = pos - r * TX;
-            const int t = contrast_by_count(sJ, L::JWP, y0, x0, H, W, r, c, sp, sConLo[it],
-                                            sConHi[it], inv_olim, lane);
+            const int t = contrast_by_count(sJ, L::JWP, y0, x0, H, W, r, c, sConM5[it], sp,
+                                            sConLo[it], sConHi[it], inv_olim, lane);
             if (lane == 0) {
                 if (t < 0) {
                     atomicOr(&sU[pos >> 5], 1u << (pos & 31));
