@@ -297,7 +297,7 @@ template <int TY, int TX>
 struct DetectLayout {
     // logical extents of the LDS planes and their row pitches; the pitches spread the
     // stage-1 and stage-2 scalar accesses over the LDS banks
-    static constexpr int JH = TY + 8, JW = TX + 8, JWP = TX + 11;   // J, apron 4
+    static constexpr int JH = TY + 8, JW = TX + 8, JWP = TX + 9;    // J, apron 4
     static constexpr int SH = TY + 4, SW = TX + 4, SWP = TX + 6;    // S estimate, apron 2
     static constexpr int HW = (SW + 31) / 32;   // words per row of the hot bitmap
     static constexpr int QW = TX / 32;          // words per row of the tile bitmaps
@@ -457,9 +457,11 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     const SEstParams sp = sest_params(f);
     const int lane = tid & 63;
     if (tid < NTY * NTX) {
-        const int ty = tid / NTX;
-        const int r5 = min(ty * TTY, L::SH - TTY);
-        const int c5 = min((tid - ty * NTX) * TTX, L::SW - TTX);
+        // column-major over the 2 x 5 tiles: with the J pitch this spreads a wave's patch
+        // loads over the LDS banks
+        const int tx = tid / NTY;
+        const int r5 = min((tid - tx * NTY) * TTY, L::SH - TTY);
+        const int c5 = min(tx * TTX, L::SW - TTX);
         float v[(TTY + 4) * PW];
 #pragma unroll
         for (int i = 0; i < TTY + 4; ++i)
@@ -477,15 +479,28 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             x = min3f(x, med3f(v[j], lo, hi), med3f(v[5 * PW + j], lo, hi));
         }
         const float R = r_bound(x, sp);
+        const int gx0 = x0 - 2 + c5;
+        // in-frame columns of the tile's five, as a bit mask
+        const uint32_t colmask = (gx0 >= 0 && gx0 + TTX <= W)
+                                     ? (1u << TTX) - 1u
+                                     : (((1u << TTX) - 1u) << max(-gx0, 0)) &
+                                           ((1u << max(min(W - gx0, TTX), 0)) - 1u);
 #pragma unroll
         for (int i = 0; i < TTY; ++i) {
+            uint32_t bits = 0u;
 #pragma unroll
             for (int j = 0; j < TTX; ++j) {
                 const int pc = (i + 2) * PW + (j + 2);
-                const int gy = y0 - 2 + r5 + i, gx = x0 - 2 + c5 + j;
-                if (s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], R, sc_lo) &&
-                    gy >= 0 && gy < H && gx >= 0 && gx < W)
-                    atomicOr(&sHot[(r5 + i) * L::HW + ((c5 + j) >> 5)], 1u << ((c5 + j) & 31));
+                bits |= s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], R, sc_lo)
+                            ? 1u << j : 0u;
+            }
+            const int gy = y0 - 2 + r5 + i;
+            bits = (gy >= 0 && gy < H) ? bits & colmask : 0u;
+            if (bits) {
+                const int w = c5 >> 5, sh = c5 & 31;
+                atomicOr(&sHot[(r5 + i) * L::HW + w], bits << sh);
+                if (sh > 32 - TTX && (bits >> (32 - sh)))
+                    atomicOr(&sHot[(r5 + i) * L::HW + w + 1], bits >> (32 - sh));
             }
         }
     }
