@@ -128,9 +128,10 @@ __device__ __forceinline__ float r_bound(float x, const SEstParams &p) {
 }
 
 // Whether S may exceed thr at a pixel of value c with 4-neighbours up, dn, lf, rt, given
-// R = r_bound(x) for a lower bound x of its med5(J): the S estimate and its error bound
-// evaluated as s_estimate does; true where R is not finite or M > 2^100 (inputs are
-// finite, so no value here is a NaN once those are excluded).
+// a finite R = r_bound(x) for a lower bound x of its med5(J): the S estimate and its
+// error bound evaluated as s_estimate does; true where M > 2^100 (inputs are finite, so
+// no value here is a NaN).  The result is combined without short-circuit evaluation so
+// that a wave takes no branch per pixel.
 __device__ __forceinline__ bool s_may_exceed(float c, float up, float dn, float lf, float rt,
                                              float R, float thr) {
     const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
@@ -139,7 +140,7 @@ __device__ __forceinline__ bool s_may_exceed(float c, float up, float dn, float 
     const float s = l4 * R;
     const float M = fmaf(4.0f, fabsf(c), fabsf(up)) + fabsf(dn) + (fabsf(lf) + fabsf(rt));
     const float err = (M * R + s) * 0x1p-19f;
-    return !(R < INFINITY) || !(M <= 0x1p100f) || s + err > thr;
+    return (s + err > thr) | !(M <= 0x1p100f);
 }
 
 // S exactly as the definition evaluates it (binary64, in its operation order), at the
@@ -494,6 +495,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 bits |= s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], R, sc_lo)
                             ? 1u << j : 0u;
             }
+            // where the analysis of the estimate does not hold at the bound, every cell
+            bits = (R < INFINITY) ? bits : (1u << TTX) - 1u;
             const int gy = y0 - 2 + r5 + i;
             bits = (gy >= 0 && gy < H) ? bits & colmask : 0u;
             if (bits) {
