@@ -128,19 +128,17 @@ __device__ __forceinline__ float r_bound(float x, const SEstParams &p) {
 }
 
 // Whether S may exceed thr at a pixel of value c with 4-neighbours up, dn, lf, rt, given
-// a finite R = r_bound(x) for a lower bound x of its med5(J): the S estimate and its
-// error bound evaluated as s_estimate does; true where M > 2^100 (inputs are finite, so
-// no value here is a NaN).  The result is combined without short-circuit evaluation so
-// that a wave takes no branch per pixel.
+// a finite R = r_bound(x) for a lower bound x of its med5(J) and E = 2^-19 * 8 v * R with
+// v >= each |value| read and 8 v <= 2^100 (so E >= 2^-19 M R, M as in s_estimate): the
+// estimate s = l4 R as s_estimate forms it, and s + 2^-19 s + E in one FMA.  That sum
+// exceeds the bound s + err of s_estimate, which holds S with four-fold slack, by far more
+// than its own rounding; compared with thr = sigclip less 2^-20 it settles S <= sigclip.
 __device__ __forceinline__ bool s_may_exceed(float c, float up, float dn, float lf, float rt,
-                                             float R, float thr) {
+                                             float R, float E, float thr) {
     const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
     const float l4 = (fmaxf(a - lf, 0.0f) + fmaxf(a - rt, 0.0f)) +
                      (fmaxf(b - lf, 0.0f) + fmaxf(b - rt, 0.0f));
-    const float s = l4 * R;
-    const float M = fmaf(4.0f, fabsf(c), fabsf(up)) + fabsf(dn) + (fabsf(lf) + fabsf(rt));
-    const float err = (M * R + s) * 0x1p-19f;
-    return (s + err > thr) | !(M <= 0x1p100f);
+    return fmaf(l4 * R, 1.0f + 0x1p-19f, E) > thr;
 }
 
 // S exactly as the definition evaluates it (binary64, in its operation order), at the
@@ -480,6 +478,16 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             x = min3f(x, med3f(v[j], lo, hi), med3f(v[5 * PW + j], lo, hi));
         }
         const float R = r_bound(x, sp);
+        // one error term for the tile's cells: every value their M reads lies in patch
+        // rows 1-4, columns 1-7, so M <= 8 vmax
+        float vmax = 0.0f;
+#pragma unroll
+        for (int i = 1; i <= 4; ++i)
+#pragma unroll
+            for (int j = 1; j <= 7; ++j)
+                vmax = fmaxf(vmax, fabsf(v[i * PW + j]));
+        const bool bound_ok = R < INFINITY && vmax <= 0x1p96f;
+        const float E = (8.0f * vmax) * R * 0x1p-19f;
         const int gx0 = x0 - 2 + c5;
         // in-frame columns of the tile's five, as a bit mask
         const uint32_t colmask = (gx0 >= 0 && gx0 + TTX <= W)
@@ -492,11 +500,11 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
 #pragma unroll
             for (int j = 0; j < TTX; ++j) {
                 const int pc = (i + 2) * PW + (j + 2);
-                bits |= s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], R, sc_lo)
-                            ? 1u << j : 0u;
+                bits |= s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], R, E,
+                                     sc_lo) ? 1u << j : 0u;
             }
             // where the analysis of the estimate does not hold at the bound, every cell
-            bits = (R < INFINITY) ? bits : (1u << TTX) - 1u;
+            bits = bound_ok ? bits : (1u << TTX) - 1u;
             const int gy = y0 - 2 + r5 + i;
             bits = (gy >= 0 && gy < H) ? bits & colmask : 0u;
             if (bits) {
