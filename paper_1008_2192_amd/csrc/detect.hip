@@ -20,6 +20,10 @@ namespace crb {
 
 #include "medtile.inc"
 
+// Exclusive prefix sum over the lanes of a wave (all lanes active), from the device
+// library's cross-lane (DPP) primitives.
+extern "C" __device__ unsigned int __ockl_wfscan_add_u32(unsigned int, bool);
+
 // 3x3 medians of a run of N horizontally adjacent outputs from three rows of N+2
 // inputs.  Each column of three is sorted once (shared by up to three windows);
 // the median of a 3x3 window with sorted columns is the median of
@@ -312,15 +316,17 @@ struct DetectLayout {
 //   G1(p) needs an A pixel within distance 1, so hi(p) matters only on D1(H);
 //   G2(p) needs a G1 pixel within distance 1, so lo(p) matters only on D2(H);
 // and lo(p) = hi(p) = 0 wherever S(p) <= sigfrac * sigclip (sigfrac <= 1).  The block
-// computes the FP32 estimate s of S with its error bound on the tile and its apron,
-// H' = {s + err > sigclip (less a margin)} (a superset of H), and evaluates the codes on
-// Q' = D2(H') & {s + max err > sigfrac * sigclip (less a margin)}, a superset of
-// Q = D2(H) & {S > sigfrac*sigclip}: med5 of the estimates gives S' within twice the
-// block's largest error (the median moves no more than its inputs), which decides the
-// two bits, and F^ (binary64) with the interval of S' decides the contrast test; a
-// pixel where an interval straddles a threshold is re-evaluated in binary64 from J.  So
-// every code written is the full definition's, codes outside Q' are 0, and the grow,
-// which reads codes only through its two dilations, sees the full definition.
+// bounds S from above on the tile and its apron (from a lower bound of med5(J)), then
+// computes the FP32 estimate s of S with its error bound err within 4 of where that
+// bound exceeds sigclip, takes H' = {s + err > sigclip (less a margin)} (a superset of
+// H), and evaluates the codes on Q' = D2(H') & {s + err > sigfrac * sigclip (less a
+// margin)}, a superset of Q = D2(H) & {S > sigfrac*sigclip}: med5 of the estimates
+// gives S' within twice the block's largest error (the median moves no more than its
+// inputs), which decides the two bits, and F^ with the interval of S' decides the
+// contrast test; a pixel where an interval straddles a threshold is re-evaluated in
+// binary64 from J.  So every code written is the full definition's, codes outside Q'
+// are 0, and the grow, which reads codes only through its two dilations, sees the full
+// definition.
 template <int TY, int TX>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))
 void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
@@ -331,6 +337,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     __shared__ __align__(16) uint8_t sCode[TY * TX];
     __shared__ uint32_t sHot[L::SH * L::HW];                // H', apron 2, in-frame
     __shared__ uint32_t sU[L::kTileWords], sUpre[L::kTileWords + 1];
+    __shared__ uint32_t sLow[L::kTileWords];     // tile cells where S may exceed sigfrac*sigclip
     __shared__ unsigned int sErrBits, sContrast, sUncertain, sQcount, sNeedCount, sExactCells,
         sConCount;
     double *const sX = reinterpret_cast<double *>(sS);
@@ -376,8 +383,10 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
 
     for (int i = tid; i < L::SH * L::HW; i += kThreads)
         sHot[i] = 0u;
-    if (tid < L::kTileWords)
+    if (tid < L::kTileWords) {
         sU[tid] = 0u;
+        sLow[tid] = 0u;
+    }
     if (tid == 0) {
         sErrBits = 0u;
         sQcount = 0u;
@@ -533,13 +542,16 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         if (tid < NP * L::HW) {
             const int pr = tid / L::HW, w = tid - pr * L::HW;
             uint32_t a = 0u, b = 0u, c = 0u;        // words w - 1, w, w + 1 of the rows
-            for (int rr = max(2 * pr - 4, 0); rr <= min(2 * pr + 5, L::SH - 1); ++rr) {
-                const uint32_t *row = &sHot[rr * L::HW];
-                b |= row[w];
-                if (w > 0)
-                    a |= row[w - 1];
-                if (w + 1 < L::HW)
-                    c |= row[w + 1];
+#pragma unroll
+            for (int k = 0; k < 10; ++k) {
+                const int rr = 2 * pr - 4 + k;
+                const bool in = rr >= 0 && rr < L::SH;
+                const uint32_t *row = &sHot[(in ? rr : 0) * L::HW];
+                const uint32_t ra = row[w > 0 ? w - 1 : 0], rb = row[w],
+                               rc = row[w + 1 < L::HW ? w + 1 : w];
+                a |= (in && w > 0) ? ra : 0u;
+                b |= in ? rb : 0u;
+                c |= (in && w + 1 < L::HW) ? rc : 0u;
             }
             // column 32w + k is needed when a bit lies in columns 32w + k - 4 .. + 4
             const unsigned long long hi = ((unsigned long long)c << 32) | b;
@@ -555,16 +567,9 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 m &= (1u << valid) - 1u;
         }
         const unsigned int cnt = (unsigned int)__popc(m);
-        unsigned int incl = cnt;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned int u = (unsigned int)__shfl_up((int)incl, o);
-            if (tid >= o)
-                incl += u;
-        }
-        const unsigned int total = (unsigned int)__builtin_amdgcn_readlane((int)incl, 63);
+        unsigned int at = __ockl_wfscan_add_u32(cnt, false);
+        const unsigned int total = (unsigned int)__builtin_amdgcn_readlane((int)(at + cnt), 63);
         if (total <= (unsigned int)kPairListMax) {
-            unsigned int at = incl - cnt;
             const int pr = tid / L::HW, w = tid - pr * L::HW;
             for (uint32_t mm = m; mm; mm &= mm - 1u)
                 sPairs[at++] = (uint16_t)(pr * L::SW + 32 * w + __ffs(mm) - 1);
@@ -612,7 +617,11 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                     if (!(s + err > sc_lo) && (*hw & hb))
                         atomicAnd(hw, ~hb);
                     const int cy = r0 + i - 2, cx = cc - 2;
-                    ncells += (cy >= 0 && cy < TY && cx >= 0 && cx < TX) ? 1u : 0u;
+                    const bool tile_cell = cy >= 0 && cy < TY && cx >= 0 && cx < TX;
+                    ncells += tile_cell ? 1u : 0u;
+                    // S may exceed sigfrac * sigclip here (the cell's own bound)
+                    if (tile_cell && s + err > ll_lo)
+                        atomicOr(&sLow[cy * L::QW + (cx >> 5)], 1u << (cx & 31));
                 }
             }
         }
@@ -646,6 +655,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     const bool all_exact = !(emax < INFINITY) || (f.flags & kExactDetect);
     // work set Q' on the tile's in-frame pixels, one 32-pixel word per lane of the
     // first wave, appended to a compact list of tile positions (in any order)
+    static_assert(L::kTileWords == 64, "one bitmap word per lane of the first wave");
     if (tid < L::kTileWords) {
         const int r = tid / L::QW, w = tid - r * L::QW;
         unsigned long long x = 0ull;
@@ -662,20 +672,15 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             q = 0u;
         else if (vc < 32)
             q &= (1u << vc) - 1u;
-        if (!all_exact) {
-            for (uint32_t m = q; m; m &= m - 1u) {
-                const int b = __ffs(m) - 1;
-                if (!(sS[(r + 2) * L::SWP + 32 * w + b + 2] + emax > ll_lo))
-                    q &= ~(1u << b);
-            }
-        }
+        q &= sLow[tid];
         if (all_exact)
             sU[tid] = q;
-        if (q) {
-            int at = (int)atomicAdd(&sQcount, (unsigned int)__popc(q));
-            for (uint32_t m = q; m; m &= m - 1u)
-                sList[at++] = (uint16_t)(tid * 32 + __ffs(m) - 1);   // = r * TX + column
-        }
+        const unsigned int cnt = (unsigned int)__popc(q);
+        unsigned int at = __ockl_wfscan_add_u32(cnt, false);
+        for (uint32_t m = q; m; m &= m - 1u)
+            sList[at++] = (uint16_t)(tid * 32 + __ffs(m) - 1);   // = r * TX + column
+        if (tid == 63)
+            sQcount = at;
     }
     __syncthreads();
 
