@@ -156,7 +156,7 @@ crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
  * med5(J) was selected exactly (counts has 4 elements).  med5(J) and the estimate of
  * S are needed only within 4 pixels of a pixel where S may exceed sigclip; the
  * detection finds those pixels from a cheap lower bound of med5(J) (S does not grow
- * with it) and selects med5(J) only in the vertical pixel pairs that meet that
+ * with it) and selects med5(J) only in the 2 x 2 pixel cells that meet that
  * region. */
 crb_status crb_plan_set_counting(crb_plan *plan, int32_t enable);
 crb_status crb_plan_work_counts(crb_plan *plan, int64_t *counts);
@@ -333,7 +333,7 @@ crb_status crb_debug_detect_exact(const float *J, const crb_frame *params,
 crb_status crb_debug_s_estimate(const float *J, const crb_frame *params, float *out_s,
                                 float *out_err);
 /* Clamped (2r+1)^2 median filter, r in {1, 2, 3}, by the kernels' networks (3x3 by
- * sorted columns, 5x5 by the network for a vertical pair of outputs, 7x7 by the
+ * sorted columns, 5x5 by the network for a 2 x 2 tile of outputs, 7x7 by the
  * single-output one). */
 crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out);
 /* Clamped 5x5 median filter of binary64 values by the single-output network the

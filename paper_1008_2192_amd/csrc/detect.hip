@@ -287,7 +287,7 @@ __device__ __forceinline__ int bitmap_select64(const uint32_t *bits, const uint3
 
 // Work shapes inside a detection block: med3 in runs of kRun3 outputs; a lower bound of
 // med5(J), L+ and an upper bound of S in 2 x 5 thread tiles over the whole tile and its
-// 2-pixel apron; med5(J) and the S estimate in vertical pairs near where S may exceed
+// 2-pixel apron; med5(J) and the S estimate in 2 x 2 quads near where S may exceed
 // sigclip.  The remaining statistics are evaluated only where a code bit can matter.
 constexpr int kRun3 = 14;
 // pixels per round of the binary64 re-evaluation (25 threads each)
@@ -528,15 +528,15 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // The later stages read S (to within the block's largest error bound) and med5(J)
     // only within 4 cells of H': the work set lies within 2 of H', and med5(S) at a work
     // pixel reads 2 further (a clamped neighbour's cell is no farther).  That region, in
-    // 2 x 1 cell pairs (row pair p, column c: a bit per pair, one 32-column word per
-    // thread), is listed by the first wave and the pairs take the exact med5 network in
-    // list order, which spreads them evenly over the block's waves.
+    // 2 x 2 cell quads (row pair p, even column c: one 32-column word per thread), is
+    // listed by the first wave and the quads take the exact med5 network in list order.
     constexpr int NP = L::SH / 2;
-    static_assert(L::SH % 2 == 0 && NP * L::HW <= 64, "one bitmap word per lane of a wave");
-    static_assert(NP * L::SW <= 2048, "pair index in 16 bits");
-    constexpr int kPairListMax = TY * TX / 2;    // uint16 entries the code plane can hold
-    constexpr int kPairRounds = (NP * L::SW + kThreads - 1) / kThreads;
-    uint16_t *const sPairs = reinterpret_cast<uint16_t *>(sCode);   // codes start later
+    static_assert(L::SH % 2 == 0 && L::SW % 2 == 0 && NP * L::HW <= 64,
+                  "whole quads, one bitmap word per lane of a wave");
+    constexpr int kQuads = NP * L::SW / 2;
+    static_assert(kQuads <= TY * TX / 2, "the quad list fits in the code plane");
+    constexpr int kQuadRounds = (kQuads + kThreads - 1) / kThreads;
+    uint16_t *const sQuads = reinterpret_cast<uint16_t *>(sCode);   // codes start later
     if (tid < 64) {
         uint32_t m = 0u;
         if (tid < NP * L::HW) {
@@ -565,15 +565,15 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             const int valid = L::SW - 32 * w;
             if (valid < 32)
                 m &= (1u << valid) - 1u;
+            // quads by their even column
+            m = (m | (m >> 1)) & 0x55555555u;
         }
         const unsigned int cnt = (unsigned int)__popc(m);
         unsigned int at = __ockl_wfscan_add_u32(cnt, false);
         const unsigned int total = (unsigned int)__builtin_amdgcn_readlane((int)(at + cnt), 63);
-        if (total <= (unsigned int)kPairListMax) {
-            const int pr = tid / L::HW, w = tid - pr * L::HW;
-            for (uint32_t mm = m; mm; mm &= mm - 1u)
-                sPairs[at++] = (uint16_t)(pr * L::SW + 32 * w + __ffs(mm) - 1);
-        }
+        const int pr = tid / L::HW, w = tid - pr * L::HW;
+        for (uint32_t mm = m; mm; mm &= mm - 1u)
+            sQuads[at++] = (uint16_t)(pr * L::SW + 32 * w + __ffs(mm) - 1);
         if (tid == 0)
             sNeedCount = total;
     }
@@ -581,47 +581,48 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // Exact pass: med5(J), L+ and the S estimate with its error bound; the block's largest
     // bound is taken over these cells, the only ones read, and H' drops the cells where
     // the estimate at med5(J) settles S <= sigclip (so H' is {s + err > sigclip less the
-    // margin} on the in-frame cells, as with the estimate everywhere).  A list too long
-    // for the code plane stands for every pair.
-    const int npairs = (int)sNeedCount;
-    const bool every_pair = npairs > kPairListMax;
-    const int nitems = every_pair ? NP * L::SW : npairs;
+    // margin} on the in-frame cells, as with the estimate everywhere).
+    const int nquads = (int)sNeedCount;
     {
         float emax = 0.0f;
         unsigned int ncells = 0u;
 #pragma unroll
-        for (int rd = 0; rd < kPairRounds; ++rd) {
+        for (int rd = 0; rd < kQuadRounds; ++rd) {
             const int it = tid + rd * kThreads;
-            if (it < nitems) {
-                const int q = every_pair ? it : (int)sPairs[it];
+            if (it < nquads) {
+                const int q = (int)sQuads[it];
                 const int pr = q / L::SW, cc = q - pr * L::SW, r0 = 2 * pr;
-                float v[6 * 5];
+                float v[6 * 6];
 #pragma unroll
                 for (int i = 0; i < 6; ++i)
 #pragma unroll
-                    for (int j = 0; j < 5; ++j)
-                        v[i * 5 + j] = sJ[(r0 + i) * L::JWP + cc + j];
-                float m5[2];
-                med5_t2x1(v, m5);
+                    for (int j = 0; j < 6; ++j)
+                        v[i * 6 + j] = sJ[(r0 + i) * L::JWP + cc + j];
+                float m5[4];
+                med5_t2x2(v, m5);
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
-                    const int pc = (i + 2) * 5 + 2;
-                    float err;
-                    const float s = s_estimate(v[pc], v[pc - 5], v[pc + 5], v[pc - 1], v[pc + 1],
-                                               m5[i], sp, err);
-                    sS[(r0 + i) * L::SWP + cc] = s;
-                    emax = fmaxf(emax, err);
-                    // H' keeps the cells whose estimate at med5(J) may exceed sigclip
-                    uint32_t *hw = &sHot[(r0 + i) * L::HW + (cc >> 5)];
-                    const uint32_t hb = 1u << (cc & 31);
-                    if (!(s + err > sc_lo) && (*hw & hb))
-                        atomicAnd(hw, ~hb);
-                    const int cy = r0 + i - 2, cx = cc - 2;
-                    const bool tile_cell = cy >= 0 && cy < TY && cx >= 0 && cx < TX;
-                    ncells += tile_cell ? 1u : 0u;
-                    // S may exceed sigfrac * sigclip here (the cell's own bound)
-                    if (tile_cell && s + err > ll_lo)
-                        atomicOr(&sLow[cy * L::QW + (cx >> 5)], 1u << (cx & 31));
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        const int pc = (i + 2) * 6 + (j + 2);
+                        float err;
+                        const float s = s_estimate(v[pc], v[pc - 6], v[pc + 6], v[pc - 1],
+                                                   v[pc + 1], m5[i * 2 + j], sp, err);
+                        const int rr = r0 + i, c = cc + j;
+                        sS[rr * L::SWP + c] = s;
+                        emax = fmaxf(emax, err);
+                        // H' keeps the cells whose estimate at med5(J) may exceed sigclip
+                        uint32_t *hw = &sHot[rr * L::HW + (c >> 5)];
+                        const uint32_t hb = 1u << (c & 31);
+                        if (!(s + err > sc_lo) && (*hw & hb))
+                            atomicAnd(hw, ~hb);
+                        const int cy = rr - 2, cx = c - 2;
+                        const bool tile_cell = cy >= 0 && cy < TY && cx >= 0 && cx < TX;
+                        ncells += tile_cell ? 1u : 0u;
+                        // S may exceed sigfrac * sigclip here (the cell's own bound)
+                        if (tile_cell && s + err > ll_lo)
+                            atomicOr(&sLow[cy * L::QW + (cx >> 5)], 1u << (cx & 31));
+                    }
                 }
             }
         }
@@ -637,6 +638,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         }
     }
     __syncthreads();
+
     // Region cells outside the image must hold the value of their clamped cell: the
     // windows of the work set read S at clamped neighbour positions.
     if (y0 < 2 || x0 < 2 || y0 + TY + 2 > H || x0 + TX + 2 > W) {
@@ -870,9 +872,9 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
 // ---------------------------------------------------------------------------
 
 // Output tile of one thread of k_debug_median: the shapes the kernels use (med3 in runs,
-// med5 in vertical pairs, med7 single).
+// med5 in 2 x 2 quads, med7 single).
 __host__ __device__ constexpr int debug_median_ty(int r) { return r == 2 ? 2 : 1; }
-__host__ __device__ constexpr int debug_median_tx(int r) { return r == 1 ? kRun3 : 1; }
+__host__ __device__ constexpr int debug_median_tx(int r) { return r == 1 ? kRun3 : (r == 2 ? 2 : 1); }
 
 template <int R>
 __global__ __launch_bounds__(kThreads) void k_debug_median(const float *__restrict__ in, int H,
@@ -900,7 +902,7 @@ __global__ __launch_bounds__(kThreads) void k_debug_median(const float *__restri
         }
         med3_run<kRun3>(a, b, c, o);
     } else if constexpr (R == 2) {
-        med5_t2x1(v, o);
+        med5_t2x2(v, o);
     } else {
         med7_t1x1(v, o);
     }

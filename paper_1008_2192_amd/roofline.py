@@ -78,7 +78,7 @@ def detect_ops() -> dict:
                  noise_bound=BOUND_NOISE_OPS, s_bound=S_OPS, hot=HOT_OPS)
     dense["total"] = sum(dense.values())
     return dict(dense=dense,
-                per_exact_pixel=network_ops_per_output("med5_t2x1") + NOISE_OPS + S_OPS,
+                per_exact_pixel=network_ops_per_output("med5_t2x2") + NOISE_OPS + S_OPS,
                 per_work_pixel=network_ops_per_output("med5_t1x1") + WORK_OPS,
                 per_contrast=CONTRAST_OPS)
 
