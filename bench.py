@@ -303,13 +303,13 @@ def main():
     ops_launch = roofline.detect_ops_per_launch(total_px, exact_px, work_px, contrast)
     achieved = ops_launch / det_avg_s                      # lane-ops per second
     o = roofline.detect_ops()
-    roof = {"bound": "alu", "kernel": "k_detect (detection: med3, a lower bound of med5(J), L+ "
-                                      "and the upper bound of S it gives everywhere; the med5 "
+    roof = {"bound": "alu", "kernel": "k_detect (detection: a lower bound of med5(J), L+ and "
+                                      "the upper bound of S it gives everywhere; the med5 "
                                       "network and the FP32 estimate of S with its error bound "
                                       "within 4 px of where S may exceed sigclip; med5(S), S' "
-                                      "and the threshold bits on the work set; F^ by counting "
-                                      "where S' > sigclip; binary64 re-evaluation where the "
-                                      "bound cannot decide)",
+                                      "and the threshold bits on the work set; the contrast "
+                                      "test by counting the med3 window where S' > sigclip; "
+                                      "binary64 re-evaluation where the bound cannot decide)",
             "achieved": round(achieved / 1e12, 3), "peak": round(roofline.ALU_PEAK / 1e12, 3),
             "unit": "Tlane-op/s", "frac": round(achieved / roofline.ALU_PEAK, 4),
             "traffic": profiled_traffic() if args.workload == "c4" else None,

@@ -2,7 +2,7 @@
 
 Algorithmic work is counted with every plane computed once (the halo recomputation
 of a tiled execution is overhead, not algorithm):
-  * dense, per image pixel: med3 of J; a lower bound of med5(J) (column medians of five,
+  * dense, per image pixel: a lower bound of med5(J) (column medians of five,
     four operations per pixel when two vertically adjacent windows share their middle
     pairs, and the least of them over each 2 x 5 cell's nine columns); L+; N at that bound
     (once per cell) and the upper bound of S it gives; the test of that bound against
@@ -11,8 +11,10 @@ of a tiled execution is overhead, not algorithm):
     counted by the kernel on the tile's own pixels): the med5 network, N and S;
   * per work-set pixel (within 2 of an S > sigclip pixel, S > sigfrac * sigclip):
     med5 of S, S' and the two threshold compares;
-  * per contrast test (S' > sigclip): N again and the test S'/F^ > objlim, decided by
-    comparing the 49 med3 values of the med7 window with the test's switching value
+  * per contrast test (S' > sigclip): med5(J) at the pixel (single-output network) and
+    N from it, the 49 med3(J) values of the med7 window (13 operations each: three
+    sorted columns of three, then three column extremes and their median), and the test
+    S'/F^ > objlim, decided by comparing those values with the test's switching value
     and counting them (the test holds at med7 iff it holds at 25 or more of them), which
     is less work than selecting med7.
 The three sparse counts come from the kernel's own counters (crb_plan_work_counts).
@@ -41,12 +43,11 @@ LPLUS_OPS = 4 * (1 + 4 + 1) + 3 + 1       # 4 sub-pixels: 4c, 4 subtractions, cl
 NOISE_OPS = 1 + 1 + 1 + 1 + 1 + 1         # +sky, floor, g*m, +rn^2, sqrt, /g
 S_OPS = 2                                 # 2N, L+/(2N)
 HOT_OPS = 1                               # S > sigclip
+MED3_AT_OPS = 3 * 3 + 3 + 1               # one med3(J) value from its 3 x 3 window
 # lower bound of med5(J): 8 min/max/median-of-3 operations per column and pair of rows,
 # then the least of 18 column medians per 2 x 5 cell
 BOUND_OPS = 8 / 2 + 17 / 10
 BOUND_NOISE_OPS = NOISE_OPS / 10          # N at the bound, once per 2 x 5 cell
-MED3_RUN = 14
-MED3_OPS = (3 * (MED3_RUN + 2) + 4 * MED3_RUN) / MED3_RUN   # column sorts of 3 ops + 4 per output
 # per work-set pixel, besides med5(S): S - med5(S), > sigclip, > sigfrac*sigclip
 WORK_OPS = 3
 # per contrast test: N (6); the floor test S'/0.01 > objlim, N S'/objlim, the switching
@@ -74,13 +75,14 @@ def network_ops_per_output(name: str) -> float:
 def detect_ops() -> dict:
     """Operations per image pixel (dense), per pixel of exact med5(J), per work-set
     pixel and per contrast test."""
-    dense = dict(med3=MED3_OPS, med5_bound=BOUND_OPS, lplus=LPLUS_OPS,
-                 noise_bound=BOUND_NOISE_OPS, s_bound=S_OPS, hot=HOT_OPS)
+    dense = dict(med5_bound=BOUND_OPS, lplus=LPLUS_OPS, noise_bound=BOUND_NOISE_OPS,
+                 s_bound=S_OPS, hot=HOT_OPS)
     dense["total"] = sum(dense.values())
     return dict(dense=dense,
                 per_exact_pixel=network_ops_per_output("med5_t2x2") + NOISE_OPS + S_OPS,
                 per_work_pixel=network_ops_per_output("med5_t1x1") + WORK_OPS,
-                per_contrast=CONTRAST_OPS)
+                per_contrast=CONTRAST_OPS + 49 * MED3_AT_OPS +
+                network_ops_per_output("med5_t1x1"))
 
 
 def detect_ops_per_launch(pixels: int, exact_pixels: float, work_pixels: float,
