@@ -197,19 +197,42 @@ __device__ __forceinline__ const float *med3_cell(const float *sJ, int jp, int y
     return &sJ[(clampi(y0 + r + dy, H) - y0 + 4) * jp + (clampi(x0 + c + dx, W) - x0 + 4)];
 }
 
-// F^ = max((med3 - med7(med3)) / N, 0.01) at tile pixel (r, c), binary64, with med3
-// taken from the staged J.
-__device__ __forceinline__ double fine_structure(const float *sJ, int jp, int y0, int x0,
-                                                 int H, int W, int r, int c, double N) {
-    float w7[49], m7[1];
+// The contrast test S'/F^ > objlim in binary64 at tile pixel (r, c), med3 taken from the
+// staged J, F^ = max((med3 - med7(med3)) / N, 0.01).  The test, evaluated in the
+// definition's operations with a value x in place of med7, is monotone in x (every step
+// and every rounding is), and med7 is the 25th of the 49 window values, with 24 on
+// either side; so the test holds at med7 iff it holds at 25 or more of them.
+__device__ __forceinline__ bool contrast_exact(const float *sJ, int jp, int y0, int x0, int H,
+                                               int W, int r, int c, double spr, double N,
+                                               double objlim) {
+    const double m3 = (double)med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, 0, 0), jp);
+    int n = 0;
+#pragma unroll 1
+    for (int i = 0; i < 7; ++i) {
 #pragma unroll
-    for (int i = 0; i < 7; ++i)
-#pragma unroll
-        for (int j = 0; j < 7; ++j)
-            w7[i * 7 + j] = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, i - 3, j - 3), jp);
-    med7_t1x1(w7, m7);
-    double fh = ((double)w7[24] - (double)m7[0]) / N;
-    return fh < 0.01 ? 0.01 : fh;
+        for (int j = 0; j < 7; ++j) {
+            const double x = (double)med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, i - 3, j - 3), jp);
+            double fh = (m3 - x) / N;
+            fh = fh < 0.01 ? 0.01 : fh;
+            n += spr / fh > objlim ? 1 : 0;
+        }
+    }
+    return n >= 25;
+}
+
+// The switching values of the contrast test below, from med3 (m3) and med5(J) (m5) at
+// the pixel: a window value x > t_sure makes the test hold for every S' >= lo, one with
+// x >= t_maybe lets it hold for some S' <= hi.
+__device__ __forceinline__ void contrast_thresholds(float m3, float m5, const SEstParams &p,
+                                                    float lo, float hi, float inv_olim,
+                                                    float &t_sure, float &t_maybe) {
+    float m = m5 + p.sky;
+    m = (m <= 0.0f) ? 1e-4f : m;
+    const float t = fmaf(p.gain, m, p.rn2);
+    const float N = t * __builtin_amdgcn_rsqf(t) * p.inv_gain;
+    const float klo = N * lo * inv_olim, khi = N * hi * inv_olim;
+    t_sure = (m3 - klo) + fmaf(0x1p-19f, fabsf(m3) + klo, 0x1p-126f);
+    t_maybe = (m3 - khi) - fmaf(0x1p-19f, fabsf(m3) + khi, 0x1p-126f);
 }
 
 // The contrast test S'/F^ > objlim at tile pixel (r, c), for every S' in [lo, hi]
@@ -239,16 +262,32 @@ __device__ __forceinline__ int contrast_by_count(const float *sJ, int jp, int y0
     const int l49 = lane < 49 ? lane : 24;
     const float x = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, l49 / 7 - 3, l49 % 7 - 3), jp);
     const float m3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 24));
-    float m = m5 + p.sky;
-    m = (m <= 0.0f) ? 1e-4f : m;
-    const float t = fmaf(p.gain, m, p.rn2);
-    const float N = t * __builtin_amdgcn_rsqf(t) * p.inv_gain;
-    const float klo = N * lo * inv_olim, khi = N * hi * inv_olim;
-    // x > t_sure: holds for every S' >= lo; x >= t_maybe: may hold for some S' <= hi
-    const float t_sure = (m3 - klo) + fmaf(0x1p-19f, fabsf(m3) + klo, 0x1p-126f);
-    const float t_maybe = (m3 - khi) - fmaf(0x1p-19f, fabsf(m3) + khi, 0x1p-126f);
+    float t_sure, t_maybe;
+    contrast_thresholds(m3, m5, p, lo, hi, inv_olim, t_sure, t_maybe);
     const int sure = __popcll(__ballot(lane < 49 && x > t_sure));
     const int maybe = __popcll(__ballot(lane < 49 && x >= t_maybe));
+    return sure >= 25 ? 1 : (maybe < 25 ? 0 : -1);
+}
+
+// The same test by one thread (for pixels beyond the contrast list): the 49 med3 values
+// one after another.
+__device__ __forceinline__ int contrast_by_count_lane(const float *sJ, int jp, int y0, int x0,
+                                                      int H, int W, int r, int c, float m5,
+                                                      const SEstParams &p, float lo, float hi,
+                                                      float inv_olim) {
+    const float m3 = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, 0, 0), jp);
+    float t_sure, t_maybe;
+    contrast_thresholds(m3, m5, p, lo, hi, inv_olim, t_sure, t_maybe);
+    int sure = 0, maybe = 0;
+#pragma unroll 1
+    for (int i = 0; i < 7; ++i) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            const float x = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, i - 3, j - 3), jp);
+            sure += x > t_sure ? 1 : 0;
+            maybe += x >= t_maybe ? 1 : 0;
+        }
+    }
     return sure >= 25 ? 1 : (maybe < 25 ? 0 : -1);
 }
 
@@ -294,7 +333,9 @@ constexpr int kRun3 = 14;
 constexpr int kExactBatch = kThreads / 25;
 // pixels whose contrast test a block lists for its contrast phase (further ones are
 // re-evaluated in binary64)
-constexpr int kConMax = 128;
+constexpr int kConMax = 32;
+// work-set pixels a block lists; a larger work set is taken from its bitmap instead
+constexpr int kListMax = 512;
 
 template <int TY, int TX>
 struct DetectLayout {
@@ -307,7 +348,7 @@ struct DetectLayout {
     static constexpr int kTileWords = TY * QW;
     static_assert(TX % 32 == 0 && kTileWords == 64, "one wave scans a tile bitmap");
     static_assert(QW + 1 <= HW, "dilation reads two bitmap words per work word");
-    static_assert(SH * SWP * 4 >= kExactBatch * 25 * 8, "re-evaluation buffer in the S plane");
+    static_assert(SH * SWP * 4 >= kExactBatch * 26 * 8, "re-evaluation buffer in the S plane");
 };
 
 // Which pixels need S', F^ and the threshold bits.  With H = {S > sigclip} (S' > t
@@ -328,7 +369,7 @@ struct DetectLayout {
 // are 0, and the grow, which reads codes only through its two dilations, sees the full
 // definition.
 template <int TY, int TX>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6)))
 void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
               DevFrame single, int kiter) {
     using L = DetectLayout<TY, TX>;
@@ -337,11 +378,12 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     __shared__ __align__(16) uint8_t sCode[TY * TX];
     __shared__ uint32_t sHot[L::SH * L::HW];                // H', apron 2, in-frame
     __shared__ uint32_t sU[L::kTileWords], sUpre[L::kTileWords + 1];
-    __shared__ uint32_t sLow[L::kTileWords];     // tile cells where S may exceed sigfrac*sigclip
+    // tile cells where S may exceed sigfrac*sigclip; after the work-set build, Q' itself
+    __shared__ uint32_t sLow[L::kTileWords];
     __shared__ unsigned int sErrBits, sContrast, sUncertain, sQcount, sNeedCount, sExactCells,
         sConCount;
     double *const sX = reinterpret_cast<double *>(sS);
-    __shared__ uint16_t sList[TY * TX];                     // work set Q'
+    __shared__ uint16_t sList[kListMax];                    // work set Q' (up to kListMax)
     // pixels whose contrast test is left to the contrast phase: position, S' interval
     __shared__ uint32_t sConInfo[kConMax];
     __shared__ float sConLo[kConMax], sConHi[kConMax], sConM5[kConMax];
@@ -675,14 +717,17 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         else if (vc < 32)
             q &= (1u << vc) - 1u;
         q &= sLow[tid];
+        sLow[tid] = q;
         if (all_exact)
             sU[tid] = q;
         const unsigned int cnt = (unsigned int)__popc(q);
         unsigned int at = __ockl_wfscan_add_u32(cnt, false);
-        for (uint32_t m = q; m; m &= m - 1u)
-            sList[at++] = (uint16_t)(tid * 32 + __ffs(m) - 1);   // = r * TX + column
-        if (tid == 63)
-            sQcount = at;
+        const unsigned int qtotal = (unsigned int)__builtin_amdgcn_readlane((int)(at + cnt), 63);
+        if (qtotal <= (unsigned int)kListMax)
+            for (uint32_t m = q; m; m &= m - 1u)
+                sList[at++] = (uint16_t)(tid * 32 + __ffs(m) - 1);   // = r * TX + column
+        if (tid == 0)
+            sQcount = qtotal;
     }
     __syncthreads();
 
@@ -690,16 +735,20 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     const double rn2 = rn * rn, sigclip = f.sigclip, objlim = f.objlim;
     const double lowlim = (double)f.sigfrac * (double)f.sigclip;
     const int total = (int)sQcount;
-    // the work set, compacted: thread t takes the t-th, (t+256)-th, ... pixel of Q'.
+    // the work set, compacted: thread t takes the t-th, (t+256)-th, ... pixel of Q' (of
+    // the tile, tested against the Q' bitmap, when the list could not hold Q').
     // S' from the estimates lies within B of the binary64 S' (B covers twice the
     // block's largest error and, with 4u, the roundings of the differences)
+    const bool listed_q = total <= kListMax;
     if (!all_exact) {
         const float b2 = 2.02f * emax;
         const float olim = f.objlim;
         const float olim_lo = olim * (1.0f - 0x1p-21f), olim_hi = olim * (1.0f + 0x1p-21f);
         unsigned int ncontrast = 0u, nunc = 0u;
-        for (int qi = tid; qi < total; qi += kThreads) {
-            const int pos = sList[qi];
+        for (int qi = tid; qi < (listed_q ? total : TY * TX); qi += kThreads) {
+            const int pos = listed_q ? (int)sList[qi] : qi;
+            if (!listed_q && !((sLow[pos >> 5] >> (pos & 31)) & 1u))
+                continue;
             const int r = pos / TX, c = pos - r * TX;
             float w[25], ms[1];
 #pragma unroll
@@ -713,7 +762,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             const float lo = spr - B, hi = spr + B;
             const bool h1 = lo > sc_hi, h0 = hi <= sc_lo, l1 = lo > ll_hi, l0 = hi <= ll_lo;
             bool unc = !((h1 || h0) && (l1 || l0));
-            bool listed = false;
+            bool listed = false, first = false;
             if (!unc && h1) {
                 // S'/F^ <= S'/0.01 <= objlim for the whole interval: the test fails
                 if (hi * 100.0f <= olim_lo) {
@@ -722,22 +771,26 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                     unc = true;
                 } else {
                     const unsigned int slot = atomicAdd(&sConCount, 1u);
+                    // med5(J) at the pixel, for N
+                    float w5[25], m5[1];
+#pragma unroll
+                    for (int i = 0; i < 5; ++i)
+#pragma unroll
+                        for (int j = 0; j < 5; ++j)
+                            w5[i * 5 + j] = sJ[(r + 2 + i) * L::JWP + c + 2 + j];
+                    med5_t1x1(w5, m5);
                     if (slot < (unsigned int)kConMax) {
-                        // med5(J) at the pixel, for N
-                        float w5[25], m5[1];
-#pragma unroll
-                        for (int i = 0; i < 5; ++i)
-#pragma unroll
-                            for (int j = 0; j < 5; ++j)
-                                w5[i * 5 + j] = sJ[(r + 2 + i) * L::JWP + c + 2 + j];
-                        med5_t1x1(w5, m5);
                         sConInfo[slot] = (uint32_t)pos | (l1 ? 1u << 16 : 0u);
                         sConLo[slot] = lo;
                         sConHi[slot] = hi;
                         sConM5[slot] = m5[0];
                         listed = true;
                     } else {
-                        unc = true;
+                        const int t = contrast_by_count_lane(sJ, L::JWP, y0, x0, H, W, r, c,
+                                                             m5[0], sp, lo, hi, 1.0f / olim);
+                        first = t > 0;
+                        unc = t < 0;
+                        ncontrast += unc ? 0u : 1u;
                     }
                 }
             }
@@ -745,7 +798,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 atomicOr(&sU[pos >> 5], 1u << (pos & 31));
                 ++nunc;
             } else if (!listed) {
-                sCode[pos] = (uint8_t)((h1 ? 2 : 0) | (l1 ? 4 : 0));
+                sCode[pos] = (uint8_t)((first ? 1 : 0) | (h1 ? 2 : 0) | (l1 ? 4 : 0));
             }
         }
         if (ncontrast && (f.flags & kCountWork))
@@ -805,15 +858,25 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                 sX[slot * 25 + cell] = s_exact(J, H, W, gy, gx, gain, sky, rn2);
             }
             __syncthreads();
+            // med5 of the window by ranks: the value with at most 12 smaller and at
+            // least 13 not larger (equal values write the same median)
+            if (slot < kExactBatch && base + slot < nunc) {
+                const double v = sX[slot * 25 + cell];
+                int lt = 0, le = 0;
+#pragma unroll 5
+                for (int q = 0; q < 25; ++q) {
+                    const double u = sX[slot * 25 + q];
+                    lt += u < v ? 1 : 0;
+                    le += u <= v ? 1 : 0;
+                }
+                if (lt <= 12 && le >= 13)
+                    sX[kExactBatch * 25 + slot] = v;
+            }
+            __syncthreads();
             if (tid < kExactBatch && base + tid < nunc) {
                 const int pos = bitmap_select64(sU, sUpre, base + tid);
                 const int r = pos / TX, c = pos - r * TX;
-                double v[25], ms[1];
-#pragma unroll
-                for (int i = 0; i < 25; ++i)
-                    v[i] = sX[tid * 25 + i];
-                med5_t1x1(v, ms);
-                const double spr = v[12] - ms[0];
+                const double spr = sX[tid * 25 + 12] - sX[kExactBatch * 25 + tid];
                 const bool hbit = spr > sigclip, lbit = spr > lowlim;
                 bool first = false;
                 if (hbit) {
@@ -824,9 +887,8 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                         for (int j = 0; j < 5; ++j)
                             w5[i * 5 + j] = sJ[(r + 2 + i) * L::JWP + c + 2 + j];
                     med5_t1x1(w5, m5);
-                    const double fh = fine_structure(sJ, L::JWP, y0, x0, H, W, r, c,
-                                                     noise_exact(m5[0], gain, sky, rn2));
-                    first = spr / fh > objlim;
+                    first = contrast_exact(sJ, L::JWP, y0, x0, H, W, r, c, spr,
+                                           noise_exact(m5[0], gain, sky, rn2), objlim);
                     ++ncontrast;
                 }
                 sCode[pos] = (uint8_t)((first ? 1 : 0) | (hbit ? 2 : 0) | (lbit ? 4 : 0));
