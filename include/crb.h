@@ -336,8 +336,8 @@ crb_status crb_debug_s_estimate(const float *J, const crb_frame *params, float *
  * sorted columns, 5x5 by the network for a 2 x 2 tile of outputs, 7x7 by the
  * single-output one). */
 crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out);
-/* Clamped 5x5 median filter of binary64 values by the single-output network the
- * detection applies to S. */
+/* Clamped 5x5 median filter of binary64 values by the single-output network that the
+ * detection applies to its FP32 estimates of S (here on binary64 inputs). */
 crb_status crb_debug_median5_f64(const double *in, int32_t H, int32_t W, double *out);
 /* Elementwise binary64 sqrt(x) and x / y on the device (rounding checks). */
 crb_status crb_debug_fp64(const double *x, const double *y, int32_t n, double *out_sqrt,

@@ -324,15 +324,16 @@ __device__ __forceinline__ int bitmap_select64(const uint32_t *bits, const uint3
     return lo * 32 + __ffs(b) - 1;
 }
 
-// Work shapes inside a detection block: med3 in runs of kRun3 outputs; a lower bound of
-// med5(J), L+ and an upper bound of S in 2 x 5 thread tiles over the whole tile and its
-// 2-pixel apron; med5(J) and the S estimate in 2 x 2 quads near where S may exceed
-// sigclip.  The remaining statistics are evaluated only where a code bit can matter.
+// Work shapes inside a detection block: a lower bound of med5(J), L+ and an upper bound
+// of S in 2 x 5 thread tiles over the whole tile and its 2-pixel apron; med5(J) and the S
+// estimate in 2 x 2 quads near where S may exceed sigclip.  The remaining statistics,
+// med3 among them, are evaluated only where a code bit can matter.
+// Run length of the 3x3 median network's parity kernel (sorted columns shared by runs).
 constexpr int kRun3 = 14;
 // pixels per round of the binary64 re-evaluation (25 threads each)
 constexpr int kExactBatch = kThreads / 25;
-// pixels whose contrast test a block lists for its contrast phase (further ones are
-// re-evaluated in binary64)
+// pixels whose contrast test a block lists for its contrast phase (one wave each);
+// further ones take the same test in their own lanes
 constexpr int kConMax = 32;
 // work-set pixels a block lists; a larger work set is taken from its bitmap instead
 constexpr int kListMax = 512;
@@ -976,8 +977,8 @@ __global__ __launch_bounds__(kThreads) void k_debug_median(const float *__restri
                 out[(size_t)(y0 + i) * W + x0 + j] = o[i * TX + j];
 }
 
-// 5x5 clamped median of binary64 values by the single-output network the detection
-// kernel applies to S.
+// 5x5 clamped median of binary64 values by the single-output network (the one the
+// detection applies to the FP32 estimates of S, here on binary64 inputs).
 __global__ __launch_bounds__(kThreads) void k_debug_median5_f64(const double *__restrict__ in,
                                                                 int H, int W,
                                                                 double *__restrict__ out) {
