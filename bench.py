@@ -71,9 +71,9 @@ KERNEL_SOURCES = ("csrc/detect.hip", "csrc/device_common.h", "csrc/kernels.h", "
 COUNTERS_SUMMARY = os.path.join(ROOT, "profiles", "k_detect_batch64_counters.md")
 
 
-def profiled_traffic():
-    """HBM bytes per detection launch from the committed counter summary, if it was
-    taken on the current kernel sources (else None)."""
+def profiled_value(key):
+    """An integer per detection launch from the committed counter summary (HBM bytes,
+    VALU wave-instructions), if it was taken on the current kernel sources (else None)."""
     import hashlib
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
@@ -91,7 +91,7 @@ def profiled_traffic():
     if vals.get("kernel_source_sha256") != h.hexdigest():
         return None
     try:
-        return int(vals["traffic_bytes_per_launch"])
+        return int(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -312,7 +312,8 @@ def main():
                                       "binary64 re-evaluation where the bound cannot decide)",
             "achieved": round(achieved / 1e12, 3), "peak": round(roofline.ALU_PEAK / 1e12, 3),
             "unit": "Tlane-op/s", "frac": round(achieved / roofline.ALU_PEAK, 4),
-            "traffic": profiled_traffic() if args.workload == "c4" else None,
+            "traffic": profiled_value("traffic_bytes_per_launch") if args.workload == "c4"
+                       else None,
             "ops_per_launch": round(ops_launch),
             "ops_per_pixel": round(ops_launch / total_px, 2),
             "dense_ops_per_pixel": round(o["dense"]["total"], 2),
@@ -324,6 +325,13 @@ def main():
             "reevaluated_per_launch": round(work["reevaluated"] / 4.0, 2),
             "pixels_per_launch": total_px, "avg_launch_ms": round(det_avg_s * 1e3, 4),
             "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()}}
+    # issued VALU lane-operations (wave-instructions x 64, from the committed counters of
+    # the same kernel sources) against the same peak: how busy the ALUs are, as opposed
+    # to how much of the issue is algorithmic work
+    valu = profiled_value("valu_instructions_per_launch") if args.workload == "c4" else None
+    roof["issued_lane_op_frac"] = (round(valu * 64 / det_avg_s / roofline.ALU_PEAK, 4)
+                                   if valu else None)
+    roof["valu_instructions_per_pixel"] = round(valu * 64 / total_px, 1) if valu else None
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
