@@ -388,6 +388,13 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // pixels whose contrast test is left to the contrast phase: position, S' interval
     __shared__ uint32_t sConInfo[kConMax];
     __shared__ float sConLo[kConMax], sConHi[kConMax], sConM5[kConMax];
+    // 6 blocks per CU: a block of 27,088 bytes already ran as 5 (the CU does not hand out
+    // all 160 KiB in sixths), so the planes and lists stay within 26,624 bytes
+    static_assert(sizeof(sJ) + sizeof(sS) + sizeof(sCode) + sizeof(sHot) + sizeof(sU) +
+                          sizeof(sUpre) + sizeof(sLow) + sizeof(sList) + sizeof(sConInfo) +
+                          sizeof(sConLo) + sizeof(sConHi) + sizeof(sConM5) + 7 * 4 <=
+                      26624,
+                  "the LDS of a detection block must let 6 blocks share a CU");
 
     DevFrame f;
     int y0, x0;
