@@ -95,7 +95,9 @@ FrameWs ws_layout(int32_t H, int32_t W) {
     L.dirty = align_up(L.listlen + 4 * (size_t)kMaxIter, 256);
     const size_t ntiles = (size_t)((H + kDetectTY - 1) / kDetectTY) *
                           (size_t)((W + kDetectTX - 1) / kDetectTX);
-    L.total = align_up(L.dirty + ntiles, 256);
+    L.tile_first = align_up(L.dirty + ntiles, 256);
+    L.tile_new = align_up(L.tile_first + ntiles, 256);
+    L.total = align_up(L.tile_new + 4 * ntiles, 256);
     return L;
 }
 
@@ -107,12 +109,16 @@ DevFrame make_devframe(const float *img, float *J, uint8_t *mask, char *ws, cons
     f.img = img;
     f.J = J;
     f.mask = mask;
-    f.codes = reinterpret_cast<uint8_t *>(ws + L.codes);
     f.g2 = nullptr;
-    f.list = reinterpret_cast<uint32_t *>(ws + L.list);
-    f.nnew = reinterpret_cast<unsigned long long *>(ws + L.nnew);
-    f.listlen = reinterpret_cast<unsigned int *>(ws + L.listlen);
-    f.dirty = reinterpret_cast<uint8_t *>(ws + L.dirty);
+    if (ws) {      // without a workspace every workspace pointer stays null
+        f.codes = reinterpret_cast<uint8_t *>(ws + L.codes);
+        f.list = reinterpret_cast<uint32_t *>(ws + L.list);
+        f.nnew = reinterpret_cast<unsigned long long *>(ws + L.nnew);
+        f.listlen = reinterpret_cast<unsigned int *>(ws + L.listlen);
+        f.dirty = reinterpret_cast<uint8_t *>(ws + L.dirty);
+        f.tile_first = reinterpret_cast<uint8_t *>(ws + L.tile_first);
+        f.tile_new = reinterpret_cast<unsigned int *>(ws + L.tile_new);
+    }
     f.H = H;
     f.W = W;
     f.gain = gain;
@@ -470,9 +476,6 @@ static crb_status debug_detect(const float *J, const crb_frame *p, uint8_t *out_
                                p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
                                p->sigfrac, p->objlim, 1, kNoEarlyStop | flags);
     f.codes = out_codes;
-    f.nnew = nullptr;
-    f.listlen = nullptr;
-    f.list = nullptr;
     return hip_status(launch_detect(nullptr, nullptr, 0, f, 1, t_stream), "kernel launch") ==
                    CRB_OK
                ? ok()

@@ -9,7 +9,7 @@ namespace crb {
 
 // Byte offsets of one frame's workspace pieces (256-byte aligned).
 struct FrameWs {
-    size_t codes, list, nnew, listlen, dirty, total;
+    size_t codes, list, nnew, listlen, dirty, tile_first, tile_new, total;
 };
 
 crb_status fail(crb_status st, const char *fmt, ...);

@@ -48,9 +48,17 @@ struct DevFrame {
     uint8_t *g2;                  // optional: selection of this iteration (debug), or null
     uint32_t *list;               // indices of flagged pixels, H x W capacity (workspace)
     unsigned long long *nnew;     // n_k per iteration [kMaxIter] (workspace)
-    unsigned int *listlen;        // list length per iteration [kMaxIter] (workspace)
+    unsigned int *listlen;        // [0]: length of the flagged list, which holds the pixels of
+                                  // the mask in the order they were flagged (workspace)
     unsigned long long *work;     // with kCountWork: kWorkCounters counters, or null
     uint8_t *dirty;               // detection tiles to re-evaluate (kIncremental), row-major
+    // per detection tile, row-major, written by detection: bit 0 some pixel of the tile
+    // has A (the first selection), bit 1 one of its first two rows, bit 2 one of its last
+    // two (the grow skips strips with no A within its 2-pixel reach), or null
+    uint8_t *tile_first;
+    // per detection tile: the last iteration whose grow flagged a new pixel in it (the
+    // replacement leaves alone pixels with no new flag within 2 pixels), or null
+    unsigned int *tile_new;
     int H, W;
     float gain, readnoise, sky, sigclip, sigfrac, objlim;
     int niter;

@@ -40,7 +40,10 @@ namespace crb {
 // first selection at y, then G1 at y-1 (vertical OR of three rows, gated by
 // S' > sigclip), then G2 at y-2 (gated by S' > sigfrac*sigclip).  No LDS and no
 // block barrier.  The flagged list is written row by row across the wave, so
-// consecutive entries are neighbours in a row.
+// consecutive entries are neighbours in a row.  Iteration 1 lists the whole mask; later
+// iterations append their new flags only, and a strip with no first selection within
+// reach returns at once (after the first iteration A is rare: the flagged pixels have
+// been replaced).
 
 constexpr uint32_t kByteLsb = 0x01010101u;
 
@@ -125,6 +128,29 @@ __device__ __forceinline__ Px16 load16_aligned(const uint8_t *__restrict__ p, in
     return Px16{{q.x & m, q.y & m, q.z & m, q.w & m}};
 }
 
+// Whether a strip of rows y0 .. y0+TYG-1 and columns x0 .. x0+kGrowTX-1 can gain a
+// flag: G2 lies within 2 pixels of A (two 3x3 dilations), so with no A in the detection
+// tiles within that reach the strip keeps its mask.  A tile that the reach enters by
+// its first or last two rows only is judged by those rows.  Called by a whole wave.
+template <int TYG>
+__device__ __forceinline__ bool strip_near_first(const DevFrame &f, int y0, int x0, int lane) {
+    // a strip lies in one row of detection tiles, so its reach touches at most three
+    static_assert(kDetectTY % TYG == 0 && 3 * ((kGrowTX + 3) / kDetectTX + 2) <= 64,
+                  "one lane per detection tile within reach");
+    const int H = f.H, W = f.W;
+    const int ylo = max(y0 - 2, 0), yhi = min(y0 + TYG + 1, H - 1);
+    const int xlo = max(x0 - 2, 0), xhi = min(x0 + kGrowTX + 1, W - 1);
+    const int r0 = ylo / kDetectTY, c0 = xlo / kDetectTX;
+    const int ncol = xhi / kDetectTX - c0 + 1;
+    bool hit = false;
+    if (lane < (yhi / kDetectTY - r0 + 1) * ncol) {
+        const int r = r0 + lane / ncol, c = c0 + lane % ncol, top = r * kDetectTY;
+        const unsigned int need = ylo >= top + kDetectTY - 2 ? 4u : (yhi < top + 2 ? 2u : 1u);
+        hit = (f.tile_first[r * ((W + kDetectTX - 1) / kDetectTX) + c] & need) != 0u;
+    }
+    return __ballot(hit) != 0ull;
+}
+
 // One wave's strip: rows y0 .. y0+TYG-1 of the 992-pixel column group at x0.  With
 // ALIGNED (the width a multiple of 16) every load is branch-free and the code and mask
 // rows are fetched kAhead rows before their use, so several are in flight at once.
@@ -135,13 +161,18 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
     const bool fresh = k == 1 && (f.flags & kFreshMask);   // mask not yet initialised
     const int px = x0 - 16 + 16 * lane;                // first pixel of this lane's group
     const bool owner = lane >= 1 && lane <= kGrowTX / 16 && px < W;
+    // from iteration 2 on the list already holds M_{k-1} and takes only the new flags
+    const bool list_new = k >= 2;
+    if (list_new && !f.g2 && f.tile_first && !strip_near_first<TYG>(f, y0, x0, lane))
+        return;
 
     Px16 hA0 = {}, hA1 = {};          // dilated first selection, rows y-2, y-1
     Px16 hi1 = {};                    // [S' > sigclip] at row y-1
     Px16 lo1 = {}, lo2 = {};          // [S' > low] at rows y-1, y-2
     Px16 hG0 = {}, hG1 = {};          // dilated G1 at rows y-3, y-2
-    uint32_t mbits[TYG / 2];          // mask bits of the strip, 16 per row
-    unsigned int nnew = 0, nm = 0;
+    uint32_t mbits[TYG / 2];          // listed bits of the strip, 16 per row
+    unsigned int nnew = 0, nm = 0;    // new flags, listed flags
+    bool lane_new = false;
     Px16 cring[kAhead], mring[kAhead];
     if constexpr (ALIGNED) {
 #pragma unroll
@@ -188,7 +219,7 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
                 if (fresh)
                     mp = Px16{};
             }
-            uint32_t m16 = 0;
+            uint32_t m16 = 0;                        // listed flags of the row
             if (owner && y - 2 < H) {
                 if constexpr (!ALIGNED)
                     mp = fresh ? Px16{} : load16(f.mask, y - 2, px, H, W, false);
@@ -200,12 +231,13 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
                     m.d[q] = mp.d[q] | g2.d[q];
                     anynew |= nw;
                     nnew += (unsigned int)__popc(nw);
-                    m16 |= squeeze4(m.d[q]) << (4 * q);
+                    m16 |= squeeze4(list_new ? nw : m.d[q]) << (4 * q);
                 }
                 if (anynew || fresh)
                     store16(f.mask, y - 2, px, W, ALIGNED, m);
                 if (f.g2)
                     store16(f.g2, y - 2, px, W, ALIGNED, g2);
+                lane_new |= anynew != 0u;
                 nm += (unsigned int)__popc(m16);
             }
             if (r & 1)
@@ -218,6 +250,10 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
         hi1 = hi2;
         hG0 = hG1; hG1 = hG2;
     }
+    // the strip lies in one row of detection tiles, and a lane's 16 pixels in one tile
+    if (lane_new && f.tile_new)
+        f.tile_new[(y0 / kDetectTY) * ((W + kDetectTX - 1) / kDetectTX) + px / kDetectTX] =
+            (unsigned int)k;
     // one atomic per wave for the count and one for the list space; one scan of the
     // lanes' counts places each lane's entries (its rows in order) in the wave's space
     const unsigned int tn = __ockl_wfred_add_u32(nnew);
@@ -232,7 +268,7 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
     if (lane == 0) {
         if (tn)
             atomicAdd(&f.nnew[k - 1], (unsigned long long)tn);
-        base = atomicAdd(&f.listlen[k - 1], total);
+        base = atomicAdd(&f.listlen[0], total);
     }
     unsigned int off = (unsigned int)__builtin_amdgcn_readfirstlane((int)base) + incl - nm;
 #pragma unroll
@@ -247,9 +283,10 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
 }
 
 template <int TYG>
-__global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ frames,
-                                                   const TileRef *__restrict__ tiles,
-                                                   DevFrame single, int kiter, int ntiles) {
+// 3 waves per SIMD: at most 168 VGPRs (the 32-row strip needs about that many)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_grow(
+    const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles, DevFrame single,
+    int kiter, int ntiles) {
     const int lane = threadIdx.x & 63;
     const int wt = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);   // wave tile index
     if (wt >= ntiles)
@@ -285,9 +322,23 @@ __global__ __launch_bounds__(kThreads) void k_grow(const DevFrame *__restrict__ 
 // values of the window are loaded unconditionally (clamped addresses are always
 // valid), so the 50 loads are in flight together; a flagged neighbour's J may be
 // rewritten meanwhile by another thread, and that value is discarded.
-__device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p) {
+__device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p, int k) {
     const int W = f.W, H = f.H;
     const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * (uint32_t)W);
+    // From iteration 2 on, J differs from the input only at pixels of M_{k-1}, whose
+    // values the previous replacement took from the unflagged input pixels of their
+    // windows.  A pixel of M_{k-1} with no new flag within 2 pixels has the same
+    // unflagged window now, so it keeps its value: a tile with no new flag of this
+    // iteration (its stamp is not k) within reach means nothing to do.
+    if (k >= 2 && f.tile_new) {
+        const int tx = (W + kDetectTX - 1) / kDetectTX;
+        const int r0 = max(y - 2, 0) / kDetectTY, r1 = min(y + 2, H - 1) / kDetectTY;
+        const int c0 = max(x - 2, 0) / kDetectTX, c1 = min(x + 2, W - 1) / kDetectTX;
+        const unsigned int *t = f.tile_new, uk = (unsigned int)k;
+        if (t[r0 * tx + c0] != uk && t[r0 * tx + c1] != uk && t[r1 * tx + c0] != uk &&
+            t[r1 * tx + c1] != uk)
+            return;
+    }
     float v[25];
     uint8_t mk[25];
 #pragma unroll
@@ -346,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_list_prefix(const DevFrame *__rest
         if (i < nframes) {
             const DevFrame &f = frames[i];
             const int k = kiter ? kiter : f.k;
-            len = frame_skips(f, k) ? 0u : f.listlen[k - 1];
+            len = frame_skips(f, k) ? 0u : f.listlen[0];
         }
         sPart[threadIdx.x] = len;
         __syncthreads();
@@ -377,9 +428,9 @@ __global__ __launch_bounds__(kThreads) void k_replace(const DevFrame *__restrict
         const int k = kiter ? kiter : single.k;
         if (frame_skips(single, k))
             return;
-        const unsigned int n = single.listlen[k - 1];
+        const unsigned int n = single.listlen[0];
         for (; i < n; i += stride)
-            replace_one(single, single.list[i]);
+            replace_one(single, single.list[i], k);
         return;
     }
     const unsigned int total = prefix[nframes];
@@ -409,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_replace(const DevFrame *__restrict
         while (prefix[lo + 1] <= i)
             ++lo;
         const DevFrame &f = frames[lo];
-        replace_one(f, f.list[i - prefix[lo]]);
+        replace_one(f, f.list[i - prefix[lo]], kiter ? kiter : f.k);
     }
 }
 

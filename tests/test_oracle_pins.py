@@ -570,3 +570,36 @@ def test_invalid_arguments_rejected():
                dict(gain=float("nan"), readnoise=5.0)]:
         with pytest.raises(ValueError):
             ref.lacosmic(img, **kw)
+
+
+def test_later_iterations_change_only_near_new_flags():
+    """Two invariants of the method (Section 5's iteration) that the GPU grow and
+    replacement use from iteration 2 on, checked on the oracle's own runs:
+    G2 lies within Chebyshev distance 2 of A (two 3x3 dilations), and a pixel flagged
+    before with no new flag within 2 px keeps its value (only flagged pixels ever
+    change, so its unflagged window is the same as at the previous replacement).  The
+    frame also has flagged pixels that do change because a new flag appeared near them,
+    the case that must not be left out."""
+    from scipy.ndimage import maximum_filter
+
+    def within2(b):
+        return maximum_filter(b.astype(np.uint8), size=5, mode="nearest").astype(bool)
+
+    f = synth.c2()
+    J = np.ascontiguousarray(f.img[:230, :301]).astype(np.float64)
+    M = np.zeros(J.shape, np.uint8)
+    changed_near_new = kept = 0
+    for k in range(1, 5):
+        r = ref.iterate(J, M, f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac, f.objlim,
+                        trace=True)
+        A, G2 = r["first"].astype(bool), r["g2"].astype(bool)
+        assert not (G2 & ~within2(A)).any()
+        if k >= 2:
+            old = M.astype(bool)
+            near = within2(G2 & ~old)
+            keep = old & ~near
+            assert (r["Jnext"][keep] == J[keep]).all()
+            kept += int(keep.sum())
+            changed_near_new += int((r["Jnext"][old & near] != J[old & near]).sum())
+        J, M = r["Jnext"], r["M"]
+    assert kept > 0 and changed_near_new > 0
