@@ -96,7 +96,7 @@ FrameWs ws_layout(int32_t H, int32_t W) {
     const size_t ntiles = (size_t)((H + kDetectTY - 1) / kDetectTY) *
                           (size_t)((W + kDetectTX - 1) / kDetectTX);
     L.tile_first = align_up(L.dirty + ntiles, 256);
-    L.tile_new = align_up(L.tile_first + ntiles, 256);
+    L.tile_new = align_up(L.tile_first + 4 * ntiles, 256);
     L.total = align_up(L.tile_new + 4 * ntiles, 256);
     return L;
 }

@@ -382,7 +382,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // tile cells where S may exceed sigfrac*sigclip; after the work-set build, Q' itself
     __shared__ uint32_t sLow[L::kTileWords];
     __shared__ unsigned int sErrBits, sContrast, sUncertain, sQcount, sNeedCount, sExactCells,
-        sConCount, sFirstRows;
+        sConCount;
     double *const sX = reinterpret_cast<double *>(sS);
     __shared__ uint16_t sList[kListMax];                    // work set Q' (up to kListMax)
     // pixels whose contrast test is left to the contrast phase: position, S' interval
@@ -392,7 +392,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // all 160 KiB in sixths), so the planes and lists stay within 26,624 bytes
     static_assert(sizeof(sJ) + sizeof(sS) + sizeof(sCode) + sizeof(sHot) + sizeof(sU) +
                           sizeof(sUpre) + sizeof(sLow) + sizeof(sList) + sizeof(sConInfo) +
-                          sizeof(sConLo) + sizeof(sConHi) + sizeof(sConM5) + 8 * 4 <=
+                          sizeof(sConLo) + sizeof(sConHi) + sizeof(sConM5) + 7 * 4 <=
                       26624,
                   "the LDS of a detection block must let 6 blocks share a CU");
 
@@ -445,7 +445,6 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         sNeedCount = 0u;
         sExactCells = 0u;
         sConCount = 0u;
-        sFirstRows = 0u;
     }
     // J over [y0-4, y0+TY+4) x [x0-4, x0+TX+4), clamped reads.  Thread t loads column
     // t % JW of rows t / JW + kJStep * b, so its clamped column is computed once and, on
@@ -909,33 +908,36 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         __syncthreads();
     }
 
-    // codes of the tile, 8 per thread; where A is set: anywhere, in the first two rows,
-    // in the last two (bits 0..2 of the tile's entry in f.tile_first)
+    // codes of the tile, 8 per thread: thread t writes row t / (TX/8), so wave w holds
+    // rows 8w .. 8w+7 and writes byte w of the tile's f.tile_first word: bit 0 where A
+    // is set in those rows, bit 1 where in rows 0-1, bit 2 where in rows TY-2 .. TY-1
+    static_assert(TY * TX / 8 == kThreads && TX == 64 && TY == 32, "one code word per thread");
     uint8_t *__restrict__ codes = f.codes;
-    unsigned int first_rows = 0u;
-    for (int i = tid; i < TY * TX / 8; i += kThreads) {
-        const int r = i / (TX / 8), c = (i - r * (TX / 8)) * 8;
+    {
+        const int r = tid / (TX / 8), c = (tid - r * (TX / 8)) * 8;
         const int gy = y0 + r, gx = x0 + c;
-        if (gy >= H || gx >= W)
-            continue;
-        uint8_t *dst = codes + (size_t)gy * W + gx;
         const uint2 word = *reinterpret_cast<const uint2 *>(&sCode[r * TX + c]);
-        if ((word.x | word.y) & 0x01010101u)
-            first_rows |= 1u | (r < 2 ? 2u : 0u) | (r >= TY - 2 ? 4u : 0u);
-        if (gx + 8 <= W && ((uintptr_t)dst & 7u) == 0u) {
-            *reinterpret_cast<uint2 *>(dst) = word;
-        } else {
-            const int nb = min(8, W - gx);
-            for (int b = 0; b < nb; ++b)
-                dst[b] = sCode[r * TX + c + b];
+        if (f.tile_first) {
+            const unsigned long long rows_a = __ballot(((word.x | word.y) & 0x01010101u) != 0u);
+            if ((tid & 63) == 0) {
+                const int w = tid >> 6;
+                const unsigned int bits = (rows_a ? 1u : 0u) |
+                                          (w == 0 && (rows_a & 0xFFFFull) ? 2u : 0u) |
+                                          (w == 3 && (rows_a >> 48) ? 4u : 0u);
+                f.tile_first[4 * ((y0 / TY) * ((W + TX - 1) / TX) + x0 / TX) + w] =
+                    (uint8_t)bits;
+            }
         }
-    }
-    if (f.tile_first) {
-        if (first_rows)
-            atomicOr(&sFirstRows, first_rows);
-        __syncthreads();
-        if (tid == 0)
-            f.tile_first[(y0 / TY) * ((W + TX - 1) / TX) + x0 / TX] = (uint8_t)sFirstRows;
+        if (gy < H && gx < W) {
+            uint8_t *dst = codes + (size_t)gy * W + gx;
+            if (gx + 8 <= W && ((uintptr_t)dst & 7u) == 0u) {
+                *reinterpret_cast<uint2 *>(dst) = word;
+            } else {
+                const int nb = min(8, W - gx);
+                for (int b = 0; b < nb; ++b)
+                    dst[b] = sCode[r * TX + c + b];
+            }
+        }
     }
     if ((f.flags & kCountWork) && tid == 0 && f.work) {
         if (total)

@@ -14,8 +14,10 @@ constexpr int kMaxIter = 1024;
 constexpr int kDetectTY = 32;
 constexpr int kDetectTX = 64;
 constexpr int kGrowTY = 32;
-constexpr int kGrowTYSmall = 8;     // strip height for single frames below 2^22 pixels
+constexpr int kGrowTYSmall = 8;     // strip height for single frames below 2^22 pixels and
+                                    // for every frame after iteration 1
 constexpr int kGrowTX = 992;
+static_assert(kGrowTY % kGrowTYSmall == 0, "a grow strip splits into short strips");
 constexpr int kThreads = 256;
 
 // Kernel classes for per-launch timing (crb_plan_kernel_times order).
@@ -52,9 +54,10 @@ struct DevFrame {
                                   // the mask in the order they were flagged (workspace)
     unsigned long long *work;     // with kCountWork: kWorkCounters counters, or null
     uint8_t *dirty;               // detection tiles to re-evaluate (kIncremental), row-major
-    // per detection tile, row-major, written by detection: bit 0 some pixel of the tile
-    // has A (the first selection), bit 1 one of its first two rows, bit 2 one of its last
-    // two (the grow skips strips with no A within its 2-pixel reach), or null
+    // 4 bytes per detection tile, row-major, written by detection (byte w for rows
+    // 8w .. 8w+7): bit 0 some pixel of those rows has A (the first selection), bit 1 one
+    // of the tile's first two rows, bit 2 one of its last two; the grow skips strips with
+    // no A within its 2-pixel reach.  Or null
     uint8_t *tile_first;
     // per detection tile: the last iteration whose grow flagged a new pixel in it (the
     // replacement leaves alone pixels with no new flag within 2 pixels), or null

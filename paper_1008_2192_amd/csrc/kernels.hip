@@ -146,7 +146,9 @@ __device__ __forceinline__ bool strip_near_first(const DevFrame &f, int y0, int 
     if (lane < (yhi / kDetectTY - r0 + 1) * ncol) {
         const int r = r0 + lane / ncol, c = c0 + lane % ncol, top = r * kDetectTY;
         const unsigned int need = ylo >= top + kDetectTY - 2 ? 4u : (yhi < top + 2 ? 2u : 1u);
-        hit = (f.tile_first[r * ((W + kDetectTX - 1) / kDetectTX) + c] & need) != 0u;
+        const uint32_t q = reinterpret_cast<const uint32_t *>(f.tile_first)
+                               [r * ((W + kDetectTX - 1) / kDetectTX) + c];
+        hit = ((q | q >> 8 | q >> 16 | q >> 24) & need) != 0u;   // the tile's four waves
     }
     return __ballot(hit) != 0ull;
 }
@@ -294,10 +296,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     DevFrame f;
     int y0, x0;
     if (tiles) {
-        const TileRef t = tiles[wt];
+        // a listed strip of kGrowTY rows is split over kGrowTY / TYG waves
+        constexpr int kSub = kGrowTY / TYG;
+        const TileRef t = tiles[wt / kSub];
         f = frames[t.frame];
         y0 = t.y0;
         x0 = t.x0;
+        if constexpr (kSub > 1) {
+            y0 += (wt % kSub) * TYG;
+            if (y0 >= f.H)
+                return;
+        }
     } else {
         f = single;
         const int ntx = (f.W + kGrowTX - 1) / kGrowTX;
@@ -599,12 +608,21 @@ hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int nti
     if (d_tiles) {
         if (ntiles <= 0)
             return hipSuccess;
-        k_grow<kGrowTY><<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(d_frames, d_tiles, single,
-                                                                       k, ntiles);
+        if (k >= 2) {
+            // after iteration 1 few strips are near A and each runs alone: a wave per
+            // 8-row part of a listed strip shortens the row chain it waits on
+            const int n = ntiles * (kGrowTY / kGrowTYSmall);
+            k_grow<kGrowTYSmall><<<(n + wpb - 1) / wpb, kThreads, 0, s>>>(d_frames, d_tiles,
+                                                                           single, k, n);
+        } else {
+            k_grow<kGrowTY><<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(d_frames, d_tiles,
+                                                                           single, k, ntiles);
+        }
         return hipGetLastError();
     }
-    // a single frame: short strips when the frame is small, so more waves share it
-    const bool small = (size_t)single.H * single.W < ((size_t)1 << 22);
+    // a single frame: short strips when the frame is small, so more waves share it, and
+    // after iteration 1
+    const bool small = k >= 2 || (size_t)single.H * single.W < ((size_t)1 << 22);
     const int ty = small ? kGrowTYSmall : kGrowTY;
     ntiles = ((single.W + kGrowTX - 1) / kGrowTX) * ((single.H + ty - 1) / ty);
     if (small)
