@@ -347,6 +347,44 @@ def test_batched_matches_solo_and_oracle_counts():
         assert st["n_flagged"] == int(r["mask"].sum())
 
 
+def edge_frames():
+    """Frames wider than one grow strip (992 px) and taller than a row of detection tiles,
+    with c2's dense, long hits: iterations 2-4 flag hundreds of new pixels, many of them
+    next to pixels flagged before and on either side of strip and tile edges."""
+    return [synth.render(H, W, seed, sky_e=50.0, gain=7.0, readnoise=5.0, n_stars=40,
+                         star_fwhm=1.5, star_flux="lognormal", hit_coverage=0.02,
+                         hit_len=(1, 20), hit_amp=(100.0, 10000.0), name=f"{H}x{W}")
+            for (H, W, seed) in [(96, 2000, 61), (100, 1993, 62)]]
+
+
+def test_later_iterations_near_strip_and_tile_edges():
+    """After iteration 1 the grow runs only on strips within reach of A (8-row strips on
+    the batched path) and the replacement only near new flags: whole 4-iteration runs,
+    solo and batched, equal the oracle on frames where that matters at the edges."""
+    frames = edge_frames()
+    for f in frames:
+        # from the oracle alone: later iterations add flags on tile edges
+        J, M = f.img.astype(np.float64), np.zeros(f.img.shape, np.uint8)
+        at_edges = 0
+        for k in range(1, 5):
+            r = ref.iterate(J, M, **fparams(f))
+            ys, xs = np.nonzero((r["G2"] != 0) & (M == 0))
+            if k >= 2:
+                at_edges += int(((ys % 32 < 3) | (ys % 32 > 28) | (xs % 64 < 3) |
+                                 (xs % 64 > 60)).sum())
+            J, M = r["Jnext"], r["M"]
+        assert at_edges > 100, (f.name, at_edges)
+    items = make_items(frames, early_stop=False)
+    _lib.lacosmic_batched(items)
+    for f, it in zip(frames, items):
+        log(f"edge frame {f.name}")
+        r = ref.lacosmic(f.img, niter=4, early_stop=False, **fparams(f))
+        c, m = _lib.lacosmic(it["img"], niter=4, early_stop=False, **fparams(f))
+        torch.cuda.synchronize()
+        compare_end_to_end(f, c, m, r)
+        compare_end_to_end(f, it["out_clean"], it["out_mask"], r)
+
+
 def test_plan_graph_replays_match_solo():
     frames = small_frames()[:4]
     items = make_items(frames, early_stop=False)
