@@ -501,6 +501,22 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             }
         }
     }
+    // iteration 1 on an uninitialised mask: the tile's mask bytes are cleared here, so
+    // the grow writes only the rows that gain a flag
+    if (k == 1 && (f.flags & kFreshMask) && f.mask) {
+        const int r = tid / (TX / 8), cs = (tid - r * (TX / 8)) * 8;
+        const int gy = y0 + r, gx = x0 + cs;
+        if (gy < H && gx < W) {
+            uint8_t *dst = f.mask + (size_t)gy * W + gx;
+            if (gx + 8 <= W && ((uintptr_t)dst & 7u) == 0u) {
+                *reinterpret_cast<uint2 *>(dst) = make_uint2(0u, 0u);
+            } else {
+                const int nb = min(8, W - gx);
+                for (int j = 0; j < nb; ++j)
+                    dst[j] = 0;
+            }
+        }
+    }
 
     // Over [y0-2, y0+TY+2) x [x0-2, x0+TX+2), in one 2 x 5 cell tile per thread.
     // Dense pass: a lower bound x of med5(J) shared by the tile's ten windows (the least

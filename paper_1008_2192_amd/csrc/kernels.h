@@ -25,7 +25,7 @@ constexpr int kKindInit = 0, kKindDetect = 1, kKindGrow = 2, kKindReplace = 3;
 constexpr int kNumKernelKinds = 4;
 
 // DevFrame::flags bits.  kNoEarlyStop has the value of CRB_FLAG_NO_EARLY_STOP;
-// kFreshMask: the mask is uninitialised before iteration 1, which then writes all of it.
+// kFreshMask: the mask is uninitialised before iteration 1, whose detection clears it.
 // kCountWork: detection adds its work-set size, contrast-test count and number of
 // binary64 re-evaluations to f.work[0..2].
 // kExactDetect: detection evaluates S' of every work-set pixel in binary64 from J
@@ -75,8 +75,8 @@ struct TileRef {                  // one (frame, tile origin) work item
 };
 
 // Clears the counters; for frames with niter == 0 also copies img into J and clears
-// the mask (otherwise iteration 1 does both: detection copies img into J, the grow
-// writes the whole mask when kFreshMask is set).  max_pixels: the largest frame with
+// the mask (otherwise iteration 1 does both: detection copies img into J and, when
+// kFreshMask is set, clears the mask).  max_pixels: the largest frame with
 // niter == 0 (0 if none), which sizes the grid.
 hipError_t launch_init(const DevFrame *d_frames, int nframes, const DevFrame &single,
                        size_t max_pixels, hipStream_t s);

@@ -160,12 +160,14 @@ template <int TYG, bool ALIGNED>
 __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, int k, int lane) {
     constexpr int kAhead = 4;
     const int H = f.H, W = f.W;
-    const bool fresh = k == 1 && (f.flags & kFreshMask);   // mask not yet initialised
+    // iteration 1 on a mask that detection has just cleared: nothing to read
+    const bool fresh = k == 1 && (f.flags & kFreshMask);
     const int px = x0 - 16 + 16 * lane;                // first pixel of this lane's group
     const bool owner = lane >= 1 && lane <= kGrowTX / 16 && px < W;
     // from iteration 2 on the list already holds M_{k-1} and takes only the new flags
     const bool list_new = k >= 2;
-    if (list_new && !f.g2 && f.tile_first && !strip_near_first<TYG>(f, y0, x0, lane))
+    if ((list_new || fresh) && !f.g2 && f.tile_first &&
+        !strip_near_first<TYG>(f, y0, x0, lane))
         return;
 
     Px16 hA0 = {}, hA1 = {};          // dilated first selection, rows y-2, y-1
@@ -235,7 +237,7 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
                     nnew += (unsigned int)__popc(nw);
                     m16 |= squeeze4(list_new ? nw : m.d[q]) << (4 * q);
                 }
-                if (anynew || fresh)
+                if (anynew)
                     store16(f.mask, y - 2, px, W, ALIGNED, m);
                 if (f.g2)
                     store16(f.g2, y - 2, px, W, ALIGNED, g2);
