@@ -41,9 +41,9 @@ namespace crb {
 // S' > sigclip), then G2 at y-2 (gated by S' > sigfrac*sigclip).  No LDS and no
 // block barrier.  The flagged list is written row by row across the wave, so
 // consecutive entries are neighbours in a row.  Iteration 1 lists the whole mask; later
-// iterations append their new flags only, and a strip with no first selection within
-// reach returns at once (after the first iteration A is rare: the flagged pixels have
-// been replaced).
+// iterations append their new flags only.  A strip with no first selection within reach
+// returns at once (at iteration 1 only where detection has cleared the mask; after it A
+// is rare, since the flagged pixels have been replaced).
 
 constexpr uint32_t kByteLsb = 0x01010101u;
 
