@@ -325,10 +325,10 @@ def main():
             "reevaluated_per_launch": round(work["reevaluated"] / 4.0, 2),
             "pixels_per_launch": total_px, "avg_launch_ms": round(det_avg_s * 1e3, 4),
             "kernel_avg_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in ktimes.items()},
-            "kernel_note": "detection evaluates every pixel at every iteration; from iteration 2 "
-                           "on the grow visits the strips within 2 px of A and the replacement "
-                           "recomputes the flagged pixels within 2 px of a new flag (elsewhere "
-                           "their results equal what the frame holds)"}
+            "kernel_note": "detection evaluates every pixel at every iteration; the grow "
+                           "visits the strips within 2 px of A, and from iteration 2 on the "
+                           "replacement recomputes the flagged pixels within 2 px of a new flag "
+                           "(elsewhere their results equal what the frame holds)"}
     # issued VALU lane-operations (wave-instructions x 64, from the committed counters of
     # the same kernel sources) against the same peak: how busy the ALUs are, as opposed
     # to how much of the issue is algorithmic work
