@@ -97,6 +97,26 @@ crb_status crb_lacosmic(const float *img, int32_t H, int32_t W, float gain, floa
                         float sky, float sigclip, float sigfrac, float objlim, int32_t niter,
                         float *out_clean, uint8_t *out_mask);
 
+/*
+ * crb_lacosmic for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * results (bit-identical to crb_lacosmic) and stream (crb_set_stream) as crb_lacosmic;
+ * it calls no hipMalloc, hipFree or other allocating routine.  Its workspace is a fixed
+ * device array of CRB_NOALLOC_MAX_WORKSPACE bytes inside the library, one per GPU,
+ * held from the first call on that GPU until the process ends.  A frame whose
+ * workspace (crb_workspace_bytes) exceeds it is rejected with CRB_ETOOBIG before
+ * anything is enqueued; 4096 x 4096 fits.  Every call on one GPU uses that GPU's
+ * array: calls that overlap on one GPU (two streams, or two threads with their own
+ * streams) race on it and give undefined results, so order them (one stream, or an
+ * event between them).  Each call resets the counters it reads, so a call never sees
+ * the previous call's state.
+ */
+#define CRB_NOALLOC_MAX_WORKSPACE ((size_t)96 << 20)
+crb_status crb_lacosmic_noalloc(const float *img, int32_t H, int32_t W, float gain,
+                                float readnoise, float sky, float sigclip, float sigfrac,
+                                float objlim, int32_t niter, float *out_clean,
+                                uint8_t *out_mask);
+
 /* One frame of a batch (host struct; pointers are device pointers). */
 typedef struct {
     const float *img;     /* input  (device, H*W FP32)                           */

@@ -22,7 +22,7 @@ CRB_OPT_INCREMENTAL = 2
 STATUS = {0: "CRB_OK", -1: "CRB_EINVAL", -2: "CRB_ENOMEM", -3: "CRB_EDEVICE",
           -4: "CRB_ETOOBIG", -5: "CRB_EBUSY"}
 
-EXPORTS = ["crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned", "crb_plan_create", "crb_plan_run",
+EXPORTS = ["crb_lacosmic", "crb_lacosmic_noalloc", "crb_lacosmic_batched", "crb_lacosmic_partitioned", "crb_plan_create", "crb_plan_run",
            "crb_plan_stats", "crb_plan_destroy", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option",
            "crb_last_error", "crb_workspace_bytes", "crb_release_workspace",
            "crb_server_create", "crb_server_submit", "crb_server_poll", "crb_server_pending",
@@ -79,6 +79,7 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
     L.crb_lacosmic.argtypes = [vp, i32, i32, f32, f32, f32, f32, f32, f32, i32, vp, vp]
+    L.crb_lacosmic_noalloc.argtypes = L.crb_lacosmic.argtypes
     L.crb_lacosmic_batched.argtypes = [ctypes.POINTER(Frame), i32, vp]
     L.crb_lacosmic_partitioned.argtypes = [vp, i32, i32, f32, f32, f32, f32, f32, f32, i32,
                                            i32, i32, i32, vp, vp]
@@ -118,7 +119,7 @@ def lib():
     L.crb_work_radius.argtypes = [ctypes.POINTER(Work)]
     L.crb_work_radius.restype = i32
     L.crb_farm_run.argtypes = [ctypes.POINTER(Work), vp, i32, i32, i32, i32, i32, vp, vp, i64, vp]
-    for name in ("crb_lacosmic", "crb_lacosmic_batched", "crb_lacosmic_partitioned",
+    for name in ("crb_lacosmic", "crb_lacosmic_noalloc", "crb_lacosmic_batched", "crb_lacosmic_partitioned",
                  "crb_plan_create", "crb_plan_run",
                  "crb_plan_stats", "crb_plan_set_timing", "crb_plan_kernel_times", "crb_set_stream", "crb_set_option", "crb_release_workspace",
                  "crb_server_create", "crb_server_submit", "crb_server_poll",
@@ -175,6 +176,31 @@ def lacosmic(img: torch.Tensor, gain: float, readnoise: float, sky: float = 0.0,
     check("crb_lacosmic", L.crb_lacosmic(img.data_ptr(), H, W, gain, readnoise, sky, sigclip,
                                          sigfrac, objlim, niter, out_clean.data_ptr(),
                                          out_mask.data_ptr()))
+    return out_clean, out_mask
+
+
+def lacosmic_noalloc(img: torch.Tensor, gain: float, readnoise: float, sky: float = 0.0,
+                     sigclip: float = 4.5, sigfrac: float = 0.3, objlim: float = 4.0,
+                     niter: int = 4, out_clean: Optional[torch.Tensor] = None,
+                     out_mask: Optional[torch.Tensor] = None, early_stop: bool = True,
+                     stream: Optional[torch.cuda.Stream] = None):
+    """crb_lacosmic_noalloc: crb_lacosmic with the library's fixed device scratch as its
+    workspace (no device allocation by the library); returns (clean, mask)."""
+    _dev2d(img, torch.float32, "img")
+    H, W = img.shape
+    if out_clean is None:
+        out_clean = torch.empty_like(img)
+    if out_mask is None:
+        out_mask = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+    _dev2d(out_clean, torch.float32, "out_clean")
+    _dev2d(out_mask, torch.uint8, "out_mask")
+    L = lib()
+    set_stream(stream)
+    check("crb_set_option", L.crb_set_option(CRB_OPT_EARLY_STOP, 1 if early_stop else 0))
+    check("crb_set_option", L.crb_set_option(CRB_OPT_INCREMENTAL, 0))
+    check("crb_lacosmic_noalloc", L.crb_lacosmic_noalloc(
+        img.data_ptr(), H, W, gain, readnoise, sky, sigclip, sigfrac, objlim, niter,
+        out_clean.data_ptr(), out_mask.data_ptr()))
     return out_clean, out_mask
 
 

@@ -223,6 +223,46 @@ static crb_status enqueue_single(const DevFrame &f, hipStream_t s) {
     return hip_status(e, "kernel launch");
 }
 
+// ---------------------------------------------------------------------------
+// fixed device scratch of the allocation-free entry point
+// ---------------------------------------------------------------------------
+
+// Workspace of crb_lacosmic_noalloc: one array per device, loaded with the code object
+// and held until the process ends.  Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in for the symbol): it takes the
+// device address from hipGetSymbolAddress, once per device, and uses that.
+constexpr size_t kScratchBytes = CRB_NOALLOC_MAX_WORKSPACE;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_dev[kMaxScratchDevices];    // device address per device, or null
+
+// Device address of the current device's scratch array (looked up on the first call on
+// that device, with the device current).
+static crb_status scratch_ptr(char **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_status(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(CRB_EDEVICE, "device %d beyond the %d the scratch table holds", dev,
+                    kMaxScratchDevices);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(CRB_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        }
+        g_scratch_dev[dev] = static_cast<char *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return CRB_OK;
+}
+
 }  // namespace crb
 
 using namespace crb;
@@ -279,6 +319,34 @@ crb_status crb_release_workspace(void *hip_stream) {
         w->buf = nullptr;
         w->cap = 0;
     }
+    return ok();
+}
+
+crb_status crb_lacosmic_noalloc(const float *img, int32_t H, int32_t W, float gain,
+                                float readnoise, float sky, float sigclip, float sigfrac,
+                                float objlim, int32_t niter, float *out_clean,
+                                uint8_t *out_mask) {
+    crb_status st = check_frame_args(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim, niter);
+    if (st != CRB_OK)
+        return st;
+    const size_t npix = (size_t)H * (size_t)W;
+    if ((st = check_buffers(img, out_clean, out_mask, npix)) != CRB_OK)
+        return st;
+    const FrameWs L = ws_layout(H, W);
+    if (L.total > kScratchBytes)
+        return fail(CRB_ETOOBIG,
+                    "crb_lacosmic_noalloc: a %d x %d frame needs %zu bytes of workspace, above "
+                    "the fixed scratch of %zu bytes (CRB_NOALLOC_MAX_WORKSPACE)",
+                    H, W, L.total, kScratchBytes);
+    char *base = nullptr;
+    if ((st = scratch_ptr(&base)) != CRB_OK)
+        return st;
+    const int flags = (g_early_stop.load() ? 0 : kNoEarlyStop) |
+                      (g_incremental.load() ? kIncremental : 0) | kFreshMask;
+    DevFrame f = make_devframe(img, out_clean, out_mask, base, L, H, W, gain, readnoise, sky,
+                               sigclip, sigfrac, objlim, niter, flags);
+    if ((st = enqueue_single(f, t_stream)) != CRB_OK)
+        return st;
     return ok();
 }
 

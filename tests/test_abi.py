@@ -173,3 +173,13 @@ def test_counting_and_debug_entry_validation(L):
     assert L.crb_debug_s_estimate(a, ctypes.byref(fr), b, ctypes.c_void_p(1 << 42)) == -1
     assert L.crb_set_option(_lib.CRB_OPT_INCREMENTAL, 2) == -1
     assert L.crb_set_option(_lib.CRB_OPT_INCREMENTAL, 0) == 0
+
+
+def test_noalloc_rejects_oversized_frames_on_host(L):
+    """A frame whose workspace exceeds the fixed scratch is refused before any device
+    work (the pointers are never dereferenced)."""
+    p, q, m = ctypes.c_void_p(16), ctypes.c_void_p(1 << 40), ctypes.c_void_p(1 << 41)
+    assert L.crb_workspace_bytes(6000, 6000) > (96 << 20)
+    assert L.crb_lacosmic_noalloc(p, 6000, 6000, 1.0, 5.0, 0.0, 4.5, 0.3, 4.0, 4, q, m) == -4
+    assert b"scratch" in L.crb_last_error()
+    assert L.crb_workspace_bytes(4096, 4096) <= (96 << 20)
