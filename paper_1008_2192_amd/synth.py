@@ -242,20 +242,21 @@ def c1_density_frame(H: int, W: int, seed: int, gain: float, readnoise: float,
                   name=name or f"{H}x{W}")
 
 
+def c4_frame(i: int, sizes=C4_SIZES, per_size: int = 16, base_seed: int = 4000) -> Frame:
+    """Frame i of the mixed-size batch: size sizes[i // per_size], seed base_seed + i,
+    gain U(1,8) and read noise U(3,8) e- from a generator keyed by the seed."""
+    H, W = sizes[i // per_size]
+    seed = base_seed + i
+    prng = np.random.Generator(np.random.PCG64(seed + 10_000_000))
+    g = float(np.float32(prng.uniform(1.0, 8.0)))
+    rn = float(np.float32(prng.uniform(3.0, 8.0)))
+    return c1_density_frame(H, W, seed, g, rn, name=f"c4[{i}]-{H}x{W}")
+
+
 def c4(sizes=C4_SIZES, per_size: int = 16, base_seed: int = 4000) -> List[Frame]:
     """64 frames: 16 each of 800x800, 1024x1024, 2048x4096, 4096x2048 (H x W); per-frame
     gain U(1,8) and read noise U(3,8) e-, frame i seeded with 4000+i."""
-    frames = []
-    i = 0
-    for (H, W) in sizes:
-        for _ in range(per_size):
-            seed = base_seed + i
-            prng = np.random.Generator(np.random.PCG64(seed + 10_000_000))
-            g = float(np.float32(prng.uniform(1.0, 8.0)))
-            rn = float(np.float32(prng.uniform(3.0, 8.0)))
-            frames.append(c1_density_frame(H, W, seed, g, rn, name=f"c4[{i}]-{H}x{W}"))
-            i += 1
-    return frames
+    return [c4_frame(i, sizes, per_size, base_seed) for i in range(len(sizes) * per_size)]
 
 
 @dataclasses.dataclass
