@@ -24,11 +24,15 @@
  * typically 4) and, unless disabled, stops after the first iteration with n_k = 0,
  * which is result-neutral because that iteration reproduces its input.
  *
- * Numerics: pixels are FP32.  Medians are exact selections.  L+, N, S, S', F^ and
- * every threshold test are evaluated in IEEE binary64 (the paper's subimage data
- * are doubles, Section 6.2), so the detection decisions for a given J_k do not
- * depend on rounding order.  A replaced pixel with an even number of unflagged
- * neighbours receives the binary64 mean of the two middle values rounded to FP32.
+ * Numerics: pixels are FP32.  Medians are exact selections.  Every detection
+ * decision (the three threshold tests and the contrast test) is the one that L+, N,
+ * S, S' and F^ evaluated in IEEE binary64 in the definition's operation order would
+ * take (the paper's subimage data are doubles, Section 6.2): the kernels decide from
+ * an FP32 estimate of S where a proven error bound shows that binary64 decides the
+ * same way, and evaluate the statistics in binary64 where it does not.  So the
+ * decisions for a given J_k do not depend on tiling, launch shape or rounding order.
+ * A replaced pixel with an even number of unflagged neighbours receives the binary64
+ * mean of the two middle values rounded to FP32.
  *
  * Conventions for every entry point:
  *   - image pointers are DEVICE pointers on the current HIP device, row-major,
@@ -78,6 +82,12 @@ typedef enum {
 #define CRB_OPT_EARLY_STOP 1       /* value 1 (default) or 0: early stop in crb_lacosmic */
 #define CRB_OPT_INCREMENTAL 2      /* value 0 (default) or 1: CRB_FLAG_INCREMENTAL for
                                       crb_lacosmic and crb_lacosmic_partitioned */
+/* Launch shapes of crb_lacosmic, crb_lacosmic_noalloc and crb_debug_* (see crb_tuning;
+ * every shape gives identical results): */
+#define CRB_OPT_TILE_H 3           /* detection tile rows: 16, 32 (default) or 64        */
+#define CRB_OPT_FUSED 4            /* 0 (default) or 1: grow and replacement fused        */
+#define CRB_OPT_GROW_H 5           /* first-iteration grow strip rows: 0 (default), 8, 16
+                                      or 32                                              */
 
 /*
  * Clean one frame (the method above).
@@ -133,10 +143,14 @@ typedef struct {
 
 /*
  * Clean n independent frames of any sizes in one batched pass (one launch per
- * stage and iteration over a (frame, tile) work list).  Each frame's outputs are
- * bit-identical to a crb_lacosmic call with the same parameters.  Synchronous:
- * returns after the batch has completed on hip_stream (NULL: default stream) and
- * has written iters_run and n_flagged into frames[].
+ * stage and iteration over a (frame, tile) work list): the paper's subimages handed
+ * to actors (Section 6.2), here whole frames of uneven size sharing each launch.
+ * Each frame's outputs are bit-identical to a crb_lacosmic call with the same
+ * parameters (Section 5 for the method).  Synchronous, unlike the other cleaning
+ * calls: it writes the host fields iters_run and n_flagged of frames[] at completion
+ * and frees its per-call workspace before returning, so it waits for the batch on
+ * hip_stream (NULL: default stream).  The stream-ordered, asynchronous form is the
+ * batch plan below (crb_plan_run, then crb_plan_stats for the per-frame results).
  */
 crb_status crb_lacosmic_batched(crb_frame *frames, int32_t n, void *hip_stream);
 
@@ -180,6 +194,56 @@ crb_status crb_plan_kernel_times(crb_plan *plan, double *ms, int64_t *launches);
  * region. */
 crb_status crb_plan_set_counting(crb_plan *plan, int32_t enable);
 crb_status crb_plan_work_counts(crb_plan *plan, int64_t *counts);
+
+/*
+ * Launch shapes of a plan (the autotuner's search space).  The paper finds the cost of a
+ * subimage set by its overlap with its neighbours and by the imbalance between subimages
+ * (Section 6.3.1: a 6 x 6 split beats 1 x 36, and the slowest subimage sets the pace);
+ * here the same trade-offs are the halo share of a tile or strip and how tiles are
+ * handed to the compute units.  Every shape computes identical results.
+ *   tile_h      detection tile rows, 16, 32 or 64 (64 columns; the halo is 4 rows and
+ *               columns of J, 2 of S): taller tiles re-read less halo per pixel, shorter
+ *               ones fit more blocks per compute unit;
+ *   persistent  0: one block per (frame, tile); 1: about as many blocks as are resident
+ *               at once, each taking tiles from 8 atomic ticket counters (one per XCD,
+ *               each over a contiguous part of the tile list, a block helping the others
+ *               once its part is used up), as CRBLASTER's actors take subimages;
+ *   fused       0: grow/count, list prefix and replacement as three launches per
+ *               iteration; 1: one launch, each 8-row strip recomputing its 2-row mask
+ *               halo (rows its neighbours own) and replacing its own flagged pixels;
+ *   grow_h      rows of a first-iteration grow strip when fused is 0 (8, 16 or 32; 0 =
+ *               32 for batches), with a 2-row code halo above and below.
+ * The default is {32, 0, 0, 0}.
+ */
+typedef struct {
+    int32_t tile_h;
+    int32_t persistent;
+    int32_t fused;
+    int32_t grow_h;
+} crb_tuning;
+
+/* Set or read a plan's launch shapes; set waits for the plan's stream and re-captures
+ * a graph plan.  A plan starts with the tune cache's entry for its batch layout (below)
+ * or with the default. */
+crb_status crb_plan_set_tuning(crb_plan *plan, const crb_tuning *tuning);
+crb_status crb_plan_get_tuning(crb_plan *plan, crb_tuning *tuning);
+
+/*
+ * Autotune a plan: time whole runs (median of reps runs each, HIP events on the plan's
+ * stream, after one untimed run) first over the six detection shapes (tile_h x
+ * persistent), then over the four grow shapes (three launches with grow_h 8, 16 or 32,
+ * or fused) under the best detection shape, keep the fastest and apply it to the plan.
+ * The runs write the frames' outputs, so no frame may be cleaned in place (out_clean
+ * == img gives CRB_EINVAL).  With use_cache != 0 and an entry for the plan's batch
+ * layout in the tune cache, that entry is applied without timing (then *ms and
+ * *default_ms are -1).  The cache is the text file named by the environment variable
+ * CRB_TUNE_CACHE (none if unset): each tuning appends a line keyed by the device
+ * (architecture, compute units) and the frames' sizes, iteration counts and flags, and
+ * crb_plan_create applies the last matching line.  Outputs (each nullable): best, the
+ * median ms of a run with it and with the default shapes.  Synchronous.
+ */
+crb_status crb_plan_autotune(crb_plan *plan, int32_t reps, int32_t use_cache, crb_tuning *best,
+                             double *ms, double *default_ms);
 
 /*
  * The paper's partitioned run (Section 6.2): the frame is split into ny x nx
@@ -268,7 +332,7 @@ int32_t crb_work_radius(const crb_work *w);
  *     8-byte aligned; null only when list_capacity is 0) in no particular order --
  *     sort by (y, x) for raster order; a count above list_capacity means the list
  *     was truncated and a rerun with a larger list returns all.  out_image must be null.
- * Tiles are handed out through 8 ticket counters, each over a contiguous range of
+ * Tiles are handed out through 32 ticket counters, each over a contiguous range of
  * tiles, in runs of several tiles; an actor drains its own range first and then
  * helps with the others.  Asynchronous on the calling thread's stream; uses 32 bytes
  * of that stream's workspace, so calls on one stream are ordered and calls on
@@ -327,14 +391,17 @@ void crb_server_destroy(crb_server *srv);
 /* ---- entry points for parity tests ------------------------------------------ */
 
 /*
- * Run exactly one iteration on a given (J_k, M_{k-1}) (device pointers): writes
- * G2 (uint8, selected this iteration), M_k, J_{k+1} and n_k (device int64).
- * params supplies H, W, gain, readnoise, sky, sigclip, sigfrac, objlim (its
- * pointers are ignored).  Runs on the calling thread's stream.
+ * Run exactly one iteration of the method (Section 5) on a given (J_k, M_{k-1}), for
+ * teacher-forced parity tests: J (FP32) and M_prev (uint8 0/1) are H x W device
+ * arrays; writes G2 (uint8, the pixels selected this iteration), M_k = M_{k-1} | G2,
+ * J_{k+1} (FP32) and n_k = #(G2 & !M_{k-1}) (one device int64).  params supplies gain,
+ * readnoise, sky, sigclip, sigfrac and objlim; its pointers, sizes, niter and flags are
+ * ignored.  out_J_next must not alias J.  Stream-ordered and asynchronous on the
+ * calling thread's stream (crb_set_stream); uses that stream's workspace.
  */
-crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_frame *params,
-                             uint8_t *out_G2, uint8_t *out_M, float *out_J_next,
-                             int64_t *out_n_new);
+crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, int32_t H, int32_t W,
+                             const crb_frame *params, uint8_t *out_G2, uint8_t *out_M,
+                             float *out_J_next, int64_t *out_n_new);
 /* Detection stage only: code = A | [S' > sigclip] << 1 | [S' > sigfrac sigclip] << 2
  * on the pixels within distance 2 (8-connected) of a pixel with S > sigclip; elsewhere
  * either 0 or that same code (the detection's work set may hold a few more pixels,

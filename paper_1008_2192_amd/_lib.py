@@ -19,6 +19,9 @@ CRB_FLAG_NO_EARLY_STOP = 1
 CRB_FLAG_INCREMENTAL = 2
 CRB_OPT_EARLY_STOP = 1
 CRB_OPT_INCREMENTAL = 2
+CRB_OPT_TILE_H = 3
+CRB_OPT_FUSED = 4
+CRB_OPT_GROW_H = 5
 STATUS = {0: "CRB_OK", -1: "CRB_EINVAL", -2: "CRB_ENOMEM", -3: "CRB_EDEVICE",
           -4: "CRB_ETOOBIG", -5: "CRB_EBUSY"}
 
@@ -29,7 +32,8 @@ EXPORTS = ["crb_lacosmic", "crb_lacosmic_noalloc", "crb_lacosmic_batched", "crb_
            "crb_server_destroy", "crb_debug_iterate", "crb_debug_detect", "crb_debug_median",
            "crb_debug_fp64", "crb_work_run", "crb_work_radius", "crb_farm_run",
            "crb_plan_set_counting", "crb_plan_work_counts", "crb_debug_median5_f64",
-           "crb_debug_detect_exact", "crb_debug_s_estimate"]
+           "crb_debug_detect_exact", "crb_debug_s_estimate", "crb_plan_set_tuning",
+           "crb_plan_get_tuning", "crb_plan_autotune"]
 CRB_WORK_LACOSMIC = 0
 CRB_WORK_POISSON = 1
 CRB_WORK_WAITER = 2
@@ -52,6 +56,19 @@ class Work(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("niter", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("threshold", ctypes.c_float), ("sky", ctypes.c_float),
                 ("peak_radius", ctypes.c_int32), ("aperture_radius", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    """Mirror of ``crb_tuning`` (a plan's launch shapes)."""
+    _fields_ = [("tile_h", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("fused", ctypes.c_int32), ("grow_h", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return dict(tile_h=self.tile_h, persistent=self.persistent, fused=self.fused,
+                    grow_h=self.grow_h)
+
+
+DEFAULT_TUNING = dict(tile_h=32, persistent=0, fused=0, grow_h=0)
 
 
 class Frame(ctypes.Structure):
@@ -94,6 +111,11 @@ def lib():
     L.crb_plan_set_counting.argtypes = [vp, i32]
     L.crb_plan_work_counts.argtypes = [vp, ctypes.POINTER(i64)]
     L.crb_debug_median5_f64.argtypes = [vp, i32, i32, vp]
+    L.crb_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.crb_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.crb_plan_autotune.argtypes = [vp, i32, i32, ctypes.POINTER(Tuning),
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]
     L.crb_set_stream.argtypes = [vp]
     L.crb_set_option.argtypes = [i32, i64]
     L.crb_last_error.argtypes = []
@@ -109,7 +131,7 @@ def lib():
     L.crb_server_pending.restype = i32
     L.crb_server_destroy.argtypes = [vp]
     L.crb_server_destroy.restype = None
-    L.crb_debug_iterate.argtypes = [vp, vp, ctypes.POINTER(Frame), vp, vp, vp, vp]
+    L.crb_debug_iterate.argtypes = [vp, vp, i32, i32, ctypes.POINTER(Frame), vp, vp, vp, vp]
     L.crb_debug_detect.argtypes = [vp, ctypes.POINTER(Frame), vp]
     L.crb_debug_detect_exact.argtypes = [vp, ctypes.POINTER(Frame), vp]
     L.crb_debug_s_estimate.argtypes = [vp, ctypes.POINTER(Frame), vp, vp]
@@ -125,7 +147,8 @@ def lib():
                  "crb_server_create", "crb_server_submit", "crb_server_poll",
                  "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64",
                  "crb_work_run", "crb_farm_run", "crb_plan_set_counting", "crb_plan_work_counts",
-                 "crb_debug_median5_f64", "crb_debug_detect_exact", "crb_debug_s_estimate"):
+                 "crb_debug_median5_f64", "crb_debug_detect_exact", "crb_debug_s_estimate",
+                 "crb_plan_set_tuning", "crb_plan_get_tuning", "crb_plan_autotune"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -152,6 +175,15 @@ def _dev2d(t: torch.Tensor, dtype: torch.dtype, name: str) -> torch.Tensor:
 
 def set_stream(stream: Optional[torch.cuda.Stream] = None) -> None:
     check("crb_set_stream", lib().crb_set_stream(ctypes.c_void_p(_stream(stream))))
+
+
+def set_single_tuning(tile_h: int = 32, fused: int = 0, grow_h: int = 0) -> None:
+    """Launch shapes of the single-frame entry points (CRB_OPT_TILE_H, CRB_OPT_FUSED,
+    CRB_OPT_GROW_H); every shape gives identical results."""
+    L = lib()
+    check("crb_set_option", L.crb_set_option(CRB_OPT_TILE_H, tile_h))
+    check("crb_set_option", L.crb_set_option(CRB_OPT_FUSED, fused))
+    check("crb_set_option", L.crb_set_option(CRB_OPT_GROW_H, grow_h))
 
 
 def lacosmic(img: torch.Tensor, gain: float, readnoise: float, sky: float = 0.0,
@@ -271,6 +303,27 @@ class Plan:
         check("crb_plan_stats", lib().crb_plan_stats(self.handle, self.frames, len(self.items)))
         return [dict(iters_run=f.iters_run, n_flagged=f.n_flagged) for f in self.frames]
 
+    def set_tuning(self, tile_h: int = 32, persistent: int = 0, fused: int = 0,
+                   grow_h: int = 0) -> None:
+        """crb_plan_set_tuning: the launch shapes of later runs (identical results)."""
+        t = Tuning(tile_h, persistent, fused, grow_h)
+        check("crb_plan_set_tuning", lib().crb_plan_set_tuning(self.handle, ctypes.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        check("crb_plan_get_tuning", lib().crb_plan_get_tuning(self.handle, ctypes.byref(t)))
+        return t.as_dict()
+
+    def autotune(self, reps: int = 3, use_cache: bool = True) -> dict:
+        """crb_plan_autotune: time the launch shapes, apply the fastest; returns
+        dict(tuning, ms, default_ms) (ms are -1 when the tune cache supplied it)."""
+        t = Tuning()
+        ms, dms = ctypes.c_double(), ctypes.c_double()
+        check("crb_plan_autotune", lib().crb_plan_autotune(
+            self.handle, reps, 1 if use_cache else 0, ctypes.byref(t), ctypes.byref(ms),
+            ctypes.byref(dms)))
+        return dict(tuning=t.as_dict(), ms=ms.value, default_ms=dms.value)
+
     def set_timing(self, enable: bool) -> None:
         check("crb_plan_set_timing", lib().crb_plan_set_timing(self.handle, 1 if enable else 0))
 
@@ -328,7 +381,7 @@ def debug_iterate(J: torch.Tensor, M_prev: torch.Tensor, gain, readnoise, sky=0.
     n = torch.zeros(1, dtype=torch.int64, device=J.device)
     p = _params_frame(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim)
     set_stream(stream)
-    check("crb_debug_iterate", lib().crb_debug_iterate(J.data_ptr(), M_prev.data_ptr(),
+    check("crb_debug_iterate", lib().crb_debug_iterate(J.data_ptr(), M_prev.data_ptr(), H, W,
                                                        ctypes.byref(p), G2.data_ptr(),
                                                        M.data_ptr(), Jn.data_ptr(),
                                                        n.data_ptr()))

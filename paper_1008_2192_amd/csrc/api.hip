@@ -4,9 +4,11 @@
 #include "api_internal.h"
 
 #include <stdarg.h>
+#include <stdlib.h>
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <map>
 #include <mutex>
@@ -93,8 +95,8 @@ FrameWs ws_layout(int32_t H, int32_t W) {
     L.nnew = align_up(L.list + 4 * n, 256);
     L.listlen = align_up(L.nnew + 8 * (size_t)kMaxIter, 256);
     L.dirty = align_up(L.listlen + 4 * (size_t)kMaxIter, 256);
-    const size_t ntiles = (size_t)((H + kDetectTY - 1) / kDetectTY) *
-                          (size_t)((W + kDetectTX - 1) / kDetectTX);
+    const size_t ntiles = (size_t)((H + kSumTY - 1) / kSumTY) *
+                          (size_t)((W + kSumTX - 1) / kSumTX);
     L.tile_first = align_up(L.dirty + ntiles, 256);
     L.tile_new = align_up(L.tile_first + 4 * ntiles, 256);
     L.total = align_up(L.tile_new + 4 * ntiles, 256);
@@ -208,16 +210,31 @@ static crb_status ws_reserve(Workspace *ws, size_t bytes) {
     return CRB_OK;
 }
 
+// launch shapes of the single-frame entry points (CRB_OPT_TILE_H, CRB_OPT_FUSED,
+// CRB_OPT_GROW_H; every shape gives identical results)
+static std::atomic<int> g_single_tile_h{kDetectTYDefault};
+static std::atomic<int> g_single_fused{0};
+static std::atomic<int> g_single_grow_h{0};
+
+static LaunchCfg single_cfg() {
+    LaunchCfg c;
+    c.tile_h = g_single_tile_h.load();
+    c.fused = g_single_fused.load();
+    c.grow_h = g_single_grow_h.load();
+    return c;
+}
+
 // enqueue niter iterations for one frame whose DevFrame is complete
-static crb_status enqueue_single(const DevFrame &f, hipStream_t s) {
+static crb_status enqueue_single(const DevFrame &f, const LaunchCfg &cfg, hipStream_t s) {
     const size_t npix = (size_t)f.H * (size_t)f.W;
+    const bool fused = cfg.fused && !f.g2;
     // the init kernel touches pixels only for niter == 0 (a copy); else just counters
-    hipError_t e = launch_init(nullptr, 1, f, f.niter == 0 ? npix : 0, s);
+    hipError_t e = launch_init(nullptr, 1, f, f.niter == 0 ? npix : 0, nullptr, 0, s);
     for (int k = 1; e == hipSuccess && k <= f.niter; ++k) {
-        e = launch_detect(nullptr, nullptr, 0, f, k, s);
+        e = launch_detect(nullptr, nullptr, 0, f, k, cfg, nullptr, s);
         if (e == hipSuccess)
-            e = launch_grow(nullptr, nullptr, 0, f, k, s);
-        if (e == hipSuccess)
+            e = launch_grow(nullptr, nullptr, 0, f, k, cfg, s);
+        if (e == hipSuccess && !fused)
             e = launch_replace(nullptr, 1, nullptr, f, k, replace_grid(npix), s);
     }
     return hip_status(e, "kernel launch");
@@ -287,6 +304,24 @@ crb_status crb_set_option(int32_t key, int64_t value) {
         g_incremental.store((int)value);
         return ok();
     }
+    if (key == CRB_OPT_TILE_H) {
+        if (value != 16 && value != 32 && value != 64)
+            return fail(CRB_EINVAL, "CRB_OPT_TILE_H takes 16, 32 or 64");
+        g_single_tile_h.store((int)value);
+        return ok();
+    }
+    if (key == CRB_OPT_FUSED) {
+        if (value != 0 && value != 1)
+            return fail(CRB_EINVAL, "CRB_OPT_FUSED takes 0 or 1");
+        g_single_fused.store((int)value);
+        return ok();
+    }
+    if (key == CRB_OPT_GROW_H) {
+        if (value != 0 && value != 8 && value != 16 && value != 32)
+            return fail(CRB_EINVAL, "CRB_OPT_GROW_H takes 0, 8, 16 or 32");
+        g_single_grow_h.store((int)value);
+        return ok();
+    }
     return fail(CRB_EINVAL, "unknown option %d", key);
 }
 
@@ -345,7 +380,7 @@ crb_status crb_lacosmic_noalloc(const float *img, int32_t H, int32_t W, float ga
                       (g_incremental.load() ? kIncremental : 0) | kFreshMask;
     DevFrame f = make_devframe(img, out_clean, out_mask, base, L, H, W, gain, readnoise, sky,
                                sigclip, sigfrac, objlim, niter, flags);
-    if ((st = enqueue_single(f, t_stream)) != CRB_OK)
+    if ((st = enqueue_single(f, single_cfg(), t_stream)) != CRB_OK)
         return st;
     return ok();
 }
@@ -371,7 +406,7 @@ crb_status crb_lacosmic(const float *img, int32_t H, int32_t W, float gain, floa
                       (g_incremental.load() ? kIncremental : 0) | kFreshMask;
     DevFrame f = make_devframe(img, out_clean, out_mask, ws->buf, L, H, W, gain, readnoise, sky,
                                sigclip, sigfrac, objlim, niter, flags);
-    if ((st = enqueue_single(f, s)) != CRB_OK)
+    if ((st = enqueue_single(f, single_cfg(), s)) != CRB_OK)
         return st;
     return ok();
 }
@@ -495,16 +530,16 @@ crb_status crb_work_run(int32_t kind, const float *in, int32_t H, int32_t W, uin
     return crb_farm_run(&w, in, H, W, workers, band_rows, W, out, nullptr, 0, nullptr);
 }
 
-crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_frame *p,
-                             uint8_t *out_G2, uint8_t *out_M, float *out_J_next,
-                             int64_t *out_n_new) {
+crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, int32_t H, int32_t W,
+                             const crb_frame *p, uint8_t *out_G2, uint8_t *out_M,
+                             float *out_J_next, int64_t *out_n_new) {
     if (!p)
         return fail(CRB_EINVAL, "null params");
-    crb_status st = check_frame_args(p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
+    crb_status st = check_frame_args(H, W, p->gain, p->readnoise, p->sky, p->sigclip,
                                      p->sigfrac, p->objlim, 1);
     if (st != CRB_OK)
         return st;
-    const size_t npix = (size_t)p->H * (size_t)p->W;
+    const size_t npix = (size_t)H * (size_t)W;
     if (!J || !M_prev || !out_G2 || !out_M || !out_J_next || !out_n_new)
         return fail(CRB_EINVAL, "null pointer");
     if (J == out_J_next)
@@ -514,17 +549,17 @@ crb_status crb_debug_iterate(const float *J, const uint8_t *M_prev, const crb_fr
     if ((st = ws_get(s, &ws)) != CRB_OK)
         return st;
     std::lock_guard<std::mutex> g(ws->mu);
-    const FrameWs L = ws_layout(p->H, p->W);
+    const FrameWs L = ws_layout(H, W);
     if ((st = ws_reserve(ws, L.total)) != CRB_OK)
         return st;
-    DevFrame f = make_devframe(J, out_J_next, out_M, ws->buf, L, p->H, p->W, p->gain,
+    DevFrame f = make_devframe(J, out_J_next, out_M, ws->buf, L, H, W, p->gain,
                                p->readnoise, p->sky, p->sigclip, p->sigfrac, p->objlim, 1,
                                kNoEarlyStop);
     f.g2 = out_G2;
     hipError_t e = hipMemcpyAsync(out_M, M_prev, npix, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess)
         return hip_status(e, "hipMemcpyAsync");
-    if ((st = enqueue_single(f, s)) != CRB_OK)
+    if ((st = enqueue_single(f, single_cfg(), s)) != CRB_OK)
         return st;
     e = hipMemcpyAsync(out_n_new, f.nnew, sizeof(int64_t), hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess)
@@ -544,8 +579,8 @@ static crb_status debug_detect(const float *J, const crb_frame *p, uint8_t *out_
                                p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
                                p->sigfrac, p->objlim, 1, kNoEarlyStop | flags);
     f.codes = out_codes;
-    return hip_status(launch_detect(nullptr, nullptr, 0, f, 1, t_stream), "kernel launch") ==
-                   CRB_OK
+    return hip_status(launch_detect(nullptr, nullptr, 0, f, 1, single_cfg(), nullptr, t_stream),
+                      "kernel launch") == CRB_OK
                ? ok()
                : CRB_EDEVICE;
 }
@@ -618,6 +653,12 @@ crb_status crb_debug_fp64(const double *x, const double *y, int32_t n, double *o
 // batch plans
 // ---------------------------------------------------------------------------
 
+namespace crb {
+// detection tile heights a plan lists its tiles for
+constexpr int kTileHeights[3] = {16, 32, 64};
+static int tile_h_index(int h) { return h == 16 ? 0 : (h == 32 ? 1 : (h == 64 ? 2 : -1)); }
+}  // namespace crb
+
 struct crb_plan {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -626,16 +667,20 @@ struct crb_plan {
     int kmax = 0;
     size_t max_pix = 0;
     size_t init_pix = 0;                // largest frame with niter == 0 (0 if none)
+    size_t all_pix = 0;
     char *dmem = nullptr;
     DevFrame *d_frames = nullptr;
-    TileRef *d_tdet = nullptr;
-    int ntdet = 0;
+    TileRef *d_tdet[3] = {nullptr, nullptr, nullptr};   // per detection tile height
+    int ntdet[3] = {0, 0, 0};
     TileRef *d_tgrow = nullptr;
     int ntgrow = 0;
     long long *d_stats = nullptr;
     unsigned int *d_prefix = nullptr;   // flat offsets of the frames' flagged lists
     unsigned long long *d_work = nullptr;   // per frame: kWorkCounters detection counters
+    unsigned int *d_tickets = nullptr;  // kDetectQueues per iteration (persistent detection)
     std::vector<DevFrame> hframes;      // host copy of the frame table
+    std::string key;                    // tune-cache key of the batch layout
+    crb::LaunchCfg cfg;                 // launch shapes of crb_plan_run
     bool counting = false;
     int rgrid = 1;
     bool use_graph = false;
@@ -682,21 +727,30 @@ static crb_status plan_enqueue(crb_plan *p) {
     hipStream_t s = p->stream;
     DevFrame none;
     memset(&none, 0, sizeof(none));
+    const LaunchCfg &cfg = p->cfg;
+    const int ti = tile_h_index(cfg.tile_h);
+    if (ti < 0)
+        return fail(CRB_EINVAL, "detection tile height %d", cfg.tile_h);
     hipError_t e = tmark_begin(p, kKindInit);
     if (e == hipSuccess)
-        e = launch_init(p->d_frames, p->n, none, p->init_pix, s);
+        e = launch_init(p->d_frames, p->n, none, p->init_pix, p->d_tickets,
+                        p->kmax * kDetectQueues, s);
     if (e == hipSuccess)
         e = tmark_end(p);
     for (int k = 1; e == hipSuccess && k <= p->kmax; ++k) {
         if ((e = tmark_begin(p, kKindDetect)) == hipSuccess &&
-            (e = launch_detect(p->d_frames, p->d_tdet, p->ntdet, none, k, s)) == hipSuccess &&
+            (e = launch_detect(p->d_frames, p->d_tdet[ti], p->ntdet[ti], none, k, cfg,
+                               p->d_tickets + (size_t)(k - 1) * kDetectQueues, s)) ==
+                hipSuccess &&
             (e = tmark_end(p)) == hipSuccess &&
             (e = tmark_begin(p, kKindGrow)) == hipSuccess &&
-            (e = launch_grow(p->d_frames, p->d_tgrow, p->ntgrow, none, k, s)) == hipSuccess &&
-            (e = tmark_end(p)) == hipSuccess &&
+            (e = launch_grow(p->d_frames, p->d_tgrow, p->ntgrow, none, k, cfg, s)) ==
+                hipSuccess &&
+            (e = tmark_end(p)) == hipSuccess && !cfg.fused &&
             (e = tmark_begin(p, kKindReplace)) == hipSuccess &&
             (e = launch_list_prefix(p->d_frames, p->n, k, p->d_prefix, s)) == hipSuccess &&
-            (e = launch_replace(p->d_frames, p->n, p->d_prefix, none, k, p->rgrid, s)) == hipSuccess)
+            (e = launch_replace(p->d_frames, p->n, p->d_prefix, none, k, p->rgrid, s)) ==
+                hipSuccess)
             e = tmark_end(p);
     }
     if (e == hipSuccess)
@@ -704,13 +758,45 @@ static crb_status plan_enqueue(crb_plan *p) {
     return hip_status(e, "kernel launch");
 }
 
-static void plan_free(crb_plan *p) {
-    if (!p)
-        return;
+static void plan_drop_graph(crb_plan *p) {
     if (p->exec)
         (void)hipGraphExecDestroy(p->exec);
     if (p->graph)
         (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+// capture the plan's launches (with its current launch shapes) as a graph
+static crb_status plan_capture(crb_plan *p) {
+    plan_drop_graph(p);
+    hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess)
+        return hip_status(e, "hipStreamBeginCapture");
+    const bool timing = p->timing;
+    p->timing = false;
+    crb_status st = plan_enqueue(p);
+    p->timing = timing;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->stream, &g);
+    if (st != CRB_OK || e != hipSuccess) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return st != CRB_OK ? st : hip_status(e, "hipStreamEndCapture");
+    }
+    p->graph = g;
+    e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        plan_drop_graph(p);
+        return hip_status(e, "hipGraphInstantiate");
+    }
+    return CRB_OK;
+}
+
+static void plan_free(crb_plan *p) {
+    if (!p)
+        return;
+    plan_drop_graph(p);
     if (p->dmem) {
         (void)hipStreamSynchronize(p->stream);
         (void)hipFree(p->dmem);
@@ -720,6 +806,153 @@ static void plan_free(crb_plan *p) {
     if (p->own_stream && p->stream)
         (void)hipStreamDestroy(p->stream);
     delete p;
+}
+
+// ---- the tune cache ---------------------------------------------------------------
+// A text file named by CRB_TUNE_CACHE, one line per batch layout:
+//   crb-tune 1 <key> tile_h=<h> persistent=<0|1> fused=<0|1> grow_h=<h> ms=<t> default_ms=<t>
+// The key names the device (architecture and compute units) and the frames' sizes,
+// iteration counts and flags; the last line for a key wins.
+
+static std::mutex g_tune_mu;
+
+static std::string layout_key(const std::vector<DevFrame> &frames, int device) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    for (char &c : arch)
+        if (c == ' ' || c == ':')
+            c = '_';
+    // FNV-1a over the frame shapes in order
+    unsigned long long h = 1469598103934665603ull;
+    long long px = 0;
+    for (const DevFrame &f : frames) {
+        const int v[4] = {f.H, f.W, f.niter, f.flags & (kNoEarlyStop | kIncremental)};
+        for (int x : v)
+            for (int b = 0; b < 4; ++b) {
+                h ^= (unsigned long long)((x >> (8 * b)) & 0xFF);
+                h *= 1099511628211ull;
+            }
+        px += (long long)f.H * f.W;
+    }
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s/cu%d/n%zu/px%lld/%016llx", arch.c_str(), cus, frames.size(), px,
+             h);
+    return buf;
+}
+
+static bool cfg_valid(const LaunchCfg &c) {
+    return tile_h_index(c.tile_h) >= 0 && (c.persistent == 0 || c.persistent == 1) &&
+           (c.fused == 0 || c.fused == 1) &&
+           (c.grow_h == 0 || c.grow_h == 8 || c.grow_h == 16 || c.grow_h == 32);
+}
+
+static bool tune_cache_lookup(const std::string &key, LaunchCfg *out) {
+    const char *path = getenv("CRB_TUNE_CACHE");
+    if (!path || !*path)
+        return false;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    FILE *fp = fopen(path, "r");
+    if (!fp)
+        return false;
+    char line[512], k[256];
+    bool found = false;
+    while (fgets(line, sizeof(line), fp)) {
+        LaunchCfg c;
+        int ver = 0;
+        if (sscanf(line, "crb-tune %d %255s tile_h=%d persistent=%d fused=%d grow_h=%d", &ver, k,
+                   &c.tile_h, &c.persistent, &c.fused, &c.grow_h) == 6 &&
+            ver == 1 && key == k && cfg_valid(c)) {
+            *out = c;
+            found = true;
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+static void tune_cache_store(const std::string &key, const LaunchCfg &c, double ms,
+                             double default_ms) {
+    const char *path = getenv("CRB_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    FILE *fp = fopen(path, "a");
+    if (!fp)
+        return;
+    fprintf(fp, "crb-tune 1 %s tile_h=%d persistent=%d fused=%d grow_h=%d ms=%.4f default_ms=%.4f\n",
+            key.c_str(), c.tile_h, c.persistent, c.fused, c.grow_h, ms, default_ms);
+    fclose(fp);
+}
+
+static LaunchCfg cfg_from(const crb_tuning &t) {
+    LaunchCfg c;
+    c.tile_h = t.tile_h;
+    c.persistent = t.persistent;
+    c.fused = t.fused;
+    c.grow_h = t.grow_h;
+    return c;
+}
+
+static crb_tuning tuning_from(const LaunchCfg &c) {
+    crb_tuning t;
+    t.tile_h = c.tile_h;
+    t.persistent = c.persistent;
+    t.fused = c.fused;
+    t.grow_h = c.grow_h;
+    return t;
+}
+
+// apply launch shapes to a plan (re-capturing its graph, if it has one)
+static crb_status plan_apply(crb_plan *p, const LaunchCfg &c) {
+    if (!cfg_valid(c))
+        return fail(CRB_EINVAL, "launch shapes tile_h=%d persistent=%d fused=%d grow_h=%d: need "
+                                "tile_h in {16, 32, 64}, persistent and fused in {0, 1}, grow_h "
+                                "in {0, 8, 16, 32}",
+                    c.tile_h, c.persistent, c.fused, c.grow_h);
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess)
+        return hip_status(e, "hipStreamSynchronize");
+    p->cfg = c;
+    return p->use_graph ? plan_capture(p) : CRB_OK;
+}
+
+// median wall time (ms) of `reps` runs of the plan's launches with shapes c, timed by HIP
+// events on the plan's stream after one untimed run
+static crb_status time_cfg(crb_plan *p, const LaunchCfg &c, int reps, hipEvent_t a,
+                           hipEvent_t b, double *ms) {
+    const LaunchCfg keep = p->cfg;
+    const bool timing = p->timing;
+    p->cfg = c;
+    p->timing = false;
+    std::vector<double> t;
+    crb_status st = plan_enqueue(p);
+    for (int r = 0; st == CRB_OK && r < reps; ++r) {
+        hipError_t e = hipEventRecord(a, p->stream);
+        if (e == hipSuccess)
+            st = plan_enqueue(p);
+        if (st == CRB_OK && e == hipSuccess)
+            e = hipEventRecord(b, p->stream);
+        if (st == CRB_OK && e == hipSuccess)
+            e = hipEventSynchronize(b);
+        float x = 0.0f;
+        if (st == CRB_OK && e == hipSuccess)
+            e = hipEventElapsedTime(&x, a, b);
+        if (st == CRB_OK && e != hipSuccess)
+            st = hip_status(e, "autotune timing");
+        t.push_back((double)x);
+    }
+    p->cfg = keep;
+    p->timing = timing;
+    if (st != CRB_OK)
+        return st;
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return CRB_OK;
 }
 
 }  // namespace crb
@@ -738,7 +971,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     std::vector<size_t> off(n);
     size_t total = 0, max_pix = 0, all_pix = 0, init_pix = 0;
     int kmax = 0;
-    size_t ntdet = 0, ntgrow = 0;
+    size_t ntdet[3] = {0, 0, 0}, ntgrow = 0;
     for (int i = 0; i < n; ++i) {
         const crb_frame &f = frames[i];
         st = check_frame_args(f.H, f.W, f.gain, f.readnoise, f.sky, f.sigclip, f.sigfrac,
@@ -756,10 +989,11 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
             init_pix = npix > init_pix ? npix : init_pix;
         all_pix += npix;
         kmax = f.niter > kmax ? f.niter : kmax;
-        ntdet += (size_t)((f.H + kDetectTY - 1) / kDetectTY) * ((f.W + kDetectTX - 1) / kDetectTX);
+        for (int t = 0; t < 3; ++t)
+            ntdet[t] += (size_t)detect_tiles(f.H, f.W, kTileHeights[t]);
         ntgrow += (size_t)((f.H + kGrowTY - 1) / kGrowTY) * ((f.W + kGrowTX - 1) / kGrowTX);
     }
-    if (ntdet > (size_t)INT32_MAX || ntgrow > (size_t)INT32_MAX)
+    if (ntdet[0] > (size_t)INT32_MAX || ntgrow > (size_t)INT32_MAX / (kGrowTY / kGrowTYSmall))
         return fail(CRB_ETOOBIG, "batch too large");
     // also guard against buffers shared between frames
     for (int i = 0; i < n; ++i)
@@ -771,14 +1005,18 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
                 ranges_overlap(frames[j].out_clean, nj * 4, frames[i].img, ni * 4))
                 return fail(CRB_EINVAL, "frames %d and %d share output memory", i, j);
         }
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     const size_t o_frames = total;
-    const size_t o_tdet = o_frames + ((n * sizeof(DevFrame) + 255) / 256) * 256;
-    const size_t o_tgrow = o_tdet + ((ntdet * sizeof(TileRef) + 255) / 256) * 256;
-    const size_t o_stats = o_tgrow + ((ntgrow * sizeof(TileRef) + 255) / 256) * 256;
-    const size_t o_prefix = o_stats + ((2 * n * sizeof(long long) + 255) / 256) * 256;
-    const size_t o_work = o_prefix + (((n + 1) * sizeof(unsigned int) + 255) / 256) * 256;
-    const size_t bytes =
-        o_work + ((kWorkCounters * n * sizeof(unsigned long long) + 255) / 256) * 256;
+    size_t o_tdet[3];
+    o_tdet[0] = o_frames + al(n * sizeof(DevFrame));
+    o_tdet[1] = o_tdet[0] + al(ntdet[0] * sizeof(TileRef));
+    o_tdet[2] = o_tdet[1] + al(ntdet[1] * sizeof(TileRef));
+    const size_t o_tgrow = o_tdet[2] + al(ntdet[2] * sizeof(TileRef));
+    const size_t o_stats = o_tgrow + al(ntgrow * sizeof(TileRef));
+    const size_t o_prefix = o_stats + al(2 * n * sizeof(long long));
+    const size_t o_work = o_prefix + al((n + 1) * sizeof(unsigned int));
+    const size_t o_tickets = o_work + al(kWorkCounters * n * sizeof(unsigned long long));
+    const size_t bytes = o_tickets + al((size_t)(kmax > 0 ? kmax : 1) * kDetectQueues * 4);
 
     crb_plan *p = new (std::nothrow) crb_plan();
     if (!p)
@@ -808,18 +1046,23 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     p->kmax = kmax;
     p->max_pix = max_pix;
     p->init_pix = init_pix;
+    p->all_pix = all_pix;
     p->d_frames = reinterpret_cast<DevFrame *>(p->dmem + o_frames);
-    p->d_tdet = reinterpret_cast<TileRef *>(p->dmem + o_tdet);
+    for (int t = 0; t < 3; ++t) {
+        p->d_tdet[t] = reinterpret_cast<TileRef *>(p->dmem + o_tdet[t]);
+        p->ntdet[t] = (int)ntdet[t];
+    }
     p->d_tgrow = reinterpret_cast<TileRef *>(p->dmem + o_tgrow);
     p->d_stats = reinterpret_cast<long long *>(p->dmem + o_stats);
     p->d_prefix = reinterpret_cast<unsigned int *>(p->dmem + o_prefix);
     p->d_work = reinterpret_cast<unsigned long long *>(p->dmem + o_work);
-    p->ntdet = (int)ntdet;
+    p->d_tickets = reinterpret_cast<unsigned int *>(p->dmem + o_tickets);
     p->ntgrow = (int)ntgrow;
 
     std::vector<DevFrame> hf(n);
-    std::vector<TileRef> td, tg;
-    td.reserve(ntdet);
+    std::vector<TileRef> td[3], tg;
+    for (int t = 0; t < 3; ++t)
+        td[t].reserve(ntdet[t]);
     tg.reserve(ntgrow);
     for (int i = 0; i < n; ++i) {
         const crb_frame &f = frames[i];
@@ -830,14 +1073,23 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
                                   (f.flags & CRB_FLAG_INCREMENTAL ? kIncremental : 0) |
                                   kFreshMask);
         hf[i].work = p->d_work + kWorkCounters * (size_t)i;
-        for (int y = 0; y < f.H; y += kDetectTY)
-            for (int x = 0; x < f.W; x += kDetectTX)
-                td.push_back(TileRef{i, y, x, 0});
+        for (int t = 0; t < 3; ++t)
+            for (int y = 0; y < f.H; y += kTileHeights[t])
+                for (int x = 0; x < f.W; x += kDetectTX)
+                    td[t].push_back(TileRef{i, y, x, 0});
         for (int y = 0; y < f.H; y += kGrowTY)
             for (int x = 0; x < f.W; x += kGrowTX)
                 tg.push_back(TileRef{i, y, x, 0});
     }
     p->rgrid = replace_grid(all_pix);
+    // launch shapes: the tune cache's entry for this layout, if any, else the defaults
+    const char *cache = getenv("CRB_TUNE_CACHE");
+    if (cache && *cache) {
+        p->key = layout_key(hf, p->device);
+        LaunchCfg cached;
+        if (tune_cache_lookup(p->key, &cached))
+            p->cfg = cached;
+    }
     // Tables and counters are written on the plan's stream and waited for: a
     // null-stream copy or memset is not ordered before work on a non-blocking stream,
     // and a pageable copy may return before its data has landed.
@@ -846,8 +1098,8 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     if (e == hipSuccess)
         e = hipMemsetAsync(p->d_work, 0, kWorkCounters * (size_t)n * sizeof(unsigned long long),
                            p->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(p->d_tdet, td.data(), td.size() * sizeof(TileRef),
+    for (int t = 0; t < 3 && e == hipSuccess; ++t)
+        e = hipMemcpyAsync(p->d_tdet[t], td[t].data(), td[t].size() * sizeof(TileRef),
                            hipMemcpyHostToDevice, p->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(p->d_tgrow, tg.data(), tg.size() * sizeof(TileRef),
@@ -860,27 +1112,11 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
         return hip_status(e, "hipMemcpy");
     }
     if (use_graph) {
-        e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            plan_free(p);
-            return hip_status(e, "hipStreamBeginCapture");
-        }
-        st = plan_enqueue(p);
-        hipGraph_t g = nullptr;
-        e = hipStreamEndCapture(p->stream, &g);
-        if (st != CRB_OK || e != hipSuccess) {
-            if (g)
-                (void)hipGraphDestroy(g);
-            plan_free(p);
-            return st != CRB_OK ? st : hip_status(e, "hipStreamEndCapture");
-        }
-        p->graph = g;
-        e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            plan_free(p);
-            return hip_status(e, "hipGraphInstantiate");
-        }
         p->use_graph = true;
+        if ((st = plan_capture(p)) != CRB_OK) {
+            plan_free(p);
+            return st;
+        }
     }
     *out_plan = p;
     return ok();
@@ -914,6 +1150,111 @@ crb_status crb_plan_stats(crb_plan *p, crb_frame *frames, int32_t n) {
 }
 
 void crb_plan_destroy(crb_plan *p) { plan_free(p); }
+
+crb_status crb_plan_set_tuning(crb_plan *p, const crb_tuning *t) {
+    if (!p || !t)
+        return fail(CRB_EINVAL, "null argument");
+    crb_status st = plan_apply(p, cfg_from(*t));
+    return st == CRB_OK ? ok() : st;
+}
+
+crb_status crb_plan_get_tuning(crb_plan *p, crb_tuning *t) {
+    if (!p || !t)
+        return fail(CRB_EINVAL, "null argument");
+    *t = tuning_from(p->cfg);
+    return ok();
+}
+
+crb_status crb_plan_autotune(crb_plan *p, int32_t reps, int32_t use_cache, crb_tuning *best,
+                             double *out_ms, double *out_default_ms) {
+    if (!p)
+        return fail(CRB_EINVAL, "null plan");
+    if (reps < 1 || reps > 1000)
+        return fail(CRB_EINVAL, "reps must lie in [1, 1000] (got %d)", reps);
+    for (const DevFrame &f : p->hframes)
+        if (f.img == f.J)
+            return fail(CRB_EINVAL, "autotuning runs the batch several times: a frame cleaned "
+                                    "in place (out_clean == img) would lose its input");
+    if (p->key.empty())
+        p->key = layout_key(p->hframes, p->device);
+    LaunchCfg chosen;
+    if (use_cache && tune_cache_lookup(p->key, &chosen)) {
+        crb_status st = plan_apply(p, chosen);
+        if (st != CRB_OK)
+            return st;
+        if (best)
+            *best = tuning_from(chosen);
+        if (out_ms)
+            *out_ms = -1.0;
+        if (out_default_ms)
+            *out_default_ms = -1.0;
+        return ok();
+    }
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess)
+        return hip_status(e, "hipStreamSynchronize");
+    hipEvent_t a = nullptr, b = nullptr;
+    e = hipEventCreate(&a);
+    if (e == hipSuccess)
+        e = hipEventCreate(&b);
+    if (e != hipSuccess) {
+        if (a)
+            (void)hipEventDestroy(a);
+        return hip_status(e, "hipEventCreate");
+    }
+    // Stage 1: detection shapes (tile height x one block per tile or persistent) under
+    // the default grow; stage 2: grow shapes (three launches with first-iteration strips
+    // of 8, 16 or 32 rows, or the fused grow and replacement) under the best detection.
+    // The two stages time whole runs; detection and grow touch disjoint launches, so
+    // their choices combine.
+    crb_status st = CRB_OK;
+    const LaunchCfg def;
+    double t_def = 0.0;
+    st = time_cfg(p, def, reps, a, b, &t_def);
+    LaunchCfg cur = def;
+    double t_cur = t_def;
+    for (int ti = 0; st == CRB_OK && ti < 3; ++ti)
+        for (int pers = 0; st == CRB_OK && pers <= 1; ++pers) {
+            LaunchCfg c = def;
+            c.tile_h = kTileHeights[ti];
+            c.persistent = pers;
+            if (c.tile_h == def.tile_h && c.persistent == def.persistent)
+                continue;
+            double t = 0.0;
+            st = time_cfg(p, c, reps, a, b, &t);
+            if (st == CRB_OK && t < t_cur) {
+                t_cur = t;
+                cur = c;
+            }
+        }
+    const int growh[4] = {8, 16, 32, -1};      // -1: fused
+    const LaunchCfg det = cur;
+    for (int gi = 0; st == CRB_OK && gi < 4; ++gi) {
+        LaunchCfg c = det;
+        c.fused = growh[gi] < 0 ? 1 : 0;
+        c.grow_h = growh[gi] < 0 ? 0 : growh[gi];
+        double t = 0.0;
+        st = time_cfg(p, c, reps, a, b, &t);
+        if (st == CRB_OK && t < t_cur) {
+            t_cur = t;
+            cur = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != CRB_OK)
+        return st;
+    if ((st = plan_apply(p, cur)) != CRB_OK)
+        return st;
+    tune_cache_store(p->key, cur, t_cur, t_def);
+    if (best)
+        *best = tuning_from(cur);
+    if (out_ms)
+        *out_ms = t_cur;
+    if (out_default_ms)
+        *out_default_ms = t_def;
+    return ok();
+}
 
 crb_status crb_plan_set_timing(crb_plan *p, int32_t enable) {
     if (!p)

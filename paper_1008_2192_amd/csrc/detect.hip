@@ -1,9 +1,10 @@
 // Detection kernel of libcrb for gfx950 (MI355X): the first stage of an L.A.Cosmic
 // iteration (Mighell, Section 5) -- L+ (2x-subsampled clipped Laplacian, rebinned),
 // N from med5(J), S = L+/(2N), S' = S - med5(S), F^ from med3(J) - med7(med3(J)),
-// the first selection and the two threshold bits the grow reads -- on 32 x 64 LDS
-// tiles with the halo each quantity needs, plus the parity-test kernels of its median
-// networks.
+// the first selection and the two threshold bits the grow reads -- on LDS tiles of 64
+// columns by 16, 32 or 64 rows with the halo each quantity needs, one block per tile or
+// persistent blocks taking tiles from ticket counters, plus the parity-test kernels of
+// its median networks.
 //
 // Numerics: medians are exact selections by min/max networks.  Every decision (a
 // threshold bit, the contrast test) is the one the binary64 definition takes: S is
@@ -291,26 +292,38 @@ __device__ __forceinline__ int contrast_by_count_lane(const float *sJ, int jp, i
     return sure >= 25 ? 1 : (maybe < 25 ? 0 : -1);
 }
 
-// Wave 0: exclusive prefix sums of the set-bit counts of 64 bitmap words (one per
-// lane) into pre[0..63], the total into pre[64].
-__device__ __forceinline__ void bitmap_prefix64(const uint32_t *bits, uint32_t *pre) {
-    const int lane = threadIdx.x;
-    const int c = __popc(bits[lane]);
-    int v = c;
+// Exclusive prefix sums of the set-bit counts of the NWORDS words of a bitmap into
+// pre[0 .. NWORDS-1], the total into pre[NWORDS]; by the first wave (all 64 lanes), each
+// lane taking NWORDS / 64 consecutive words (or one, or none past NWORDS, when NWORDS is
+// at most 64).
+template <int NWORDS>
+__device__ __forceinline__ void bitmap_prefix(const uint32_t *bits, uint32_t *pre) {
+    static_assert(NWORDS <= 64 || NWORDS % 64 == 0, "whole words per lane");
+    constexpr int WPL = NWORDS > 64 ? NWORDS / 64 : 1;
+    const int lane = threadIdx.x & 63;
+    unsigned int c[WPL], tot = 0u;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(v, off);
-        if (lane >= off)
-            v += u;
+    for (int i = 0; i < WPL; ++i) {
+        const int w = lane * WPL + i;
+        c[i] = w < NWORDS ? (unsigned int)__popc(bits[w]) : 0u;
+        tot += c[i];
     }
-    pre[lane] = (uint32_t)(v - c);
+    unsigned int ex = __ockl_wfscan_add_u32(tot, false);
+#pragma unroll
+    for (int i = 0; i < WPL; ++i) {
+        const int w = lane * WPL + i;
+        if (w < NWORDS)
+            pre[w] = ex;
+        ex += c[i];
+    }
     if (lane == 63)
-        pre[64] = (uint32_t)v;
+        pre[NWORDS] = ex;
 }
 
-// Position (word * 32 + bit) of the q-th set bit of a 64-word bitmap with prefix pre.
-__device__ __forceinline__ int bitmap_select64(const uint32_t *bits, const uint32_t *pre, int q) {
-    int lo = 0, hi = 63;    // last word whose prefix is <= q
+// Position (word * 32 + bit) of the q-th set bit of an NWORDS-word bitmap with prefix pre.
+template <int NWORDS>
+__device__ __forceinline__ int bitmap_select(const uint32_t *bits, const uint32_t *pre, int q) {
+    int lo = 0, hi = NWORDS - 1;    // last word whose prefix is <= q
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if ((int)pre[mid] <= q)
@@ -324,22 +337,37 @@ __device__ __forceinline__ int bitmap_select64(const uint32_t *bits, const uint3
     return lo * 32 + __ffs(b) - 1;
 }
 
+// Appends pos0 + b for every set bit b of m (one word per lane; called by whole waves) to
+// an LDS list: places within the wave by a DPP prefix sum, the wave's base by one LDS
+// atomic on *count, so that several waves append in any order.  Entries at or beyond cap
+// are not stored; *count ends as the number of bits appended by all waves.
+__device__ __forceinline__ void list_append(uint32_t m, int pos0, uint16_t *list,
+                                            unsigned int *count, unsigned int cap, int lane) {
+    const unsigned int cnt = (unsigned int)__popc(m);
+    unsigned int at = __ockl_wfscan_add_u32(cnt, false);
+    const unsigned int total = (unsigned int)__builtin_amdgcn_readlane((int)(at + cnt), 63);
+    unsigned int base = 0u;
+    if (lane == 0 && total)
+        base = atomicAdd(count, total);
+    at += (unsigned int)__builtin_amdgcn_readfirstlane((int)base);
+    for (uint32_t mm = m; mm; mm &= mm - 1u, ++at)
+        if (at < cap)
+            list[at] = (uint16_t)(pos0 + __ffs(mm) - 1);
+}
+
 // Work shapes inside a detection block: a lower bound of med5(J), L+ and an upper bound
 // of S in 2 x 5 thread tiles over the whole tile and its 2-pixel apron; med5(J) and the S
 // estimate in 2 x 2 quads near where S may exceed sigclip.  The remaining statistics,
 // med3 among them, are evaluated only where a code bit can matter.
 // Run length of the 3x3 median network's parity kernel (sorted columns shared by runs).
 constexpr int kRun3 = 14;
-// pixels per round of the binary64 re-evaluation (25 threads each)
-constexpr int kExactBatch = kThreads / 25;
-// pixels whose contrast test a block lists for its contrast phase (one wave each);
-// further ones take the same test in their own lanes
-constexpr int kConMax = 32;
-// work-set pixels a block lists; a larger work set is taken from its bitmap instead
-constexpr int kListMax = 512;
 
-template <int TY, int TX>
+// A detection tile is TY rows of 64 columns, one block of 8 * TY threads: each thread
+// writes 8 codes of one row, so wave w holds rows 8w .. 8w+7.  TY in {16, 32, 64} (the
+// tile shapes the autotuner picks from; 32 is the default).
+template <int TY>
 struct DetectLayout {
+    static constexpr int TX = 64, NT = 8 * TY, NW = NT / 64;
     // logical extents of the LDS planes and their row pitches; the pitches spread the
     // stage-1 and stage-2 scalar accesses over the LDS banks
     static constexpr int JH = TY + 8, JW = TX + 8, JWP = TX + 9;    // J, apron 4
@@ -347,11 +375,25 @@ struct DetectLayout {
     static constexpr int HW = (SW + 31) / 32;   // words per row of the hot bitmap
     static constexpr int QW = TX / 32;          // words per row of the tile bitmaps
     static constexpr int kTileWords = TY * QW;
-    static_assert(TX % 32 == 0 && kTileWords == 64, "one wave scans a tile bitmap");
+    // pixels per round of the binary64 re-evaluation (25 threads each)
+    static constexpr int kExactBatch = NT / 25;
+    // pixels whose contrast test a block lists for its contrast phase (one wave each);
+    // further ones take the same test in their own lanes
+    static constexpr int kConMax = TY;
+    // work-set pixels a block lists; a larger work set is taken from its bitmap instead
+    static constexpr int kListMax = 16 * TY;
+    // LDS budget for the resident blocks per CU (the CU hands out LDS in 1 KiB units):
+    // 12 blocks of 16 rows, 6 of 32 rows, 3 of 64 rows (about 24 waves per CU)
+    static constexpr int kLdsBudget = TY == 16 ? 15360 : (TY == 32 ? 26624 : 53248);
+    static_assert(TY == 16 || TY == 32 || TY == 64, "tile heights 16, 32, 64");
+    static_assert(NW * 64 == NT && QW == 2, "whole waves; two bitmap words per tile row");
     static_assert(QW + 1 <= HW, "dilation reads two bitmap words per work word");
     static_assert(SH * SWP * 4 >= kExactBatch * 26 * 8, "re-evaluation buffer in the S plane");
 };
 
+// The detection of one tile (origin y0, x0 of frame f, iteration k), by the whole block.
+// Every early return is taken by all threads alike.
+//
 // Which pixels need S', F^ and the threshold bits.  With H = {S > sigclip} (S' > t
 // implies S > t for t >= 0: med5(S) >= 0 because S >= 0, and rounding is monotone):
 //   first(p) can be 1 only on H;
@@ -369,11 +411,11 @@ struct DetectLayout {
 // binary64 from J.  So every code written is the full definition's, codes outside Q'
 // are 0, and the grow, which reads codes only through its two dilations, sees the full
 // definition.
-template <int TY, int TX>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(6)))
-void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
-              DevFrame single, int kiter) {
-    using L = DetectLayout<TY, TX>;
+template <int TY>
+__device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, int k, int tid) {
+    using L = DetectLayout<TY>;
+    constexpr int TX = L::TX, NT = L::NT;
+    constexpr int kConMax = L::kConMax, kListMax = L::kListMax, kExactBatch = L::kExactBatch;
     __shared__ __align__(16) float sJ[L::JH * L::JWP];       // J, clamped extension
     __shared__ __align__(16) float sS[L::SH * L::SWP];      // later: re-evaluation buffer
     __shared__ __align__(16) uint8_t sCode[TY * TX];
@@ -388,40 +430,28 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // pixels whose contrast test is left to the contrast phase: position, S' interval
     __shared__ uint32_t sConInfo[kConMax];
     __shared__ float sConLo[kConMax], sConHi[kConMax], sConM5[kConMax];
-    // 6 blocks per CU: a block of 27,088 bytes already ran as 5 (the CU does not hand out
-    // all 160 KiB in sixths), so the planes and lists stay within 26,624 bytes
     static_assert(sizeof(sJ) + sizeof(sS) + sizeof(sCode) + sizeof(sHot) + sizeof(sU) +
                           sizeof(sUpre) + sizeof(sLow) + sizeof(sList) + sizeof(sConInfo) +
-                          sizeof(sConLo) + sizeof(sConHi) + sizeof(sConM5) + 7 * 4 <=
-                      26624,
-                  "the LDS of a detection block must let 6 blocks share a CU");
+                          sizeof(sConLo) + sizeof(sConHi) + sizeof(sConM5) + 7 * 4 + 16 <=
+                      L::kLdsBudget,
+                  "the LDS of a detection block must let its resident blocks share a CU");
 
-    DevFrame f;
-    int y0, x0;
-    if (tiles) {
-        const TileRef t = tiles[blockIdx.x];
-        f = frames[t.frame];
-        y0 = t.y0;
-        x0 = t.x0;
-    } else {
-        f = single;
-        y0 = blockIdx.y * TY;
-        x0 = blockIdx.x * TX;
-    }
-    const int k = kiter ? kiter : f.k;
     if (frame_skips(f, k))
         return;
-    const int H = f.H, W = f.W, tid = threadIdx.x;
-    // incremental mode: a tile whose J neighbourhood is unchanged since the previous
-    // iteration keeps its codes; every thread reads the flag before it is consumed
-    if ((f.flags & kIncremental) && f.dirty) {
-        const int ti = (y0 / TY) * ((W + TX - 1) / TX) + x0 / TX;
-        const bool dirty = k == 1 || f.dirty[ti] != 0;
-        __syncthreads();
-        if (!dirty)
+    const int H = f.H, W = f.W;
+    const int lane = tid & 63;
+    // incremental mode: from iteration 2 on, a tile is re-evaluated only when the
+    // previous replacement changed J within 4 pixels of it, which it records by stamping
+    // the 32 x 64 summary tiles it reached with its iteration (every thread reads the
+    // same stamps, so the return is uniform)
+    if ((f.flags & kIncremental) && f.dirty && k >= 2) {
+        // a tile of at most 64 rows meets one or two rows of summary tiles
+        static_assert(TY <= 2 * kSumTY, "at most two summary rows per tile");
+        const int ntx = (W + kSumTX - 1) / kSumTX, c = x0 / kSumTX;
+        const int r0 = y0 / kSumTY, r1 = (min(y0 + TY, H) - 1) / kSumTY;
+        const uint8_t want = (uint8_t)(k - 1);
+        if (f.dirty[r0 * ntx + c] != want && f.dirty[r1 * ntx + c] != want)
             return;
-        if (tid == 0)
-            f.dirty[ti] = 0;
     }
     // iteration 1 reads the input frame and initialises J with the tile's own pixels
     const float *__restrict__ J = (k == 1) ? f.img : f.J;
@@ -431,11 +461,11 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     const float sc_lo = sc * (1.0f - 0x1p-20f), sc_hi = sc * (1.0f + 0x1p-20f);
     const float ll_lo = ll * (1.0f - 0x1p-20f), ll_hi = ll * (1.0f + 0x1p-20f);
 
-    for (int i = tid; i < L::SH * L::HW; i += kThreads)
+    for (int i = tid; i < L::SH * L::HW; i += NT)
         sHot[i] = 0u;
-    if (tid < L::kTileWords) {
-        sU[tid] = 0u;
-        sLow[tid] = 0u;
+    for (int i = tid; i < L::kTileWords; i += NT) {
+        sU[i] = 0u;
+        sLow[i] = 0u;
     }
     if (tid == 0) {
         sErrBits = 0u;
@@ -449,43 +479,56 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // J over [y0-4, y0+TY+4) x [x0-4, x0+TX+4), clamped reads.  Thread t loads column
     // t % JW of rows t / JW + kJStep * b, so its clamped column is computed once and, on
     // tiles whose rows are all inside the frame, each further row costs one address
-    // step.  All of a thread's loads are issued before the first LDS store, so their
-    // latencies overlap.
+    // step.  A thread's loads (all of them, or half when there are more than 16) are
+    // issued before its first LDS store, so their latencies overlap.
     {
-        constexpr int kJStep = kThreads / L::JW;
+        constexpr int kJStep = NT / L::JW;
         constexpr int NB = (L::JH + kJStep - 1) / kJStep;
+        constexpr int NC = NB > 16 ? (NB + 1) / 2 : NB;      // loads in flight per round
         const int c = tid % L::JW, r0 = tid / L::JW;
         if (r0 < kJStep) {
             const int cc = clampi(x0 - 4 + c, W);
-            float v[NB];
-            if (y0 >= 4 && y0 + TY + 4 <= H && W <= (1 << 24)) {
-                // buffer loads over the JH staged rows (below 2^32 bytes: at most 2^24
-                // pixels per row): a per-lane byte offset and a uniform row step, so a
-                // further row costs no vector instruction
+            if (y0 >= 4 && y0 + TY + 4 <= H && (long long)L::JH * W * 4 <= 0x7fffffffll) {
+                // buffer loads over the JH staged rows (below 2^31 bytes, so the byte
+                // count, the lane offsets and the row steps below are exact in int): a
+                // per-lane byte offset and a uniform row step, so a further row costs no
+                // vector instruction
                 const __amdgpu_buffer_rsrc_t rows = __builtin_amdgcn_make_buffer_rsrc(
                     (void *)(J + (size_t)(y0 - 4) * W), (short)0, L::JH * W * 4, kBufferWord3);
                 const int boff = (r0 * W + cc) * 4;
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    if (r0 + kJStep * b < L::JH)
-                        v[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-                            rows, boff, kJStep * b * W * 4, 0));
+                for (int b0 = 0; b0 < NB; b0 += NC) {
+                    float v[NC];
+#pragma unroll
+                    for (int b = 0; b < NC; ++b)
+                        if (b0 + b < NB && r0 + kJStep * (b0 + b) < L::JH)
+                            v[b] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                                rows, boff, kJStep * (b0 + b) * W * 4, 0));
+#pragma unroll
+                    for (int b = 0; b < NC; ++b)
+                        if (b0 + b < NB && r0 + kJStep * (b0 + b) < L::JH)
+                            sJ[(r0 + kJStep * (b0 + b)) * L::JWP + c] = v[b];
+                }
             } else {
 #pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    if (r0 + kJStep * b < L::JH)
-                        v[b] = J[(size_t)clampi(y0 - 4 + r0 + kJStep * b, H) * W + cc];
-            }
+                for (int b0 = 0; b0 < NB; b0 += NC) {
+                    float v[NC];
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                if (r0 + kJStep * b < L::JH)
-                    sJ[(r0 + kJStep * b) * L::JWP + c] = v[b];
+                    for (int b = 0; b < NC; ++b)
+                        if (b0 + b < NB && r0 + kJStep * (b0 + b) < L::JH)
+                            v[b] = J[(size_t)clampi(y0 - 4 + r0 + kJStep * (b0 + b), H) * W + cc];
+#pragma unroll
+                    for (int b = 0; b < NC; ++b)
+                        if (b0 + b < NB && r0 + kJStep * (b0 + b) < L::JH)
+                            sJ[(r0 + kJStep * (b0 + b)) * L::JWP + c] = v[b];
+                }
+            }
         }
     }
     __syncthreads();
     // iteration 1: the tile's own pixels of the input become J, 8 per thread
+    static_assert(TY * TX == 8 * NT, "one 8-pixel row segment per thread");
     if (k == 1 && f.img != f.J) {
-        static_assert(TY * TX == 8 * kThreads, "one 8-pixel row segment per thread");
         const int r = tid / (TX / 8), cs = (tid - r * (TX / 8)) * 8;
         const int gy = y0 + r, gx = x0 + cs;
         if (gy < H && gx < W) {
@@ -518,23 +561,22 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         }
     }
 
-    // Over [y0-2, y0+TY+2) x [x0-2, x0+TX+2), in one 2 x 5 cell tile per thread.
-    // Dense pass: a lower bound x of med5(J) shared by the tile's ten windows (the least
-    // of the column medians of its 6 x 9 patch: every window holds five of those columns,
-    // each with three values at or above its median, so 15 of its 25 values are >= x);
-    // S does not increase with med5(J), so the estimate at x with its error bound bounds
-    // S from above, and H' = the in-frame cells where that bound exceeds sigclip (less a
-    // margin) holds H.
+    // Over [y0-2, y0+TY+2) x [x0-2, x0+TX+2), in 2 x 5 cell tiles (one per thread and
+    // pass).  Dense pass: a lower bound x of med5(J) shared by the tile's ten windows (the
+    // least of the column medians of its 6 x 9 patch: every window holds five of those
+    // columns, each with three values at or above its median, so 15 of its 25 values are
+    // >= x); S does not increase with med5(J), so the estimate at x with its error bound
+    // bounds S from above, and H' = the in-frame cells where that bound exceeds sigclip
+    // (less a margin) holds H.
     constexpr int TTY = 2, TTX = 5, PW = TTX + 4;
     constexpr int NTY = (L::SH + TTY - 1) / TTY, NTX = (L::SW + TTX - 1) / TTX;
-    static_assert(NTY * NTX <= kThreads, "one pass of 2 x 5 tiles");
     const SEstParams sp = sest_params(f);
-    const int lane = tid & 63;
-    if (tid < NTY * NTX) {
+#pragma unroll 1
+    for (int ti = tid; ti < NTY * NTX; ti += NT) {
         // column-major over the 2 x 5 tiles: with the J pitch this spreads a wave's patch
         // loads over the LDS banks
-        const int tx = tid / NTY;
-        const int r5 = min((tid - tx * NTY) * TTY, L::SH - TTY);
+        const int tx = ti / NTY;
+        const int r5 = min((ti - tx * NTY) * TTY, L::SH - TTY);
         const int c5 = min(tx * TTX, L::SW - TTX);
         float v[(TTY + 4) * PW];
 #pragma unroll
@@ -594,23 +636,25 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // The later stages read S (to within the block's largest error bound) and med5(J)
     // only within 4 cells of H': the work set lies within 2 of H', and med5(S) at a work
     // pixel reads 2 further (a clamped neighbour's cell is no farther).  That region, in
-    // 2 x 2 cell quads (row pair p, even column c: one 32-column word per thread), is
-    // listed by the first wave and the quads take the exact med5 network in list order.
+    // 2 x 2 cell quads (row pair p, even column c: one 32-column word per lane), is
+    // listed by the first waves and the quads take the exact med5 network in list order.
     constexpr int NP = L::SH / 2;
-    static_assert(L::SH % 2 == 0 && L::SW % 2 == 0 && NP * L::HW <= 64,
-                  "whole quads, one bitmap word per lane of a wave");
+    constexpr int kQuadWords = NP * L::HW;
+    constexpr int kQuadWaves = (kQuadWords + 63) / 64;
+    static_assert(L::SH % 2 == 0 && L::SW % 2 == 0 && kQuadWaves <= L::NW,
+                  "whole quads; the quad bitmap words fit the block's waves");
     constexpr int kQuads = NP * L::SW / 2;
     static_assert(kQuads <= TY * TX / 2, "the quad list fits in the code plane");
-    constexpr int kQuadRounds = (kQuads + kThreads - 1) / kThreads;
+    constexpr int kQuadRounds = (kQuads + NT - 1) / NT;
     uint16_t *const sQuads = reinterpret_cast<uint16_t *>(sCode);   // codes start later
-    if (tid < 64) {
+    if (tid < 64 * kQuadWaves) {
         uint32_t m = 0u;
-        if (tid < NP * L::HW) {
-            const int pr = tid / L::HW, w = tid - pr * L::HW;
+        const int pr = tid / L::HW, w = tid - pr * L::HW;
+        if (tid < kQuadWords) {
             uint32_t a = 0u, b = 0u, c = 0u;        // words w - 1, w, w + 1 of the rows
 #pragma unroll
-            for (int k = 0; k < 10; ++k) {
-                const int rr = 2 * pr - 4 + k;
+            for (int kk = 0; kk < 10; ++kk) {
+                const int rr = 2 * pr - 4 + kk;
                 const bool in = rr >= 0 && rr < L::SH;
                 const uint32_t *row = &sHot[(in ? rr : 0) * L::HW];
                 const uint32_t ra = row[w > 0 ? w - 1 : 0], rb = row[w],
@@ -634,14 +678,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             // quads by their even column
             m = (m | (m >> 1)) & 0x55555555u;
         }
-        const unsigned int cnt = (unsigned int)__popc(m);
-        unsigned int at = __ockl_wfscan_add_u32(cnt, false);
-        const unsigned int total = (unsigned int)__builtin_amdgcn_readlane((int)(at + cnt), 63);
-        const int pr = tid / L::HW, w = tid - pr * L::HW;
-        for (uint32_t mm = m; mm; mm &= mm - 1u)
-            sQuads[at++] = (uint16_t)(pr * L::SW + 32 * w + __ffs(mm) - 1);
-        if (tid == 0)
-            sNeedCount = total;
+        list_append(m, pr * L::SW + 32 * w, sQuads, &sNeedCount, (unsigned int)kQuads, lane);
     }
     __syncthreads();
     // Exact pass: med5(J), L+ and the S estimate with its error bound; the block's largest
@@ -654,7 +691,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         unsigned int ncells = 0u;
 #pragma unroll
         for (int rd = 0; rd < kQuadRounds; ++rd) {
-            const int it = tid + rd * kThreads;
+            const int it = tid + rd * NT;
             if (it < nquads) {
                 const int q = (int)sQuads[it];
                 const int pr = q / L::SW, cc = q - pr * L::SW, r0 = 2 * pr;
@@ -708,7 +745,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // Region cells outside the image must hold the value of their clamped cell: the
     // windows of the work set read S at clamped neighbour positions.
     if (y0 < 2 || x0 < 2 || y0 + TY + 2 > H || x0 + TX + 2 > W) {
-        for (int i = tid; i < L::SH * L::SW; i += kThreads) {
+        for (int i = tid; i < L::SH * L::SW; i += NT) {
             const int r = i / L::SW, c = i - r * L::SW;
             const int gy = y0 - 2 + r, gx = x0 - 2 + c;
             if (gy < 0 || gy >= H || gx < 0 || gx >= W)
@@ -716,42 +753,39 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
                     sS[(clampi(gy, H) - (y0 - 2)) * L::SWP + (clampi(gx, W) - (x0 - 2))];
         }
     }
-    for (int i = tid; i < TY * TX / 4; i += kThreads)
+    for (int i = tid; i < TY * TX / 4; i += NT)
         reinterpret_cast<uint32_t *>(sCode)[i] = 0u;
     const float emax = __uint_as_float(sErrBits);
     // no estimate of the block is usable: every work pixel is re-evaluated
     const bool all_exact = !(emax < INFINITY) || (f.flags & kExactDetect);
-    // work set Q' on the tile's in-frame pixels, one 32-pixel word per lane of the
-    // first wave, appended to a compact list of tile positions (in any order)
-    static_assert(L::kTileWords == 64, "one bitmap word per lane of the first wave");
-    if (tid < L::kTileWords) {
-        const int r = tid / L::QW, w = tid - r * L::QW;
-        unsigned long long x = 0ull;
+    // work set Q' on the tile's in-frame pixels, one 32-pixel word per lane of the first
+    // waves, appended to a compact list of tile positions (in any order)
+    constexpr int kWorkWaves = (L::kTileWords + 63) / 64;
+    if (tid < 64 * kWorkWaves) {
+        uint32_t q = 0u;
+        if (tid < L::kTileWords) {
+            const int r = tid / L::QW, w = tid - r * L::QW;
+            unsigned long long x = 0ull;
 #pragma unroll
-        for (int dr = 0; dr < 5; ++dr) {
-            const uint32_t *row = &sHot[(r + dr) * L::HW + w];
-            x |= (unsigned long long)row[0] | ((unsigned long long)row[1] << 32);
+            for (int dr = 0; dr < 5; ++dr) {
+                const uint32_t *row = &sHot[(r + dr) * L::HW + w];
+                x |= (unsigned long long)row[0] | ((unsigned long long)row[1] << 32);
+            }
+            // bit b of the dilation covers region columns 32w+b .. 32w+b+4, centred on
+            // the tile column 32w+b
+            q = (uint32_t)(x | (x >> 1) | (x >> 2) | (x >> 3) | (x >> 4));
+            const int vc = W - x0 - 32 * w;
+            if (y0 + r >= H || vc <= 0)
+                q = 0u;
+            else if (vc < 32)
+                q &= (1u << vc) - 1u;
+            q &= sLow[tid];
+            sLow[tid] = q;
+            if (all_exact)
+                sU[tid] = q;
         }
-        // bit b of the dilation covers region columns 32w+b .. 32w+b+4, centred on
-        // the tile column 32w+b
-        uint32_t q = (uint32_t)(x | (x >> 1) | (x >> 2) | (x >> 3) | (x >> 4));
-        const int vc = W - x0 - 32 * w;
-        if (y0 + r >= H || vc <= 0)
-            q = 0u;
-        else if (vc < 32)
-            q &= (1u << vc) - 1u;
-        q &= sLow[tid];
-        sLow[tid] = q;
-        if (all_exact)
-            sU[tid] = q;
-        const unsigned int cnt = (unsigned int)__popc(q);
-        unsigned int at = __ockl_wfscan_add_u32(cnt, false);
-        const unsigned int qtotal = (unsigned int)__builtin_amdgcn_readlane((int)(at + cnt), 63);
-        if (qtotal <= (unsigned int)kListMax)
-            for (uint32_t m = q; m; m &= m - 1u)
-                sList[at++] = (uint16_t)(tid * 32 + __ffs(m) - 1);   // = r * TX + column
-        if (tid == 0)
-            sQcount = qtotal;
+        // word tid covers tile positions tid * 32 .. (r * TX + 32 w with two words a row)
+        list_append(q, tid * 32, sList, &sQcount, (unsigned int)kListMax, lane);
     }
     __syncthreads();
 
@@ -759,7 +793,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     const double rn2 = rn * rn, sigclip = f.sigclip, objlim = f.objlim;
     const double lowlim = (double)f.sigfrac * (double)f.sigclip;
     const int total = (int)sQcount;
-    // the work set, compacted: thread t takes the t-th, (t+256)-th, ... pixel of Q' (of
+    // the work set, compacted: thread t takes the t-th, (t+NT)-th, ... pixel of Q' (of
     // the tile, tested against the Q' bitmap, when the list could not hold Q').
     // S' from the estimates lies within B of the binary64 S' (B covers twice the
     // block's largest error and, with 4u, the roundings of the differences)
@@ -769,7 +803,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         const float olim = f.objlim;
         const float olim_lo = olim * (1.0f - 0x1p-21f), olim_hi = olim * (1.0f + 0x1p-21f);
         unsigned int ncontrast = 0u, nunc = 0u;
-        for (int qi = tid; qi < (listed_q ? total : TY * TX); qi += kThreads) {
+        for (int qi = tid; qi < (listed_q ? total : TY * TX); qi += NT) {
             const int pos = listed_q ? (int)sList[qi] : qi;
             if (!listed_q && !((sLow[pos >> 5] >> (pos & 31)) & 1u))
                 continue;
@@ -837,10 +871,9 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // contrast tests of the listed pixels (S' > sigclip certain), one wave per pixel
     const int ncon = min((int)sConCount, kConMax);
     if (ncon) {
-        const SEstParams sp = sest_params(f);
         const float inv_olim = 1.0f / f.objlim;
         unsigned int ncontrast = 0u, nunc = 0u;
-        for (int it = tid >> 6; it < ncon; it += kThreads / 64) {
+        for (int it = tid >> 6; it < ncon; it += L::NW) {
             const uint32_t info = sConInfo[it];
             const int pos = (int)(info & 0xFFFFu);
             const int r = pos / TX, c = pos - r * TX;
@@ -867,14 +900,14 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
     // 25 threads compute the S window of a pixel, then one thread its codes
     const int nunc = (int)sUncertain;
     if (nunc) {
-        if (tid < L::kTileWords)
-            bitmap_prefix64(sU, sUpre);
+        if (tid < 64)
+            bitmap_prefix<L::kTileWords>(sU, sUpre);
         __syncthreads();
         unsigned int ncontrast = 0u;
         for (int base = 0; base < nunc; base += kExactBatch) {
             const int slot = tid / 25, cell = tid - slot * 25;
             if (slot < kExactBatch && base + slot < nunc) {
-                const int pos = bitmap_select64(sU, sUpre, base + slot);
+                const int pos = bitmap_select<L::kTileWords>(sU, sUpre, base + slot);
                 const int r = pos / TX, c = pos - r * TX;
                 const int i = cell / 5, j = cell - i * 5;
                 // window cell in frame coordinates, clamped
@@ -898,7 +931,7 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             }
             __syncthreads();
             if (tid < kExactBatch && base + tid < nunc) {
-                const int pos = bitmap_select64(sU, sUpre, base + tid);
+                const int pos = bitmap_select<L::kTileWords>(sU, sUpre, base + tid);
                 const int r = pos / TX, c = pos - r * TX;
                 const double spr = sX[tid * 25 + 12] - sX[kExactBatch * 25 + tid];
                 const bool hbit = spr > sigclip, lbit = spr > lowlim;
@@ -924,10 +957,11 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         __syncthreads();
     }
 
-    // codes of the tile, 8 per thread: thread t writes row t / (TX/8), so wave w holds
-    // rows 8w .. 8w+7 and writes byte w of the tile's f.tile_first word: bit 0 where A
-    // is set in those rows, bit 1 where in rows 0-1, bit 2 where in rows TY-2 .. TY-1
-    static_assert(TY * TX / 8 == kThreads && TX == 64 && TY == 32, "one code word per thread");
+    // codes of the tile, 8 per thread: thread t writes 8 pixels of row t / 8, so wave w
+    // holds rows 8w .. 8w+7 and writes its byte of the summary word of the 32 x 64
+    // summary tile those rows lie in: bit 0 where A is set in those rows, bit 1 where in
+    // the summary tile's rows 0-1, bit 2 where in its rows 30-31
+    static_assert(TX == kSumTX && kSumTY == 32 && TY % 8 == 0, "8-row waves on the summary grid");
     uint8_t *__restrict__ codes = f.codes;
     {
         const int r = tid / (TX / 8), c = (tid - r * (TX / 8)) * 8;
@@ -935,13 +969,14 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
         const uint2 word = *reinterpret_cast<const uint2 *>(&sCode[r * TX + c]);
         if (f.tile_first) {
             const unsigned long long rows_a = __ballot(((word.x | word.y) & 0x01010101u) != 0u);
-            if ((tid & 63) == 0) {
-                const int w = tid >> 6;
+            const int gr = y0 + 8 * (tid >> 6);      // first row of the wave
+            if (lane == 0 && gr < H) {
+                const int sb = (gr & (kSumTY - 1)) >> 3;
                 const unsigned int bits = (rows_a ? 1u : 0u) |
-                                          (w == 0 && (rows_a & 0xFFFFull) ? 2u : 0u) |
-                                          (w == 3 && (rows_a >> 48) ? 4u : 0u);
-                f.tile_first[4 * ((y0 / TY) * ((W + TX - 1) / TX) + x0 / TX) + w] =
-                    (uint8_t)bits;
+                                          (sb == 0 && (rows_a & 0xFFFFull) ? 2u : 0u) |
+                                          (sb == 3 && (rows_a >> 48) ? 4u : 0u);
+                f.tile_first[4 * ((gr / kSumTY) * ((W + kSumTX - 1) / kSumTX) + x0 / kSumTX) +
+                             sb] = (uint8_t)bits;
             }
         }
         if (gy < H && gx < W) {
@@ -964,6 +999,84 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
             atomicAdd(&f.work[2], (unsigned long long)nunc);
         if (sExactCells)
             atomicAdd(&f.work[3], (unsigned long long)sExactCells);
+    }
+}
+
+// (frame, tile origin) of tile t of a launch: from the work list, or for a single frame
+// (tiles == null) the row-major tile t of its grid.
+template <int TY>
+__device__ __forceinline__ void tile_of(const DevFrame *__restrict__ frames,
+                                        const TileRef *__restrict__ tiles, const DevFrame &single,
+                                        int t, DevFrame &f, int &y0, int &x0) {
+    if (tiles) {
+        const TileRef r = tiles[t];
+        f = frames[r.frame];
+        y0 = r.y0;
+        x0 = r.x0;
+    } else {
+        f = single;
+        const int ntx = (single.W + kSumTX - 1) / kSumTX;
+        y0 = (t / ntx) * TY;
+        x0 = (t - (t / ntx) * ntx) * kSumTX;
+    }
+}
+
+// One block per tile.
+template <int TY>
+__global__ __launch_bounds__(8 * TY) __attribute__((amdgpu_waves_per_eu(TY == 16 ? 4 : 6)))
+void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
+              DevFrame single, int kiter) {
+    DevFrame f;
+    int y0, x0;
+    tile_of<TY>(frames, tiles, single, (int)blockIdx.x, f, y0, x0);
+    detect_tile<TY>(f, y0, x0, kiter ? kiter : f.k, (int)threadIdx.x);
+}
+
+// Persistent blocks over a (frame, tile) work list: the grid holds about as many
+// blocks as are resident at once, and each block takes tiles from kDetectQueues ticket
+// counters (zero at launch), counter q over the q-th contiguous part of the list.  Blocks are dispatched round-robin over
+// the XCDs, so block b starts on part b mod kDetectQueues, and the tiles in flight on
+// one XCD are neighbours sharing halo rows and columns in its L2; a block whose part is
+// used up moves to the next, and it returns once all parts are (every counter only
+// grows, so every block gets there).
+template <int TY>
+__global__ __launch_bounds__(8 * TY) __attribute__((amdgpu_waves_per_eu(TY == 16 ? 4 : 6)))
+void k_detect_persistent(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
+                         int kiter, int ntiles, unsigned int *__restrict__ tickets) {
+    __shared__ int sTile;
+    int q = (int)(blockIdx.x % kDetectQueues), tried = 0;
+    for (;;) {
+        __syncthreads();      // the previous tile is done with the LDS and with sTile
+        if (threadIdx.x == 0) {
+            int t = -1;
+            while (tried < kDetectQueues) {
+                const unsigned int lo = (unsigned int)((long long)ntiles * q / kDetectQueues);
+                const unsigned int hi =
+                    (unsigned int)((long long)ntiles * (q + 1) / kDetectQueues);
+                const unsigned int got = lo + atomicAdd(&tickets[q], 1u);
+                if (got < hi) {
+                    t = (int)got;
+                    break;
+                }
+                q = (q + 1) % kDetectQueues;
+                ++tried;
+            }
+            sTile = t;
+        }
+        __syncthreads();
+        // uniform over the block: the tile and frame records then load into scalar
+        // registers, as with blockIdx.x in the one-block-per-tile kernel
+        const int t = __builtin_amdgcn_readfirstlane(sTile);
+        if (t < 0)
+            return;
+        const TileRef r = tiles[t];
+        const DevFrame f = frames[r.frame];
+        // the thread index passes through an empty asm statement each round, so that
+        // values derived from it are recomputed per tile rather than held in registers
+        // across the loop
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        detect_tile<TY>(f, r.y0, r.x0, kiter ? kiter : f.k, tid);
     }
 }
 
@@ -1067,17 +1180,62 @@ hipError_t launch_debug_s_estimate(const DevFrame &f, float *out_s, float *out_e
     return hipGetLastError();
 }
 
-hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
-                         const DevFrame &single, int k, hipStream_t s) {
-    if (d_tiles) {
-        if (ntiles <= 0)
-            return hipSuccess;
-        k_detect<kDetectTY, kDetectTX><<<ntiles, kThreads, 0, s>>>(d_frames, d_tiles, single, k);
+// Resident blocks of a persistent detection launch: the occupancy the runtime reports
+// for the kernel, times the compute units (looked up once per device and tile height).
+template <int TY>
+static int persistent_grid() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+        return 0;
+    if (!cached[dev]) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_detect_persistent<TY>,
+                                                         8 * TY, 0) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                hipSuccess)
+            return 0;
+        cached[dev] = (per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    }
+    return cached[dev];
+}
+
+template <int TY>
+static hipError_t launch_detect_ty(const DevFrame *d_frames, const TileRef *d_tiles,
+                                   int ntiles, const DevFrame &single, int k, bool persistent,
+                                   unsigned int *tickets, hipStream_t s) {
+    if (ntiles <= 0)
+        return hipSuccess;
+    if (persistent && tickets && d_tiles) {
+        const int cap = persistent_grid<TY>();
+        if (cap <= 0)
+            return hipErrorInvalidValue;
+        const int grid = ntiles < cap ? ntiles : cap;
+        k_detect_persistent<TY><<<grid, 8 * TY, 0, s>>>(d_frames, d_tiles, k, ntiles, tickets);
     } else {
-        dim3 grid((single.W + kDetectTX - 1) / kDetectTX, (single.H + kDetectTY - 1) / kDetectTY);
-        k_detect<kDetectTY, kDetectTX><<<grid, kThreads, 0, s>>>(nullptr, nullptr, single, k);
+        k_detect<TY><<<ntiles, 8 * TY, 0, s>>>(d_frames, d_tiles, single, k);
     }
     return hipGetLastError();
+}
+
+hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
+                         const DevFrame &single, int k, const LaunchCfg &cfg,
+                         unsigned int *tickets, hipStream_t s) {
+    if (!d_tiles)
+        ntiles = detect_tiles(single.H, single.W, cfg.tile_h);
+    switch (cfg.tile_h) {
+    case 16:
+        return launch_detect_ty<16>(d_frames, d_tiles, ntiles, single, k, cfg.persistent != 0,
+                                    tickets, s);
+    case 32:
+        return launch_detect_ty<32>(d_frames, d_tiles, ntiles, single, k, cfg.persistent != 0,
+                                    tickets, s);
+    case 64:
+        return launch_detect_ty<64>(d_frames, d_tiles, ntiles, single, k, cfg.persistent != 0,
+                                    tickets, s);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_debug_median5_f64(const double *in, int H, int W, double *out,

@@ -9,10 +9,17 @@ namespace crb {
 
 // Upper bound on iterations per frame (sizes the per-frame counters).
 constexpr int kMaxIter = 1024;
-// Detection tile (outputs per block) and grow tile (outputs per wave: 62 groups of
-// 16 pixels by kGrowTY rows).
-constexpr int kDetectTY = 32;
+// Detection tiles are kDetectTX = 64 columns by 16, 32 (default) or 64 rows, one block of
+// 8 threads per row.  The per-tile records shared by detection, grow and replacement
+// (where A occurs, the last iteration with a new flag, the incremental-detection stamps)
+// live on a fixed grid of kSumTY x kSumTX summary tiles, whatever the detection tile.
 constexpr int kDetectTX = 64;
+constexpr int kDetectTYDefault = 32;
+constexpr int kSumTY = 32;
+constexpr int kSumTX = 64;
+// ticket counters of one persistent detection launch (one per XCD)
+constexpr int kDetectQueues = 8;
+// Grow tile (outputs per wave: 62 groups of 16 pixels by kGrowTY rows).
 constexpr int kGrowTY = 32;
 constexpr int kGrowTYSmall = 8;     // strip height for single frames below 2^22 pixels and
                                     // for every frame after iteration 1
@@ -35,8 +42,9 @@ constexpr int kFreshMask = 1 << 8;
 constexpr int kCountWork = 1 << 9;
 constexpr int kExactDetect = 1 << 10;
 // kIncremental (the value of CRB_FLAG_INCREMENTAL): from iteration 2 on, detection
-// re-evaluates only the tiles flagged in f.dirty (replacement flags the tiles whose
-// codes can change); the others keep their codes, which the unchanged J determines.
+// re-evaluates only the tiles near a summary tile stamped in f.dirty with the previous
+// iteration (replacement stamps the summary tiles whose codes can change); the others
+// keep their codes, which the unchanged J determines.
 constexpr int kIncremental = 2;
 constexpr int kWorkCounters = 4;
 
@@ -53,13 +61,15 @@ struct DevFrame {
     unsigned int *listlen;        // [0]: length of the flagged list, which holds the pixels of
                                   // the mask in the order they were flagged (workspace)
     unsigned long long *work;     // with kCountWork: kWorkCounters counters, or null
-    uint8_t *dirty;               // detection tiles to re-evaluate (kIncremental), row-major
-    // 4 bytes per detection tile, row-major, written by detection (byte w for rows
+    // per summary tile, row-major (kIncremental): the last iteration (mod 256) whose
+    // replacement changed J within 4 pixels of it, or null
+    uint8_t *dirty;
+    // 4 bytes per summary tile, row-major, written by detection (byte w for rows
     // 8w .. 8w+7): bit 0 some pixel of those rows has A (the first selection), bit 1 one
     // of the tile's first two rows, bit 2 one of its last two; the grow skips strips with
     // no A within its 2-pixel reach.  Or null
     uint8_t *tile_first;
-    // per detection tile: the last iteration whose grow flagged a new pixel in it (the
+    // per summary tile: the last iteration whose grow flagged a new pixel in it (the
     // replacement leaves alone pixels with no new flag within 2 pixels), or null
     unsigned int *tile_new;
     int H, W;
@@ -74,18 +84,41 @@ struct TileRef {                  // one (frame, tile origin) work item
     int frame, y0, x0, pad;
 };
 
-// Clears the counters; for frames with niter == 0 also copies img into J and clears
-// the mask (otherwise iteration 1 does both: detection copies img into J and, when
-// kFreshMask is set, clears the mask).  max_pixels: the largest frame with
-// niter == 0 (0 if none), which sizes the grid.
+// Clears the counters and the nticket launch tickets; for frames with niter == 0 also
+// copies img into J and clears the mask (otherwise iteration 1 does both: detection
+// copies img into J and, when kFreshMask is set, clears the mask).  max_pixels: the
+// largest frame with niter == 0 (0 if none), which sizes the grid.
 hipError_t launch_init(const DevFrame *d_frames, int nframes, const DevFrame &single,
-                       size_t max_pixels, hipStream_t s);
-// Detection (codes) for one frame (d_tiles == null: grid over `single`) or a work list.
+                       size_t max_pixels, unsigned int *tickets, int nticket, hipStream_t s);
+
+// How a pass is launched (the autotuner's choices; every choice gives identical
+// results).  tile_h: detection tile rows (16, 32 or 64); persistent: detection by
+// resident blocks taking tiles from ticket counters instead of one block per tile;
+// fused: grow, count and replacement in one launch per iteration (each strip recomputes
+// its 2-row mask halo) instead of grow, list prefix and replacement; grow_h: rows of a
+// first-iteration grow strip of the three-launch path (8, 16 or 32).
+struct LaunchCfg {
+    int tile_h = kDetectTYDefault;
+    int persistent = 0;
+    int fused = 0;
+    int grow_h = 0;          // 0: 32 for batches and large frames, 8 for small frames
+};
+
+// Detection (codes) for one frame (d_tiles == null: tiles over `single`) or a work list
+// of (frame, tile) built for cfg.tile_h.  Persistent launches take kDetectQueues zeroed
+// ticket counters.
 hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
-                         const DevFrame &single, int k, hipStream_t s);
-// Two-stage grow, new-flag count, cumulative mask, flagged list.
+                         const DevFrame &single, int k, const LaunchCfg &cfg,
+                         unsigned int *tickets, hipStream_t s);
+// Number of detection tiles of an H x W frame at tile height tile_h.
+inline int detect_tiles(int H, int W, int tile_h) {
+    return ((H + tile_h - 1) / tile_h) * ((W + kDetectTX - 1) / kDetectTX);
+}
+// Two-stage grow, new-flag count, cumulative mask and flagged list; with cfg.fused (and
+// no debug G2 plane) also the replacement, in one launch (then no list prefix and
+// replacement launch follow).  d_tiles lists 32-row strips of kGrowTX columns.
 hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
-                       const DevFrame &single, int k, hipStream_t s);
+                       const DevFrame &single, int k, const LaunchCfg &cfg, hipStream_t s);
 // Offsets of each frame's flagged list in one flat index space (batched path):
 // d_prefix[i] = sum of the list lengths of frames before i; d_prefix[n] = total.
 hipError_t launch_list_prefix(const DevFrame *d_frames, int nframes, int k,

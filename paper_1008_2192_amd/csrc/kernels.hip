@@ -14,10 +14,13 @@
 // the halo each stage needs: 4 pixels of J for detection (med7 of med3, and med5
 // of S built from a 2-pixel apron of S), 2 pixels of codes for the grow.
 //
-// Numerics: medians are exact selections by min/max networks on FP32 (J, med3) or
-// binary64 (S).  The statistics are binary64, evaluated in the same operation order
-// as the plain definition (no contraction: built with -ffp-contract=off), so a
-// decision on a given J is independent of the tiling and of the launch shape.
+// Numerics: medians are exact selections by min/max networks.  The replacement's
+// median is an exact FP32 selection (the mean of two middle values is formed in
+// binary64 and rounded once).  Every detection decision is the one the binary64
+// definition takes (detect.hip: an FP32 estimate of S decides only where its proven
+// error bound settles the comparison, binary64 in the definition's operation order
+// elsewhere; no contraction: built with -ffp-contract=off), so a decision on a given
+// J is independent of the tiling and of the launch shape.
 #include "kernels.h"
 #include "device_common.h"
 
@@ -134,20 +137,20 @@ __device__ __forceinline__ Px16 load16_aligned(const uint8_t *__restrict__ p, in
 // its first or last two rows only is judged by those rows.  Called by a whole wave.
 template <int TYG>
 __device__ __forceinline__ bool strip_near_first(const DevFrame &f, int y0, int x0, int lane) {
-    // a strip lies in one row of detection tiles, so its reach touches at most three
-    static_assert(kDetectTY % TYG == 0 && 3 * ((kGrowTX + 3) / kDetectTX + 2) <= 64,
-                  "one lane per detection tile within reach");
+    // a strip lies in one row of summary tiles, so its reach touches at most three
+    static_assert(kSumTY % TYG == 0 && 3 * ((kGrowTX + 3) / kSumTX + 2) <= 64,
+                  "one lane per summary tile within reach");
     const int H = f.H, W = f.W;
     const int ylo = max(y0 - 2, 0), yhi = min(y0 + TYG + 1, H - 1);
     const int xlo = max(x0 - 2, 0), xhi = min(x0 + kGrowTX + 1, W - 1);
-    const int r0 = ylo / kDetectTY, c0 = xlo / kDetectTX;
-    const int ncol = xhi / kDetectTX - c0 + 1;
+    const int r0 = ylo / kSumTY, c0 = xlo / kSumTX;
+    const int ncol = xhi / kSumTX - c0 + 1;
     bool hit = false;
-    if (lane < (yhi / kDetectTY - r0 + 1) * ncol) {
-        const int r = r0 + lane / ncol, c = c0 + lane % ncol, top = r * kDetectTY;
-        const unsigned int need = ylo >= top + kDetectTY - 2 ? 4u : (yhi < top + 2 ? 2u : 1u);
+    if (lane < (yhi / kSumTY - r0 + 1) * ncol) {
+        const int r = r0 + lane / ncol, c = c0 + lane % ncol, top = r * kSumTY;
+        const unsigned int need = ylo >= top + kSumTY - 2 ? 4u : (yhi < top + 2 ? 2u : 1u);
         const uint32_t q = reinterpret_cast<const uint32_t *>(f.tile_first)
-                               [r * ((W + kDetectTX - 1) / kDetectTX) + c];
+                               [r * ((W + kSumTX - 1) / kSumTX) + c];
         hit = ((q | q >> 8 | q >> 16 | q >> 24) & need) != 0u;   // the tile's four waves
     }
     return __ballot(hit) != 0ull;
@@ -254,10 +257,9 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
         hi1 = hi2;
         hG0 = hG1; hG1 = hG2;
     }
-    // the strip lies in one row of detection tiles, and a lane's 16 pixels in one tile
+    // the strip lies in one row of summary tiles, and a lane's 16 pixels in one tile
     if (lane_new && f.tile_new)
-        f.tile_new[(y0 / kDetectTY) * ((W + kDetectTX - 1) / kDetectTX) + px / kDetectTX] =
-            (unsigned int)k;
+        f.tile_new[(y0 / kSumTY) * ((W + kSumTX - 1) / kSumTX) + px / kSumTX] = (unsigned int)k;
     // one atomic per wave for the count and one for the list space; one scan of the
     // lanes' counts places each lane's entries (its rows in order) in the wave's space
     const unsigned int tn = __ockl_wfred_add_u32(nnew);
@@ -328,6 +330,46 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 // replacement
 // ---------------------------------------------------------------------------
 
+// The replacement of pixel (y, x) from its clamped 5 x 5 window: v holds J_k there and
+// bit j of fl is set where the window's pixel j is flagged (M_k).  The median of the
+// unflagged values (an even count: the mean of the two middle ones, formed in binary64
+// and rounded once) is written to J; with no unflagged value J keeps its value.
+__device__ __forceinline__ void replace_from_window(const DevFrame &f, int y, int x,
+                                                    float (&v)[25], uint32_t fl, int k) {
+    const int W = f.W, H = f.H;
+    const float old = v[12];
+    int cnt = 0;
+#pragma unroll
+    for (int j = 0; j < 25; ++j) {
+        const bool m = (fl >> j) & 1u;
+        v[j] = m ? INFINITY : v[j];
+        cnt += m ? 0 : 1;
+    }
+    if (cnt == 0)
+        return;
+    sort25(v);
+    const int ia = (cnt - 1) >> 1, ib = cnt >> 1;
+    float a = v[0], b = v[0];
+#pragma unroll
+    for (int j = 1; j < 25; ++j) {
+        a = (j == ia) ? v[j] : a;
+        b = (j == ib) ? v[j] : b;
+    }
+    const float nv = (ia == ib) ? a : (float)(((double)a + (double)b) * 0.5);
+    f.J[(size_t)y * W + x] = nv;
+    // incremental detection: a new value stamps every summary tile within Chebyshev
+    // distance 4 (the reach of a code into J) with this iteration; the next detection
+    // re-evaluates the tiles meeting a summary tile with that stamp
+    if ((f.flags & kIncremental) && __float_as_uint(nv) != __float_as_uint(old)) {
+        const int tx = (W + kSumTX - 1) / kSumTX;
+        const int ty0 = max(y - 4, 0) / kSumTY, ty1 = min(y + 4, H - 1) / kSumTY;
+        const int tx0 = max(x - 4, 0) / kSumTX, tx1 = min(x + 4, W - 1) / kSumTX;
+        for (int a2 = ty0; a2 <= ty1; ++a2)
+            for (int b2 = tx0; b2 <= tx1; ++b2)
+                f.dirty[a2 * tx + b2] = (uint8_t)k;
+    }
+}
+
 // Unflagged pixels are never written and flagged ones are never used as values, so
 // the update in place is correct within the launch.  All 25 mask bytes and all 25 J
 // values of the window are loaded unconditionally (clamped addresses are always
@@ -342,9 +384,9 @@ __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p, int k
     // unflagged window now, so it keeps its value: a tile with no new flag of this
     // iteration (its stamp is not k) within reach means nothing to do.
     if (k >= 2 && f.tile_new) {
-        const int tx = (W + kDetectTX - 1) / kDetectTX;
-        const int r0 = max(y - 2, 0) / kDetectTY, r1 = min(y + 2, H - 1) / kDetectTY;
-        const int c0 = max(x - 2, 0) / kDetectTX, c1 = min(x + 2, W - 1) / kDetectTX;
+        const int tx = (W + kSumTX - 1) / kSumTX;
+        const int r0 = max(y - 2, 0) / kSumTY, r1 = min(y + 2, H - 1) / kSumTY;
+        const int c0 = max(x - 2, 0) / kSumTX, c1 = min(x + 2, W - 1) / kSumTX;
         const unsigned int *t = f.tile_new, uk = (unsigned int)k;
         if (t[r0 * tx + c0] != uk && t[r0 * tx + c1] != uk && t[r1 * tx + c0] != uk &&
             t[r1 * tx + c1] != uk)
@@ -362,38 +404,12 @@ __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p, int k
             v[(dy + 2) * 5 + dx + 2] = f.J[q];
         }
     }
-    const float old = v[12];
-    int cnt = 0;
+    uint32_t fl = 0u;
 #pragma unroll
-    for (int j = 0; j < 25; ++j) {
-        const bool m = mk[j] != 0;
-        v[j] = m ? INFINITY : v[j];
-        cnt += m ? 0 : 1;
-    }
-    if (cnt == 0)
-        return;
-    sort25(v);
-    const int ia = (cnt - 1) >> 1, ib = cnt >> 1;
-    float a = v[0], b = v[0];
-#pragma unroll
-    for (int j = 1; j < 25; ++j) {
-        a = (j == ia) ? v[j] : a;
-        b = (j == ib) ? v[j] : b;
-    }
-    const float nv = (ia == ib) ? a : (float)(((double)a + (double)b) * 0.5);
-    f.J[p] = nv;
-    // incremental detection: a new value dirties every detection tile within
-    // Chebyshev distance 4 (the reach of a code into J)
-    if ((f.flags & kIncremental) && __float_as_uint(nv) != __float_as_uint(old)) {
-        const int tx = (W + kDetectTX - 1) / kDetectTX;
-        const int ty0 = max(y - 4, 0) / kDetectTY, ty1 = min(y + 4, H - 1) / kDetectTY;
-        const int tx0 = max(x - 4, 0) / kDetectTX, tx1 = min(x + 4, W - 1) / kDetectTX;
-        for (int a = ty0; a <= ty1; ++a)
-            for (int b = tx0; b <= tx1; ++b)
-                f.dirty[a * tx + b] = 1;
-    }
+    for (int j = 0; j < 25; ++j)
+        fl |= mk[j] != 0 ? 1u << j : 0u;
+    replace_from_window(f, y, x, v, fl, k);
 }
-
 __global__ __launch_bounds__(kThreads) void k_list_prefix(const DevFrame *__restrict__ frames,
                                                           int nframes, int kiter,
                                                           unsigned int *__restrict__ prefix) {
@@ -476,14 +492,282 @@ __global__ __launch_bounds__(kThreads) void k_replace(const DevFrame *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// fused grow + count + replacement (one launch per iteration)
+// ---------------------------------------------------------------------------
+//
+// A wave takes a strip of TYG rows and 992 columns, as the grow does, and also computes
+// G2 and M_k on the two rows above and the two below it (its mask halo, owned and written
+// by the neighbouring strips): the codes it reads reach 4 rows beyond the strip, the
+// mask 2.  M_k and G2 of those TYG + 4 rows go to the wave's part of the LDS as 16 bits
+// per lane and row.  The wave then replaces the pixels of its own rows that need it, 64 at
+// a time from a compacted list: at iteration 1 every pixel of M_k; later the pixels of M_k
+// with a pixel of G2 within Chebyshev distance 2 (a superset of those with a new flag
+// within 2, the only ones whose replacement can differ from the value they hold).
+// No flagged list, list prefix or separate replacement launch is needed.
+//
+// The halo's mask may be read while its owner writes it: a halo pixel q has M_k(q) =
+// M_{k-1}(q) | G2(q), and the owner only adds G2(q) to M_{k-1}(q), so whether the wave
+// reads M_{k-1}(q) or M_k(q) the OR is M_k(q).  The replacement reads J only at pixels
+// outside M_k, which no wave writes in this launch.
+
+constexpr int kFusedList = 128;      // candidates per round of a wave's replacement
+
+// Whether a strip of rows y0 .. y0+TYG-1 and columns x0 .. x0+kGrowTX-1 has a pixel of A
+// within Chebyshev distance R (R <= 4), from the detection's summary bytes (8 rows each;
+// a reach that meets a summary tile only in its first or last two rows tests those).
+// Called by a whole wave.
+template <int TYG, int R>
+__device__ __forceinline__ bool strip_near_first_r(const DevFrame &f, int y0, int x0, int lane) {
+    static_assert(R <= 4 && TYG <= kSumTY && kSumTY % TYG == 0 &&
+                      3 * ((kGrowTX + 2 * R - 1) / kSumTX + 2) <= 64,
+                  "one lane per summary tile within reach");
+    const int H = f.H, W = f.W;
+    const int ylo = max(y0 - R, 0), yhi = min(y0 + TYG - 1 + R, H - 1);
+    const int xlo = max(x0 - R, 0), xhi = min(x0 + kGrowTX - 1 + R, W - 1);
+    const int r0 = ylo / kSumTY, c0 = xlo / kSumTX;
+    const int ncol = xhi / kSumTX - c0 + 1;
+    bool hit = false;
+    if (lane < (yhi / kSumTY - r0 + 1) * ncol) {
+        const int r = r0 + lane / ncol, c = c0 + lane % ncol, top = r * kSumTY;
+        const int lo = max(ylo, top) - top, hi = min(yhi, top + kSumTY - 1) - top;
+        const uint32_t q = reinterpret_cast<const uint32_t *>(f.tile_first)
+                               [r * ((W + kSumTX - 1) / kSumTX) + c];
+        if (hi <= 1)
+            hit = ((q & 0xFFu) & 2u) != 0u;                 // rows 0-1 of the tile
+        else if (lo >= kSumTY - 2)
+            hit = (((q >> 24) & 0xFFu) & 4u) != 0u;         // rows 30-31
+        else
+            for (int b = lo >> 3; b <= hi >> 3; ++b)       // bytes of 8 rows
+                hit |= ((q >> (8 * b)) & 1u) != 0u;
+    }
+    return __ballot(hit) != 0ull;
+}
+
+// LDS of one wave of the fused kernel: M_k and G2 for rows y0-2 .. y0+TYG+1, 16 bits per
+// lane and row (bit b of lane l: pixel x0 - 16 + 16 l + b), and the candidate list.
+template <int TYG>
+struct FusedLds {
+    uint16_t m[(TYG + 4) * 64];
+    uint16_t g[(TYG + 4) * 64];
+    uint32_t list[kFusedList];
+};
+
+// The wave's LDS writes visible to all of its lanes before they are read.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// 16 flag bytes (bit 0 of each) -> 16 bits
+__device__ __forceinline__ uint32_t squeeze16(const Px16 &v) {
+    return squeeze4(v.d[0]) | (squeeze4(v.d[1]) << 4) | (squeeze4(v.d[2]) << 8) |
+           (squeeze4(v.d[3]) << 12);
+}
+
+template <int TYG, bool ALIGNED>
+__device__ __forceinline__ void grow_replace_strip(const DevFrame &f, int y0, int x0, int k,
+                                                   int lane, FusedLds<TYG> &sh) {
+    constexpr int kAhead = 4;
+    constexpr int NR = TYG + 8;                 // code rows streamed: y0-4 .. y0+TYG+3
+    const int H = f.H, W = f.W;
+    const bool fresh = k == 1 && (f.flags & kFreshMask);
+    const int px = x0 - 16 + 16 * lane;
+    const bool owner = lane >= 1 && lane <= kGrowTX / 16 && px < W;
+    // a candidate needs a pixel of G2 within 2 pixels (or, at iteration 1, is one), and
+    // G2 lies within 2 of A: no A within 4 of the strip means nothing to do
+    if ((k >= 2 || fresh) && f.tile_first && !strip_near_first_r<TYG, 4>(f, y0, x0, lane))
+        return;
+
+    Px16 hA0 = {}, hA1 = {}, hi1 = {}, lo1 = {}, lo2 = {}, hG0 = {}, hG1 = {};
+    unsigned int nnew = 0;
+    Px16 cring[kAhead];
+    if constexpr (ALIGNED) {
+#pragma unroll
+        for (int t = 0; t < kAhead; ++t)
+            cring[t] = load16_aligned(f.codes, y0 - 4 + t, px, H, W);
+    }
+#pragma unroll
+    for (int t = 0; t < NR; ++t) {
+        const int y = y0 - 4 + t;
+        Px16 c;
+        if constexpr (ALIGNED) {
+            c = cring[t % kAhead];
+            if (t + kAhead < NR)
+                cring[t % kAhead] = load16_aligned(f.codes, y + kAhead, px, H, W);
+        } else {
+            c = load16(f.codes, y, px, H, W, false);
+        }
+        Px16 a, hi2, lo0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a.d[q] = c.d[q] & kByteLsb;
+            hi2.d[q] = (c.d[q] >> 1) & kByteLsb;
+            lo0.d[q] = (c.d[q] >> 2) & kByteLsb;
+        }
+        const Px16 hA2 = hdilate(a);
+        Px16 g1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            g1.d[q] = (hA0.d[q] | hA1.d[q] | hA2.d[q]) & hi1.d[q];
+        const Px16 hG2 = hdilate(g1);
+        if (t >= 4) {
+            const int r = t - 6;                        // output row y0 + r == y - 2
+            const int yr = y - 2;
+            Px16 g2;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                g2.d[q] = (hG0.d[q] | hG1.d[q] | hG2.d[q]) & lo2.d[q];
+            Px16 mp = {};
+            if (!fresh) {
+                if constexpr (ALIGNED)
+                    mp = load16_aligned(f.mask, yr, px, H, W);
+                else
+                    mp = load16(f.mask, yr, px, H, W, false);
+            }
+            Px16 m;
+            uint32_t anynew = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t nw = g2.d[q] & ~mp.d[q];
+                m.d[q] = mp.d[q] | g2.d[q];
+                anynew |= nw;
+                if (r >= 0 && r < TYG)
+                    nnew += owner && yr < H ? (unsigned int)__popc(nw) : 0u;
+            }
+            if (r >= 0 && r < TYG && owner && yr < H && anynew)
+                store16(f.mask, yr, px, W, ALIGNED, m);
+            sh.m[(r + 2) * 64 + lane] = (uint16_t)squeeze16(m);
+            sh.g[(r + 2) * 64 + lane] = (uint16_t)squeeze16(g2);
+        }
+        hA0 = hA1; hA1 = hA2;
+        lo2 = lo1; lo1 = lo0;
+        hi1 = hi2;
+        hG0 = hG1; hG1 = hG2;
+    }
+    const unsigned int tn = __ockl_wfred_add_u32(nnew);
+    if (tn && lane == 0)
+        atomicAdd(&f.nnew[k - 1], (unsigned long long)tn);
+    wave_lds_sync();
+
+    // candidates of the owned rows, 16 bits per lane and row
+    uint32_t cbits[(TYG + 1) / 2];
+    unsigned int ncand = 0;
+#pragma unroll
+    for (int r = 0; r < TYG; ++r) {
+        uint32_t c16 = owner && y0 + r < H ? (uint32_t)sh.m[(r + 2) * 64 + lane] : 0u;
+        if (k >= 2) {
+            uint32_t v = 0u, vp = 0u, vn = 0u;           // G2 of rows r-2 .. r+2
+#pragma unroll
+            for (int d = 0; d <= 4; ++d) {
+                v |= sh.g[(r + d) * 64 + lane];
+                vp |= sh.g[(r + d) * 64 + (lane > 0 ? lane - 1 : 0)];
+                vn |= sh.g[(r + d) * 64 + (lane < 63 ? lane + 1 : 63)];
+            }
+            const uint32_t d5 = (v | (v << 1) | (v << 2) | (v >> 1) | (v >> 2) | (vp >> 14) |
+                                 (vp >> 15) | (vn << 15) | (vn << 14)) & 0xFFFFu;
+            c16 &= d5;
+        }
+        if (r & 1)
+            cbits[r >> 1] |= c16 << 16;
+        else
+            cbits[r >> 1] = c16;
+        ncand += (unsigned int)__popc(c16);
+    }
+    const unsigned int incl = wave_incl_scan(ncand, lane);
+    const unsigned int total = (unsigned int)__builtin_amdgcn_readlane((int)incl, 63);
+    const unsigned int excl = incl - ncand;
+    for (unsigned int base = 0; base < total; base += kFusedList) {
+        // this round's candidates: the lanes' entries base .. base + kFusedList - 1
+        unsigned int at = excl;
+#pragma unroll
+        for (int r = 0; r < TYG; ++r) {
+            uint32_t c16 = (cbits[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
+            while (c16) {
+                const int b = __ffs(c16) - 1;
+                if (at >= base && at < base + kFusedList)
+                    sh.list[at - base] = ((uint32_t)r << 10) | (uint32_t)(16 * lane + b);
+                ++at;
+                c16 &= c16 - 1u;
+            }
+        }
+        wave_lds_sync();
+        const unsigned int nround = min(total - base, (unsigned int)kFusedList);
+        for (unsigned int e = (unsigned int)lane; e < nround; e += 64) {
+            const uint32_t ent = sh.list[e];
+            const int r = (int)(ent >> 10), cx = (int)(ent & 1023u);
+            const int y = y0 + r, x = x0 - 16 + cx;
+            float v[25];
+            uint32_t fl = 0u;
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy) {
+                const int yy = clampi(y + dy, H);
+                const uint16_t *mrow = &sh.m[(yy - y0 + 2) * 64];
+                const size_t row = (size_t)yy * W;
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx) {
+                    const int xx = clampi(x + dx, W);
+                    const int c = xx - (x0 - 16);
+                    v[(dy + 2) * 5 + dx + 2] = f.J[row + xx];
+                    fl |= ((mrow[c >> 4] >> (c & 15)) & 1u) << ((dy + 2) * 5 + dx + 2);
+                }
+            }
+            replace_from_window(f, y, x, v, fl, k);
+        }
+        wave_lds_sync();       // the list is rewritten in the next round
+    }
+}
+
+template <int TYG>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_grow_replace(
+    const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles, DevFrame single,
+    int kiter, int ntiles) {
+    __shared__ FusedLds<TYG> sLds[kThreads / 64];
+    const int lane = threadIdx.x & 63;
+    const int wt = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (wt >= ntiles)
+        return;
+    DevFrame f;
+    int y0, x0;
+    if (tiles) {
+        constexpr int kSub = kGrowTY / TYG;
+        const TileRef t = tiles[wt / kSub];
+        f = frames[t.frame];
+        y0 = t.y0 + (wt % kSub) * TYG;
+        x0 = t.x0;
+        if (y0 >= f.H)
+            return;
+    } else {
+        f = single;
+        const int ntx = (f.W + kGrowTX - 1) / kGrowTX;
+        y0 = (wt / ntx) * TYG;
+        x0 = (wt % ntx) * kGrowTX;
+    }
+    const int k = kiter ? kiter : f.k;
+    if (frame_skips(f, k))
+        return;
+    FusedLds<TYG> &sh = sLds[threadIdx.x >> 6];
+    if ((f.W & 15) == 0)
+        grow_replace_strip<TYG, true>(f, y0, x0, k, lane, sh);
+    else
+        grow_replace_strip<TYG, false>(f, y0, x0, k, lane, sh);
+}
+
+// ---------------------------------------------------------------------------
 // init and stats
 // ---------------------------------------------------------------------------
 
 // Grid rows (blockIdx.y) take the frames in turn.
 __global__ __launch_bounds__(kThreads) void k_init(const DevFrame *__restrict__ frames,
-                                                   int nframes, DevFrame single) {
+                                                   int nframes, DevFrame single,
+                                                   unsigned int *__restrict__ tickets,
+                                                   int nticket) {
     const size_t gid = (size_t)blockIdx.x * kThreads + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * kThreads;
+    // the persistent launches' ticket counters start at zero on every run
+    if (tickets && blockIdx.y == 0)
+        for (size_t i = gid; i < (size_t)nticket; i += stride)
+            tickets[i] = 0u;
     const int nf = frames ? nframes : 1;
     for (int fi = blockIdx.y; fi < nf; fi += gridDim.y) {
         const DevFrame f = frames ? frames[fi] : single;
@@ -590,11 +874,13 @@ static unsigned int grid_for(size_t items, unsigned int cap) {
 }
 
 hipError_t launch_init(const DevFrame *d_frames, int nframes, const DevFrame &single,
-                       size_t max_pixels, hipStream_t s) {
+                       size_t max_pixels, unsigned int *tickets, int nticket, hipStream_t s) {
     const int rows = d_frames ? (nframes < 65535 ? nframes : 65535) : 1;
     const unsigned int cap = 4096u / (unsigned int)rows > 16u ? 4096u / (unsigned int)rows : 16u;
-    const unsigned int gx = grid_for(max_pixels > (size_t)kMaxIter ? max_pixels : kMaxIter, cap);
-    k_init<<<dim3(gx, rows), kThreads, 0, s>>>(d_frames, nframes, single);
+    size_t items = max_pixels > (size_t)kMaxIter ? max_pixels : (size_t)kMaxIter;
+    items = items > (size_t)nticket ? items : (size_t)nticket;
+    const unsigned int gx = grid_for(items, cap);
+    k_init<<<dim3(gx, rows), kThreads, 0, s>>>(d_frames, nframes, single, tickets, nticket);
     return hipGetLastError();
 }
 
@@ -604,35 +890,52 @@ hipError_t launch_list_prefix(const DevFrame *d_frames, int nframes, int k,
     return hipGetLastError();
 }
 
+// Strip height of a grow launch: the configured first-iteration height (default: 32 rows
+// for batches and frames of 2^22 pixels or more, 8 below), 8 rows after iteration 1,
+// where few strips are near A and each runs alone, so a shorter row chain is waited on.
+static int grow_height(bool batch, const DevFrame &single, int k, const LaunchCfg &cfg) {
+    if (k >= 2)
+        return kGrowTYSmall;
+    if (cfg.grow_h)
+        return cfg.grow_h;
+    if (batch)
+        return kGrowTY;
+    return (size_t)single.H * single.W < ((size_t)1 << 22) ? kGrowTYSmall : kGrowTY;
+}
+
 hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
-                       const DevFrame &single, int k, hipStream_t s) {
+                       const DevFrame &single, int k, const LaunchCfg &cfg, hipStream_t s) {
     constexpr int wpb = kThreads / 64;
-    if (d_tiles) {
-        if (ntiles <= 0)
-            return hipSuccess;
-        if (k >= 2) {
-            // after iteration 1 few strips are near A and each runs alone: a wave per
-            // 8-row part of a listed strip shortens the row chain it waits on
-            const int n = ntiles * (kGrowTY / kGrowTYSmall);
-            k_grow<kGrowTYSmall><<<(n + wpb - 1) / wpb, kThreads, 0, s>>>(d_frames, d_tiles,
-                                                                           single, k, n);
-        } else {
-            k_grow<kGrowTY><<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(d_frames, d_tiles,
-                                                                           single, k, ntiles);
-        }
-        return hipGetLastError();
-    }
-    // a single frame: short strips when the frame is small, so more waves share it, and
-    // after iteration 1
-    const bool small = k >= 2 || (size_t)single.H * single.W < ((size_t)1 << 22);
-    const int ty = small ? kGrowTYSmall : kGrowTY;
-    ntiles = ((single.W + kGrowTX - 1) / kGrowTX) * ((single.H + ty - 1) / ty);
-    if (small)
-        k_grow<kGrowTYSmall><<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(nullptr, nullptr,
-                                                                            single, k, ntiles);
+    if (d_tiles && ntiles <= 0)
+        return hipSuccess;
+    // serving launches (k == 0) mix iterations: the first-iteration height for all.  The
+    // fused kernel runs 8-row strips (taller ones would hold their rows in registers
+    // beyond the 168 a wave may have at 3 waves per SIMD).
+    const bool fused = cfg.fused && !single.g2;
+    const int ty = fused ? kGrowTYSmall : grow_height(d_tiles != nullptr, single, k, cfg);
+    int n;
+    if (d_tiles)
+        n = ntiles * (kGrowTY / ty);          // a listed 32-row strip splits into kGrowTY / ty
     else
-        k_grow<kGrowTY><<<(ntiles + wpb - 1) / wpb, kThreads, 0, s>>>(nullptr, nullptr, single,
-                                                                       k, ntiles);
+        n = ((single.W + kGrowTX - 1) / kGrowTX) * ((single.H + ty - 1) / ty);
+    const unsigned int grid = (unsigned int)((n + wpb - 1) / wpb);
+    if (fused) {
+        k_grow_replace<kGrowTYSmall><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+    } else {
+        switch (ty) {
+        case 8:
+            k_grow<8><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            break;
+        case 16:
+            k_grow<16><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            break;
+        case 32:
+            k_grow<32><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
+    }
     return hipGetLastError();
 }
 

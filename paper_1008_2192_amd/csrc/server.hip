@@ -334,7 +334,7 @@ static crb_status launch_round(crb_server *s) {
         return CRB_OK;
     size_t ntd = 0, ntg = 0, pix = 0;
     for (Request *r : s->active) {
-        ntd += (size_t)((r->H + kDetectTY - 1) / kDetectTY) * ((r->W + kDetectTX - 1) / kDetectTX);
+        ntd += (size_t)detect_tiles(r->H, r->W, kDetectTYDefault);
         ntg += (size_t)((r->H + kGrowTY - 1) / kGrowTY) * ((r->W + kGrowTX - 1) / kGrowTX);
         pix += (size_t)r->H * r->W;
     }
@@ -354,7 +354,7 @@ static crb_status launch_round(crb_server *s) {
         Request *r = s->active[i];
         hf[i] = r->df;
         hf[i].k = r->k_next;
-        for (int y = 0; y < r->H; y += kDetectTY)
+        for (int y = 0; y < r->H; y += kDetectTYDefault)
             for (int x = 0; x < r->W; x += kDetectTX)
                 htd[itd++] = TileRef{i, y, x, 0};
         for (int y = 0; y < r->H; y += kGrowTY)
@@ -375,12 +375,15 @@ static crb_status launch_round(crb_server *s) {
     DevFrame none;
     memset(&none, 0, sizeof(none));
     hipError_t e = hipMemcpyAsync(s->d_tab, s->h_tab, o_pre, hipMemcpyHostToDevice, s->compute);
+    // rounds mix frames at different iterations: the default launch shapes (one block per
+    // 32 x 64 detection tile, separate grow, list prefix and replacement)
+    const LaunchCfg cfg;
     if (e == hipSuccess)
-        e = launch_init(dfr, n, none, (size_t)kMaxIter, s->compute);
+        e = launch_init(dfr, n, none, (size_t)kMaxIter, nullptr, 0, s->compute);
     if (e == hipSuccess)
-        e = launch_detect(dfr, dtd, (int)ntd, none, 0, s->compute);
+        e = launch_detect(dfr, dtd, (int)ntd, none, 0, cfg, nullptr, s->compute);
     if (e == hipSuccess)
-        e = launch_grow(dfr, dtg, (int)ntg, none, 0, s->compute);
+        e = launch_grow(dfr, dtg, (int)ntg, none, 0, cfg, s->compute);
     if (e == hipSuccess)
         e = launch_list_prefix(dfr, n, 0, dpre, s->compute);
     if (e == hipSuccess)
@@ -404,7 +407,7 @@ static crb_status finish_round(crb_server *s) {
     const int n = (int)s->round_members.size();
     size_t ntd = 0, ntg = 0;
     for (Request *r : s->round_members) {
-        ntd += (size_t)((r->H + kDetectTY - 1) / kDetectTY) * ((r->W + kDetectTX - 1) / kDetectTX);
+        ntd += (size_t)detect_tiles(r->H, r->W, kDetectTYDefault);
         ntg += (size_t)((r->H + kGrowTY - 1) / kGrowTY) * ((r->W + kGrowTX - 1) / kGrowTX);
     }
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };

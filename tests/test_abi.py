@@ -175,6 +175,38 @@ def test_counting_and_debug_entry_validation(L):
     assert L.crb_set_option(_lib.CRB_OPT_INCREMENTAL, 0) == 0
 
 
+def prototypes():
+    """{name: [parameter type strings]} of the functions include/crb.h declares."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    text = re.sub(r"#[^\n]*", "", text)
+    out = {}
+    for m in re.finditer(r"\b(crb_[a-z0-9_]+)\s*\(([^;{)]*)\)\s*;", text):
+        params = [re.sub(r"\s+", " ", p).strip() for p in m.group(2).split(",")]
+        out[m.group(1)] = [re.sub(r"\s*\b[a-zA-Z_][a-zA-Z0-9_]*$", "", p).replace(" *", "*")
+                           for p in params if p and p != "void"]
+    return out
+
+
+def test_boundary_signatures():
+    """The calls the boundary is specified by keep their argument lists: crb_lacosmic
+    with the (img, H, W, gain, readnoise, sky, sigclip, sigfrac, objlim, niter,
+    out_clean, out_mask) signature, the batched variant over crb_frame records on a
+    stream, the stream, error and workspace queries, and the teacher-forced iteration
+    with H and W as arguments."""
+    P = prototypes()
+    f32, i32 = "float", "int32_t"
+    assert P["crb_lacosmic"] == ["const float*", i32, i32, f32, f32, f32, f32, f32, f32, i32,
+                                 "float*", "uint8_t*"]
+    assert P["crb_lacosmic_noalloc"] == P["crb_lacosmic"]
+    assert P["crb_lacosmic_batched"] == ["crb_frame*", i32, "void*"]
+    assert P["crb_set_stream"] == ["void*"]
+    assert P["crb_last_error"] == []
+    assert P["crb_workspace_bytes"] == [i32, i32]
+    assert P["crb_debug_iterate"] == ["const float*", "const uint8_t*", i32, i32,
+                                      "const crb_frame*", "uint8_t*", "uint8_t*", "float*",
+                                      "int64_t*"]
+
+
 def test_noalloc_rejects_oversized_frames_on_host(L):
     """A frame whose workspace exceeds the fixed scratch is refused before any device
     work (the pointers are never dereferenced)."""
