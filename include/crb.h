@@ -365,12 +365,15 @@ crb_status crb_release_workspace(void *hip_stream);
  * for every admitted frame, so frames at different iterations share the GPU.
  * Frames leave after niter iterations or an early stop; their results are copied
  * to the caller's host buffers and a completion is reported.
- *   crb_server_submit: host FP32 image, read when the request is admitted (it must
- *     stay valid and unchanged until the request completes), host outputs written
- *     at completion; returns CRB_EBUSY when the request can never fit the budget.
- *     Requests wait in FIFO order until slots and memory allow.  When the image and
- *     both outputs are page-locked host memory (hipHostMalloc) they are transferred
- *     directly; otherwise they pass through the server's pinned staging buffers.
+ *   crb_server_submit: FP32 image, read when the request is admitted (it must stay
+ *     valid and unchanged until the request completes), outputs written at
+ *     completion; returns CRB_EBUSY when the request can never fit the budget.
+ *     Requests wait in FIFO order until slots and memory allow.  The image and both
+ *     outputs are all host memory or all device memory of the server's device
+ *     (CRB_EINVAL otherwise).  Device buffers are copied on the device (the caller
+ *     makes the input ready before submitting, e.g. by synchronizing its stream);
+ *     page-locked host buffers (hipHostMalloc) are transferred directly; pageable ones
+ *     pass through the server's pinned staging buffers.
  *   crb_server_poll: enqueue the next round when the previous one has finished,
  *     admit waiting requests, retire finished frames; never blocks.  Writes up to
  *     max_done completed request ids to done_ids and their latency (seconds from
@@ -426,6 +429,11 @@ crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, fl
 /* Clamped 5x5 median filter of binary64 values by the single-output network that the
  * detection applies to its FP32 estimates of S (here on binary64 inputs). */
 crb_status crb_debug_median5_f64(const double *in, int32_t H, int32_t W, double *out);
+/* Copy n FP32 elements (device, no overlap) by 4-byte buffer loads and stores, the
+ * access width with which the detection stages J: a kernel of known traffic (4n bytes
+ * read, 4n written) that calibrates the HBM byte counters for that width.  Runs on the
+ * calling thread's stream. */
+crb_status crb_debug_copy_b32(const float *src, float *dst, int64_t n);
 /* Elementwise binary64 sqrt(x) and x / y on the device (rounding checks). */
 crb_status crb_debug_fp64(const double *x, const double *y, int32_t n, double *out_sqrt,
                           double *out_div);

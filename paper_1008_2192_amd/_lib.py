@@ -33,7 +33,7 @@ EXPORTS = ["crb_lacosmic", "crb_lacosmic_noalloc", "crb_lacosmic_batched", "crb_
            "crb_debug_fp64", "crb_work_run", "crb_work_radius", "crb_farm_run",
            "crb_plan_set_counting", "crb_plan_work_counts", "crb_debug_median5_f64",
            "crb_debug_detect_exact", "crb_debug_s_estimate", "crb_plan_set_tuning",
-           "crb_plan_get_tuning", "crb_plan_autotune"]
+           "crb_plan_get_tuning", "crb_plan_autotune", "crb_debug_copy_b32"]
 CRB_WORK_LACOSMIC = 0
 CRB_WORK_POISSON = 1
 CRB_WORK_WAITER = 2
@@ -137,6 +137,7 @@ def lib():
     L.crb_debug_s_estimate.argtypes = [vp, ctypes.POINTER(Frame), vp, vp]
     L.crb_debug_median.argtypes = [vp, i32, i32, i32, vp]
     L.crb_debug_fp64.argtypes = [vp, vp, i32, vp, vp]
+    L.crb_debug_copy_b32.argtypes = [vp, vp, i64]
     L.crb_work_run.argtypes = [i32, vp, i32, i32, ctypes.c_uint64, i32, i32, vp]
     L.crb_work_radius.argtypes = [ctypes.POINTER(Work)]
     L.crb_work_radius.restype = i32
@@ -148,7 +149,8 @@ def lib():
                  "crb_debug_iterate", "crb_debug_detect", "crb_debug_median", "crb_debug_fp64",
                  "crb_work_run", "crb_farm_run", "crb_plan_set_counting", "crb_plan_work_counts",
                  "crb_debug_median5_f64", "crb_debug_detect_exact", "crb_debug_s_estimate",
-                 "crb_plan_set_tuning", "crb_plan_get_tuning", "crb_plan_autotune"):
+                 "crb_plan_set_tuning", "crb_plan_get_tuning", "crb_plan_autotune",
+                 "crb_debug_copy_b32"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -448,6 +450,19 @@ def debug_fp64(x: torch.Tensor, y: torch.Tensor, stream: Optional[torch.cuda.Str
     check("crb_debug_fp64", lib().crb_debug_fp64(x.data_ptr(), y.data_ptr(), x.numel(),
                                                  s.data_ptr(), d.data_ptr()))
     return s, d
+
+
+def debug_copy_b32(src: torch.Tensor, dst: torch.Tensor,
+                   stream: Optional[torch.cuda.Stream] = None) -> None:
+    """crb_debug_copy_b32: dst = src (float32, contiguous, same size) by 4-byte buffer
+    loads and stores (HBM counter calibration)."""
+    if src.dtype != torch.float32 or dst.dtype != torch.float32 or not src.is_cuda or \
+            not dst.is_cuda or not src.is_contiguous() or not dst.is_contiguous() or \
+            src.numel() != dst.numel():
+        raise ValueError("src and dst must be contiguous float32 CUDA tensors of one size")
+    set_stream(stream)
+    check("crb_debug_copy_b32", lib().crb_debug_copy_b32(src.data_ptr(), dst.data_ptr(),
+                                                         src.numel()))
 
 
 def workspace_bytes(H: int, W: int) -> int:

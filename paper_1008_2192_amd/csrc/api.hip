@@ -636,6 +636,16 @@ crb_status crb_debug_median5_f64(const double *in, int32_t H, int32_t W, double 
     return st == CRB_OK ? ok() : st;
 }
 
+crb_status crb_debug_copy_b32(const float *src, float *dst, int64_t n) {
+    if (!src || !dst || n < 0)
+        return fail(CRB_EINVAL, "bad arguments");
+    if (ranges_overlap(src, (size_t)n * 4, dst, (size_t)n * 4))
+        return fail(CRB_EINVAL, "src and dst overlap");
+    crb_status st = hip_status(launch_debug_copy_b32(src, dst, (long long)n, t_stream),
+                               "kernel launch");
+    return st == CRB_OK ? ok() : st;
+}
+
 crb_status crb_debug_fp64(const double *x, const double *y, int32_t n, double *out_sqrt,
                           double *out_div) {
     if (!x || !y || !out_sqrt || !out_div || n < 0)
@@ -677,7 +687,7 @@ struct crb_plan {
     long long *d_stats = nullptr;
     unsigned int *d_prefix = nullptr;   // flat offsets of the frames' flagged lists
     unsigned long long *d_work = nullptr;   // per frame: kWorkCounters detection counters
-    unsigned int *d_tickets = nullptr;  // kDetectQueues per iteration (persistent detection)
+    unsigned int *d_tickets = nullptr;  // kTicketWords per iteration (persistent detection)
     std::vector<DevFrame> hframes;      // host copy of the frame table
     std::string key;                    // tune-cache key of the batch layout
     crb::LaunchCfg cfg;                 // launch shapes of crb_plan_run
@@ -731,16 +741,43 @@ static crb_status plan_enqueue(crb_plan *p) {
     const int ti = tile_h_index(cfg.tile_h);
     if (ti < 0)
         return fail(CRB_EINVAL, "detection tile height %d", cfg.tile_h);
+    // A plan of one frame passes the frame by value to one-block-per-tile and per-strip
+    // grids, as crb_lacosmic does (no work-list lookups, no list prefix), unless its
+    // detection is persistent, which needs the tile list.
+    if (p->n == 1 && !cfg.persistent) {
+        const DevFrame &f = p->hframes[0];
+        const size_t npix = (size_t)f.H * (size_t)f.W;
+        hipError_t e = tmark_begin(p, kKindInit);
+        if (e == hipSuccess)
+            e = launch_init(nullptr, 1, f, p->init_pix, nullptr, 0, s);
+        if (e == hipSuccess)
+            e = tmark_end(p);
+        for (int k = 1; e == hipSuccess && k <= p->kmax; ++k) {
+            if ((e = tmark_begin(p, kKindDetect)) == hipSuccess &&
+                (e = launch_detect(nullptr, nullptr, 0, f, k, cfg, nullptr, s)) == hipSuccess &&
+                (e = tmark_end(p)) == hipSuccess &&
+                (e = tmark_begin(p, kKindGrow)) == hipSuccess &&
+                (e = launch_grow(nullptr, nullptr, 0, f, k, cfg, s)) == hipSuccess &&
+                (e = tmark_end(p)) == hipSuccess && !cfg.fused &&
+                (e = tmark_begin(p, kKindReplace)) == hipSuccess &&
+                (e = launch_replace(nullptr, 1, nullptr, f, k, replace_grid(npix), s)) ==
+                    hipSuccess)
+                e = tmark_end(p);
+        }
+        if (e == hipSuccess)
+            e = launch_stats(p->d_frames, p->n, p->d_stats, s);
+        return hip_status(e, "kernel launch");
+    }
     hipError_t e = tmark_begin(p, kKindInit);
     if (e == hipSuccess)
         e = launch_init(p->d_frames, p->n, none, p->init_pix, p->d_tickets,
-                        p->kmax * kDetectQueues, s);
+                        p->kmax * kTicketWords, s);
     if (e == hipSuccess)
         e = tmark_end(p);
     for (int k = 1; e == hipSuccess && k <= p->kmax; ++k) {
         if ((e = tmark_begin(p, kKindDetect)) == hipSuccess &&
             (e = launch_detect(p->d_frames, p->d_tdet[ti], p->ntdet[ti], none, k, cfg,
-                               p->d_tickets + (size_t)(k - 1) * kDetectQueues, s)) ==
+                               p->d_tickets + (size_t)(k - 1) * kTicketWords, s)) ==
                 hipSuccess &&
             (e = tmark_end(p)) == hipSuccess &&
             (e = tmark_begin(p, kKindGrow)) == hipSuccess &&
@@ -1016,7 +1053,7 @@ crb_status crb_plan_create(const crb_frame *frames, int32_t n, void *hip_stream,
     const size_t o_prefix = o_stats + al(2 * n * sizeof(long long));
     const size_t o_work = o_prefix + al((n + 1) * sizeof(unsigned int));
     const size_t o_tickets = o_work + al(kWorkCounters * n * sizeof(unsigned long long));
-    const size_t bytes = o_tickets + al((size_t)(kmax > 0 ? kmax : 1) * kDetectQueues * 4);
+    const size_t bytes = o_tickets + al((size_t)(kmax > 0 ? kmax : 1) * kTicketWords * 4);
 
     crb_plan *p = new (std::nothrow) crb_plan();
     if (!p)
@@ -1287,6 +1324,12 @@ crb_status crb_plan_set_counting(crb_plan *p, int32_t enable) {
     if (e != hipSuccess)
         return hip_status(e, "counter setup");
     p->counting = enable != 0;
+    // a one-frame plan passes its frame by value: its graph holds the old flags
+    if (p->use_graph && p->n == 1) {
+        crb_status st = plan_capture(p);
+        if (st != CRB_OK)
+            return st;
+    }
     return ok();
 }
 

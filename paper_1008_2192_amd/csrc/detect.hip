@@ -1033,50 +1033,60 @@ void k_detect(const DevFrame *__restrict__ frames, const TileRef *__restrict__ t
 }
 
 // Persistent blocks over a (frame, tile) work list: the grid holds about as many
-// blocks as are resident at once, and each block takes tiles from kDetectQueues ticket
-// counters (zero at launch), counter q over the q-th contiguous part of the list.  Blocks are dispatched round-robin over
-// the XCDs, so block b starts on part b mod kDetectQueues, and the tiles in flight on
-// one XCD are neighbours sharing halo rows and columns in its L2; a block whose part is
-// used up moves to the next, and it returns once all parts are (every counter only
-// grows, so every block gets there).
+// blocks as are resident at once, and each block takes runs of kRun consecutive tiles
+// from kDetectQueues ticket counters (zero at launch, each on its own cache line),
+// counter q over the q-th contiguous part of the list.  Blocks are dispatched
+// round-robin over the XCDs, so block b starts on part b mod kDetectQueues, and the
+// tiles in flight on one XCD are neighbours sharing halo rows and columns in its L2; a
+// block whose part is used up moves to the next, and it returns once all parts are
+// (every counter only grows, so every block gets there).
 template <int TY>
 __global__ __launch_bounds__(8 * TY) __attribute__((amdgpu_waves_per_eu(TY == 16 ? 4 : 6)))
 void k_detect_persistent(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
                          int kiter, int ntiles, unsigned int *__restrict__ tickets) {
-    __shared__ int sTile;
+    constexpr int kRun = TY == 64 ? 2 : 4;
+    __shared__ int sTile, sEnd;
     int q = (int)(blockIdx.x % kDetectQueues), tried = 0;
     for (;;) {
-        __syncthreads();      // the previous tile is done with the LDS and with sTile
+        __syncthreads();      // the previous run is done with the LDS and with sTile
         if (threadIdx.x == 0) {
-            int t = -1;
+            int t = -1, end = -1;
             while (tried < kDetectQueues) {
                 const unsigned int lo = (unsigned int)((long long)ntiles * q / kDetectQueues);
                 const unsigned int hi =
                     (unsigned int)((long long)ntiles * (q + 1) / kDetectQueues);
-                const unsigned int got = lo + atomicAdd(&tickets[q], 1u);
+                const unsigned int got =
+                    lo + (unsigned int)kRun * atomicAdd(&tickets[q * kTicketStride], 1u);
                 if (got < hi) {
                     t = (int)got;
+                    end = (int)min(got + (unsigned int)kRun, hi);
                     break;
                 }
                 q = (q + 1) % kDetectQueues;
                 ++tried;
             }
             sTile = t;
+            sEnd = end;
         }
         __syncthreads();
         // uniform over the block: the tile and frame records then load into scalar
         // registers, as with blockIdx.x in the one-block-per-tile kernel
-        const int t = __builtin_amdgcn_readfirstlane(sTile);
-        if (t < 0)
+        const int t0 = __builtin_amdgcn_readfirstlane(sTile);
+        const int t1 = __builtin_amdgcn_readfirstlane(sEnd);
+        if (t0 < 0)
             return;
-        const TileRef r = tiles[t];
-        const DevFrame f = frames[r.frame];
-        // the thread index passes through an empty asm statement each round, so that
-        // values derived from it are recomputed per tile rather than held in registers
-        // across the loop
-        int tid = (int)threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        detect_tile<TY>(f, r.y0, r.x0, kiter ? kiter : f.k, tid);
+        for (int t = t0; t < t1; ++t) {
+            if (t > t0)
+                __syncthreads();   // the previous tile is done with the LDS
+            const TileRef r = tiles[t];
+            const DevFrame f = frames[r.frame];
+            // the thread index passes through an empty asm statement each round, so that
+            // values derived from it are recomputed per tile rather than held in registers
+            // across the loop
+            int tid = (int)threadIdx.x;
+            asm volatile("" : "+v"(tid));
+            detect_tile<TY>(f, r.y0, r.x0, kiter ? kiter : f.k, tid);
+        }
     }
 }
 

@@ -17,8 +17,11 @@ constexpr int kDetectTX = 64;
 constexpr int kDetectTYDefault = 32;
 constexpr int kSumTY = 32;
 constexpr int kSumTX = 64;
-// ticket counters of one persistent detection launch (one per XCD)
+// ticket counters of one persistent detection launch (one per XCD), each on its own
+// 128-byte line (kTicketStride words apart) so that the XCDs do not contend for one line
 constexpr int kDetectQueues = 8;
+constexpr int kTicketStride = 32;
+constexpr int kTicketWords = kDetectQueues * kTicketStride;   // per launch
 // Grow tile (outputs per wave: 62 groups of 16 pixels by kGrowTY rows).
 constexpr int kGrowTY = 32;
 constexpr int kGrowTYSmall = 8;     // strip height for single frames below 2^22 pixels and
@@ -105,8 +108,8 @@ struct LaunchCfg {
 };
 
 // Detection (codes) for one frame (d_tiles == null: tiles over `single`) or a work list
-// of (frame, tile) built for cfg.tile_h.  Persistent launches take kDetectQueues zeroed
-// ticket counters.
+// of (frame, tile) built for cfg.tile_h.  Persistent launches take kTicketWords zeroed
+// words of ticket counters.
 hipError_t launch_detect(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
                          const DevFrame &single, int k, const LaunchCfg &cfg,
                          unsigned int *tickets, hipStream_t s);
@@ -157,6 +160,8 @@ hipError_t launch_debug_s_estimate(const DevFrame &f, float *out_s, float *out_e
                                    hipStream_t s);
 hipError_t launch_debug_median5_f64(const double *in, int H, int W, double *out,
                                    hipStream_t s);
+// n FP32 elements copied by 4-byte buffer loads and stores (counter calibration).
+hipError_t launch_debug_copy_b32(const float *src, float *dst, long long n, hipStream_t s);
 hipError_t launch_debug_fp64(const double *x, const double *y, int n, double *out_sqrt,
                              double *out_div, hipStream_t s);
 

@@ -853,6 +853,29 @@ __global__ __launch_bounds__(kThreads) void k_stitch(float *__restrict__ out_cle
 // parity-test kernels: the median networks alone, binary64 sqrt and division
 // ---------------------------------------------------------------------------
 
+// A copy by 4-byte buffer loads and stores, one element per lane in consecutive order
+// (the detection stages J with the same 4-byte buffer loads): its HBM counter readings
+// against its known byte count calibrate the counters for that access width.  Blocks
+// take 2^20-element chunks (each within one buffer resource, below 2^32 bytes).
+__global__ __launch_bounds__(kThreads) void k_debug_copy_b32(const float *__restrict__ src,
+                                                             float *__restrict__ dst,
+                                                             long long n) {
+    constexpr long long kChunk = 1ll << 20;
+    const long long nchunks = (n + kChunk - 1) / kChunk;
+    for (long long c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const long long base = c * kChunk;
+        const long long len = n - base < kChunk ? n - base : kChunk;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(src + base), (short)0, (int)(len * 4), 0x00020000);
+        const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(dst + base), (short)0, (int)(len * 4), 0x00020000);
+        for (int i = threadIdx.x; i < (int)len; i += kThreads) {
+            const unsigned int v = __builtin_amdgcn_raw_buffer_load_b32(rs, i * 4, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(v, rd, i * 4, 0, 0);
+        }
+    }
+}
+
 __global__ void k_debug_fp64(const double *__restrict__ x, const double *__restrict__ y, int n,
                              double *__restrict__ os, double *__restrict__ od) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -968,6 +991,15 @@ hipError_t launch_stitch(float *out_clean, uint8_t *out_mask, int W, const SubRe
                          int nsub, size_t max_pixels, hipStream_t s) {
     dim3 grid(grid_for(max_pixels, 1024), nsub);
     k_stitch<<<grid, kThreads, 0, s>>>(out_clean, out_mask, W, d_subs);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_copy_b32(const float *src, float *dst, long long n, hipStream_t s) {
+    if (n <= 0)
+        return hipSuccess;
+    const long long nchunks = (n + (1ll << 20) - 1) >> 20;
+    k_debug_copy_b32<<<(unsigned int)(nchunks < 4096 ? nchunks : 4096), kThreads, 0, s>>>(src,
+                                                                                        dst, n);
     return hipGetLastError();
 }
 

@@ -119,7 +119,9 @@ struct Request {
     float gain = 0, readnoise = 0, sky = 0, sigclip = 0, sigfrac = 0, objlim = 0;
     int32_t niter = 0;
     const float *host_img = nullptr;   // caller's input, valid until completion
-    bool direct = false;               // caller's buffers are pinned: no staging copies
+    bool direct = false;               // caller's buffers are pinned or on the device:
+                                       // transferred without staging copies
+    bool on_device = false;            // caller's buffers are device memory
     float *host_clean = nullptr;
     uint8_t *host_mask = nullptr;
     double t_submit = 0;
@@ -218,14 +220,20 @@ static crb_status dev_alloc(crb_server *s, size_t bytes, char **out) {
     return CRB_OK;
 }
 
-// true when p is page-locked host memory the device can read and write directly
-static bool is_pinned_host(const void *p) {
+// the kind of memory p points to: 0 pageable host memory (unknown to HIP), 1 page-locked
+// host memory the device can read and write directly, 2 device memory of `device`,
+// -1 another device's memory
+static int memory_kind(const void *p, int device) {
     hipPointerAttribute_t a;
     if (hipPointerGetAttributes(&a, p) != hipSuccess) {
         (void)hipGetLastError();
-        return false;
+        return 0;
     }
-    return a.type == hipMemoryTypeHost;
+    if (a.type == hipMemoryTypeHost)
+        return 1;
+    if (a.type == hipMemoryTypeDevice)
+        return a.device == device ? 2 : -1;
+    return 0;
 }
 
 static size_t frame_dev_bytes(int32_t H, int32_t W) {
@@ -256,7 +264,8 @@ static void release_request(crb_server *s, Request *r) {
 constexpr int kAdmitPerPoll = 4;
 
 static crb_status admit(crb_server *s) {
-    for (int admitted = 0; !s->waiting.empty() && admitted < kAdmitPerPoll; ++admitted) {
+    // a cap on staged admissions only: direct transfers cost the host nothing
+    for (int staged = 0; !s->waiting.empty() && staged < kAdmitPerPoll;) {
         Request *r = s->waiting.front();
         const int held = (int)(s->active.size() + s->draining.size());
         if (held >= s->max_slots || s->in_use + r->dev_bytes > s->budget)
@@ -277,6 +286,7 @@ static crb_status admit(crb_server *s) {
                 return st;
             }
             s->copies->copy(r->pin, r->host_img, 4 * (size_t)r->H * r->W);
+            ++staged;
         }
         const size_t n = (size_t)r->H * (size_t)r->W;
         const size_t img = (4 * n + 255) / 256 * 256;
@@ -289,7 +299,9 @@ static crb_status admit(crb_server *s) {
                               r->gain, r->readnoise, r->sky, r->sigclip, r->sigfrac, r->objlim,
                               r->niter, kFreshMask);
         hipError_t e = hipMemcpyAsync(J, r->direct ? (const void *)r->host_img : r->pin, 4 * n,
-                                      hipMemcpyHostToDevice, s->copy);
+                                      r->on_device ? hipMemcpyDeviceToDevice
+                                                   : hipMemcpyHostToDevice,
+                                      s->copy);
         if (e == hipSuccess)
             e = hipEventRecord(r->ev_h2d, s->copy);
         if (e != hipSuccess)
@@ -432,10 +444,11 @@ static crb_status finish_round(crb_server *s) {
         hipError_t e = hipStreamWaitEvent(s->copy, s->ev_round, 0);
         void *dst_clean = r->direct ? (void *)r->host_clean : (void *)r->pin;
         void *dst_mask = r->direct ? (void *)r->host_mask : (void *)(r->pin + 4 * npx);
+        const hipMemcpyKind kind = r->on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
         if (e == hipSuccess)
-            e = hipMemcpyAsync(dst_clean, r->df.J, 4 * npx, hipMemcpyDeviceToHost, s->copy);
+            e = hipMemcpyAsync(dst_clean, r->df.J, 4 * npx, kind, s->copy);
         if (e == hipSuccess)
-            e = hipMemcpyAsync(dst_mask, r->df.mask, npx, hipMemcpyDeviceToHost, s->copy);
+            e = hipMemcpyAsync(dst_mask, r->df.mask, npx, kind, s->copy);
         if (e == hipSuccess)
             e = hipEventRecord(r->ev_d2h, s->copy);
         if (e != hipSuccess)
@@ -525,14 +538,33 @@ crb_status crb_server_submit(crb_server *s, const float *host_img, int32_t H, in
     }
     r->pin_bytes = 5 * npx;
     r->host_img = host_img;
-    r->direct = is_pinned_host(host_img) && is_pinned_host(host_clean) &&
-                is_pinned_host(host_mask);
-    r->id = s->next_id++;
-    *out_id = r->id;
-    if (niter == 0) {              // nothing to compute: the result is the input
+    const int ki = memory_kind(host_img, s->device), kc = memory_kind(host_clean, s->device),
+              km = memory_kind(host_mask, s->device);
+    if (ki < 0 || kc < 0 || km < 0 || (ki == 2) != (kc == 2) || (ki == 2) != (km == 2)) {
+        delete r;
+        return fail(CRB_EINVAL, "the image and both outputs must all be host memory or all "
+                                "device memory of the server's device");
+    }
+    r->on_device = ki == 2;
+    r->direct = ki > 0 && kc > 0 && km > 0;
+    if (niter == 0 && r->on_device) {
+        // nothing to compute: the result is the input, copied on the device
+        hipError_t e = hipMemcpyAsync(host_clean, host_img, 4 * npx, hipMemcpyDeviceToDevice,
+                                      s->copy);
+        if (e == hipSuccess)
+            e = hipMemsetAsync(host_mask, 0, npx, s->copy);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s->copy);
+        if (e != hipSuccess) {
+            delete r;
+            return hip_status(e, "niter 0 copy");
+        }
+    } else if (niter == 0) {       // nothing to compute: the result is the input
         memcpy(host_clean, host_img, 4 * npx);
         memset(host_mask, 0, npx);
     }
+    r->id = s->next_id++;
+    *out_id = r->id;
     s->waiting.push_back(r);
     return ok();
 }

@@ -30,17 +30,22 @@ class Server:
     def submit(self, img, gain: float, readnoise: float, sky: float = 0.0,
                sigclip: float = 4.5, sigfrac: float = 0.3, objlim: float = 4.0,
                niter: int = 4) -> int:
-        """img: a numpy array, or a pinned CPU torch tensor (then the outputs are pinned
-        tensors too and the server transfers without staging copies)."""
+        """img: a numpy array, a pinned CPU torch tensor (then the outputs are pinned
+        tensors too and the server transfers without staging copies), or a CUDA tensor on
+        the server's device, ready to be read (then the outputs are CUDA tensors and every
+        transfer stays on the device)."""
         import torch
         if isinstance(img, torch.Tensor):
-            if img.is_cuda or img.dtype != torch.float32 or img.dim() != 2 or \
-                    not img.is_contiguous():
-                raise ValueError("img must be a contiguous 2-D float32 CPU tensor")
+            if img.dtype != torch.float32 or img.dim() != 2 or not img.is_contiguous():
+                raise ValueError("img must be a contiguous 2-D float32 tensor")
             H, W = img.shape
-            pinned = img.is_pinned()
-            clean = torch.empty((H, W), dtype=torch.float32, pin_memory=pinned)
-            mask = torch.empty((H, W), dtype=torch.uint8, pin_memory=pinned)
+            if img.is_cuda:
+                clean = torch.empty((H, W), dtype=torch.float32, device=img.device)
+                mask = torch.empty((H, W), dtype=torch.uint8, device=img.device)
+            else:
+                pinned = img.is_pinned()
+                clean = torch.empty((H, W), dtype=torch.float32, pin_memory=pinned)
+                mask = torch.empty((H, W), dtype=torch.uint8, pin_memory=pinned)
             p_img, p_clean, p_mask = img.data_ptr(), clean.data_ptr(), mask.data_ptr()
         else:
             img = np.ascontiguousarray(img, dtype=np.float32)
@@ -64,7 +69,7 @@ class Server:
         for i in range(n.value):
             rid = int(self._ids[i])
             _, clean, mask = self._outs.pop(rid)
-            if not isinstance(clean, np.ndarray):
+            if not isinstance(clean, np.ndarray) and not clean.is_cuda:
                 clean, mask = clean.numpy(), mask.numpy()
             out.append((rid, float(self._lat[i]), clean, mask))
         return out

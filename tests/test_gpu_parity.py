@@ -451,3 +451,14 @@ def test_mixed_batch_sampled():
     for f, it in zip(frames, items):
         check_sampled(f, it["out_clean"], it["out_mask"], 4)
     plan.close()
+
+
+def test_calibration_copy_b32():
+    """The counter-calibration copy (4-byte buffer loads) copies exactly, across its
+    2^20-element chunks and a ragged tail."""
+    for n in (1, 1000, (1 << 20) + 7, 3 * (1 << 20)):
+        src = torch.arange(n, dtype=torch.float32, device=DEV) * 0.5
+        dst = torch.full_like(src, -1.0)
+        _lib.debug_copy_b32(src, dst)
+        torch.cuda.synchronize()
+        assert torch.equal(src, dst), n

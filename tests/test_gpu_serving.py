@@ -116,3 +116,38 @@ def test_pinned_buffers_transfer_directly():
         c, m = solo(frames[ids[rid]])
         np.testing.assert_array_equal(clean, c)
         np.testing.assert_array_equal(mask, m)
+
+
+def test_device_resident_requests_identical_and_mixed_with_host_ones():
+    """Requests whose image and outputs are device memory (the host link out of the way)
+    give the same results as host requests and as solo runs, also when both kinds share
+    rounds; mixing host and device buffers in one request is refused."""
+    frames = mixed_frames()
+    budget = 3 * _lib.workspace_bytes(800, 800) + 3 * 5 * 800 * 800 + (1 << 20)
+    srv = serving.Server(budget, max_slots=4)
+    ids = {}
+    for i, f in enumerate(frames):
+        src = torch.from_numpy(f.img).to(DEV) if i % 2 == 0 else f.img
+        ids[srv.submit(src, **params(f))] = i
+    torch.cuda.synchronize()
+    done = srv.drain()
+    assert len(done) == len(frames)
+    for rid, lat, clean, mask in done:
+        i = ids[rid]
+        c, m = solo(frames[i])
+        if i % 2 == 0:
+            assert clean.is_cuda and mask.is_cuda
+            clean, mask = clean.cpu().numpy(), mask.cpu().numpy()
+        np.testing.assert_array_equal(clean, c)
+        np.testing.assert_array_equal(mask, m)
+    f = frames[0]
+    img = torch.from_numpy(f.img).to(DEV)
+    host_out = np.empty(f.img.shape, np.float32)
+    dev_mask = torch.empty(f.img.shape, dtype=torch.uint8, device=DEV)
+    import ctypes
+    rid = ctypes.c_int64(0)
+    st = _lib.lib().crb_server_submit(srv.handle, img.data_ptr(), f.img.shape[0], f.img.shape[1],
+                                      f32(f.gain), f32(f.readnoise), 0.0, 4.5, 0.3, 4.0, 4,
+                                      host_out.ctypes.data, dev_mask.data_ptr(), ctypes.byref(rid))
+    assert st == -1
+    srv.close()

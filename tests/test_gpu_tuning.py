@@ -205,3 +205,33 @@ def test_autotune_refuses_in_place_frames():
     with pytest.raises(_lib.CrbError):
         plan.autotune(reps=1, use_cache=False)
     plan.close()
+
+
+@pytest.mark.parametrize("shape", [dict(tile_h=32, persistent=0, fused=0, grow_h=0),
+                                   dict(tile_h=64, persistent=0, fused=1, grow_h=0),
+                                   dict(tile_h=16, persistent=1, fused=0, grow_h=16)],
+                         ids=["default", "t64-fused", "t16-persistent"])
+def test_one_frame_plans(reference, shape):
+    """A plan of one frame launches it by value (as crb_lacosmic does) unless its
+    detection is persistent; eager and graph runs, with the work counters switched on
+    between them, reproduce the reference."""
+    frames, ref_out, ref_stats = reference
+    for i in (0, 1, 7):
+        items = make_items([frames[i]])
+        for use_graph in (False, True):
+            plan = _lib.Plan(items, use_graph=use_graph)
+            plan.set_tuning(**shape)
+            for counting in (False, True):
+                if counting and not use_graph:
+                    plan.set_counting(True)
+                poison(items)
+                plan.run()
+                st = plan.stats()
+                c, m = ref_out[i]
+                assert torch.equal(items[0]["out_mask"], m), (shape, i, use_graph)
+                assert torch.equal(items[0]["out_clean"], c), (shape, i, use_graph)
+                assert st[0] == ref_stats[i], (shape, i, use_graph)
+            if not use_graph:
+                counts = plan.work_counts()
+                assert counts["work_pixels"] > 0, (shape, i)
+            plan.close()
