@@ -179,14 +179,17 @@ def roofline_record(total_px, det_avg_s, work, step_s, valu_per_launch, traffic)
     return rec
 
 
-def plan_leg(items, total_px, steps, warmup, tune, label):
-    """Batch plan of `items`: autotuned shapes (unless tune is False), timed steps with
-    per-launch events, the detection work counters, and the same plan at the default
-    shapes.  Returns (record, ms per step, kernel averages, work, plan stats, tuning)."""
+def plan_leg(items, total_px, steps, warmup, tune, label, shape=None):
+    """Batch plan of `items`: autotuned shapes (unless tune is False; `shape` forces
+    one), timed steps with per-launch events, the detection work counters, and the same
+    plan at the default shapes.  Returns (record, ms per step, kernel averages, work,
+    plan stats, tuning)."""
     from paper_1008_2192_amd import _lib
-    plan = _lib.Plan(items, use_graph=False)
+    plan = _lib.Plan(items, use_graph=False, on_current_stream=True)
     tuned = None
-    if tune:
+    if shape:
+        plan.set_tuning(**shape)
+    elif tune:
         tuned = plan.autotune(reps=3, use_cache=True)
         log(f"{label}: autotune {tuned}")
     tuning = plan.get_tuning()
@@ -202,16 +205,19 @@ def plan_leg(items, total_px, steps, warmup, tune, label):
     work = plan.work_counts()
     plan.set_counting(False)
     rec = {"tuning": tuning}
-    if tune and tuning != _lib.DEFAULT_TUNING:
+    # the tuned and the default shapes without per-launch events, for their comparison
+    t_s = time_steps(plan.run, steps, warmup)
+    rec["tuned_no_events"] = {"ms_per_step": round(t_s * 1e3, 3),
+                              "value": round(total_px * 4 / t_s / 1e6, 1)}
+    if tuning != _lib.DEFAULT_TUNING:
         plan.set_tuning(**_lib.DEFAULT_TUNING)
         d_s = time_steps(plan.run, steps, warmup)
         plan.set_tuning(**tuning)
-        rec["default"] = {"ms_per_step": round(d_s * 1e3, 3),
-                          "value": round(total_px * 4 / d_s / 1e6, 1)}
-    elif tune:
-        rec["default"] = {"ms_per_step": round(step_s * 1e3, 3),
-                          "value": round(total_px * 4 / step_s / 1e6, 1),
-                          "note": "the autotuner kept the default shapes"}
+    else:
+        d_s = t_s
+    rec["default"] = {"ms_per_step": round(d_s * 1e3, 3),
+                      "value": round(total_px * 4 / d_s / 1e6, 1),
+                      "tuned_speedup": round(d_s / t_s, 3)}
     if tuned:
         rec["autotune"] = {"ms": round(tuned["ms"], 4), "default_ms": round(tuned["default_ms"], 4)}
     plan.close()
@@ -224,7 +230,7 @@ def plan_leg(items, total_px, steps, warmup, tune, label):
 
 def graph_leg(items, tuning, total_px, steps, warmup):
     from paper_1008_2192_amd import _lib
-    gplan = _lib.Plan(items, use_graph=True)
+    gplan = _lib.Plan(items, use_graph=True, on_current_stream=True)
     gplan.set_tuning(**tuning)
     g_s = time_steps(gplan.run, steps, warmup)
     gplan.close()
@@ -262,7 +268,8 @@ def c3_leg(args, dev):
     items = device_items([f], dev)
     px = f.img.size
     rec, step_s, kt, kavg, work, stats, tuning = plan_leg(items, px, args.steps, args.warmup,
-                                                         not args.no_tune, "c3 batch plan")
+                                                         not args.no_tune, "c3 batch plan",
+                                                         parse_shape(args.c3_shape))
     batch_out = (items[0]["out_clean"].clone(), items[0]["out_mask"].clone())
     det_ms, det_n = kt["detect"]
     out = {"workload": "c3: one 4096x4096 FP32 crowded field, 20000 stars (power-law flux), "
@@ -468,7 +475,9 @@ def oracle_parity(frames, items):
     t0 = time.perf_counter()
     n_mask = n_clean = 0
     worst = 0.0
-    for f, it in zip(frames, items):
+    for i, (f, it) in enumerate(zip(frames, items)):
+        if i % 8 == 0:
+            log(f"oracle parity: frame {i} of {len(frames)}, {time.perf_counter() - t0:.1f} s")
         r = partition.lacosmic_partitioned(f.img, f.gain, f.readnoise, f.sky, f.sigclip,
                                            f.sigfrac, f.objlim, 4)
         gm = it["out_mask"].cpu().numpy()
@@ -539,25 +548,26 @@ def farm_mode(band_rows=1):
     return out
 
 
-def sources_mode():
+def sources_mode(tiles=None, workers=None, frames=None):
     """The SOURCES work function (Section 7: actors returning structures) on the
     4096x4096 crowded field and on that field tiled 4 x 4 (1 GiB): algorithmic bytes
     (4 B per pixel + 40 B per source) per launch against 8 TB/s, over tile shapes and
-    actor counts."""
+    actor counts (or the ones given)."""
     import torch
     from paper_1008_2192_amd import _lib, synth
     f = synth.c3()
     sky = 200.0 / 1.5
     t = sky + 5.0 * np.sqrt(200.0 + 16.0) / 1.5
     out = {"workload": "sources", "rows": []}
-    for name, frame in (("4096x4096", f.img), ("16384x16384", np.tile(f.img, (4, 4)))):
+    for name in frames or ("4096x4096", "16384x16384"):
+        frame = f.img if name == "4096x4096" else np.tile(f.img, (4, 4))
         x = torch.from_numpy(frame).cuda()
         res = _lib.farm_sources(x, t, sky, 2, 3, capacity=1 << 22)
         torch.cuda.synchronize()
         n_src = int(res.count.item())
         alg = 4.0 * frame.size + 40.0 * n_src
-        for th, tw in ((16, 64), (32, 64), (64, 64), (32, 128), (8, 256)):
-            for w in (1024, 2048, 4096, 8192, 16384):
+        for th, tw in tiles or ((16, 64), (32, 64), (64, 64), (32, 128), (8, 256)):
+            for w in workers or (1024, 2048, 4096, 8192, 16384):
                 evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                        for _ in range(10)]
                 _lib.farm_sources(x, t, sky, 2, 3, workers=w, tile_h=th, tile_w=tw, out=res)
@@ -576,6 +586,13 @@ def sources_mode():
     return out
 
 
+def parse_shape(text):
+    if not text:
+        return None
+    th, pe, fu, gh = (int(v) for v in text.split(","))
+    return dict(tile_h=th, persistent=pe, fused=fu, grow_h=gh)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,9 +606,18 @@ def main():
     ap.add_argument("--no-incremental", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 4096x4096 record")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes, no autotune")
+    ap.add_argument("--shape", default=None,
+                    help="launch shapes tile_h,persistent,fused,grow_h instead of the "
+                         "autotuner's (e.g. 32,1,0,32)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run 1 GiB device copies, wide (torch) and by 4-byte buffer "
                          "loads (counter calibration)")
+    ap.add_argument("--c3-shape", default=None,
+                    help="launch shapes of the 4096x4096 record instead of the autotuner's")
+    ap.add_argument("--sources-tile", default=None, help="sources study: one tile, e.g. 64x64")
+    ap.add_argument("--sources-workers", type=int, default=None,
+                    help="sources study: one actor count")
+    ap.add_argument("--sources-frame", default=None, choices=["4096x4096", "16384x16384"])
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the Poisson request trace (0 skips serving)")
@@ -605,6 +631,10 @@ def main():
                     help="every pixel of every batch frame against the oracle on all host "
                          "cores")
     args = ap.parse_args()
+    # launch shapes chosen by the autotuner on MI355X for the batch layouts timed here
+    # (a tune cache keyed by device and layout; other layouts or devices are tuned live)
+    os.environ.setdefault("CRB_TUNE_CACHE", os.path.join(ROOT, "paper_1008_2192_amd",
+                                                         "tune_cache.txt"))
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (frames shard across GPUs by "
@@ -617,15 +647,30 @@ def main():
     _lib.lib()                     # fail loudly if the HIP library is missing
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-
     if args.workload in ("halo", "farm", "sources"):
-        out = {"halo": halo_mode, "farm": farm_mode, "sources": sources_mode}[args.workload]()
+        if args.workload == "sources":
+            out = sources_mode(
+                [tuple(int(v) for v in args.sources_tile.split("x"))] if args.sources_tile
+                else None,
+                [args.sources_workers] if args.sources_workers else None,
+                [args.sources_frame] if args.sources_frame else None)
+        else:
+            out = {"halo": halo_mode, "farm": farm_mode}[args.workload]()
         print(json.dumps(out), flush=True)
         return
-
     t0 = time.perf_counter()
     frames = make_workload(args.workload, args.workers)
     log(f"generated {len(frames)} frame(s) in {time.perf_counter() - t0:.1f} s")
+    # every leg runs on one stream of the benchmark's own (plans, graphs and the
+    # per-frame calls alike), so no leg pays for cross-stream waits
+    with torch.cuda.stream(torch.cuda.Stream(device=dev)):
+        run(args, dev, frames)
+
+
+def run(args, dev, frames):
+    import torch
+    from paper_1008_2192_amd import _lib
+
     items = device_items(frames, dev)
     torch.cuda.synchronize()
     total_px = sum(f.img.size for f in frames)
@@ -634,7 +679,7 @@ def main():
     # ---- timed region: the autotuned batch plan, events around every launch -----
     rec, step_s, kt, kavg, work, stats, tuning = plan_leg(items, total_px, args.steps,
                                                          args.warmup, not args.no_tune,
-                                                         "batch plan")
+                                                         "batch plan", parse_shape(args.shape))
     value = px_iter / step_s / 1e6
     det_ms, det_n = kt["detect"]
     summary = "k_detect_batch64_counters.md" if args.workload == "c4" else None
@@ -667,7 +712,7 @@ def main():
 
     if not args.no_incremental:
         inc_items = [dict(it, incremental=True) for it in items]
-        iplan = _lib.Plan(inc_items, use_graph=False)
+        iplan = _lib.Plan(inc_items, use_graph=False, on_current_stream=True)
         iplan.set_tuning(**tuning)
         for _ in range(args.warmup):
             iplan.run()

@@ -283,19 +283,29 @@ def lacosmic_batched(items: Sequence[dict], stream: Optional[torch.cuda.Stream] 
 
 
 class Plan:
-    """A graph-captured batch plan (crb_plan_*) on a stream of its own, ordered
-    after the caller's current stream at each run and before it afterwards."""
+    """A batch plan (crb_plan_*), optionally graph-captured.  By default it runs on a
+    stream of its own, ordered after the caller's current stream at each run and
+    before it afterwards; with on_current_stream it runs on the stream that is current
+    at creation, with no cross-stream waits (a graph plan needs that stream to be one
+    other than the null stream, on which no graph can be captured)."""
 
-    def __init__(self, items: Sequence[dict], use_graph: bool = True):
+    def __init__(self, items: Sequence[dict], use_graph: bool = True,
+                 on_current_stream: bool = False):
         self.items = list(items)
         self.frames = make_frames(self.items)
         self.handle = ctypes.c_void_p()
-        self.stream = torch.cuda.Stream()
+        if on_current_stream and use_graph and torch.cuda.current_stream().cuda_stream == 0:
+            raise ValueError("a graph plan cannot be captured on the null stream")
+        self.stream = torch.cuda.current_stream() if on_current_stream else torch.cuda.Stream()
+        self._own = not on_current_stream
         check("crb_plan_create", lib().crb_plan_create(
             self.frames, len(self.items), ctypes.c_void_p(self.stream.cuda_stream),
             1 if use_graph else 0, ctypes.byref(self.handle)))
 
     def run(self) -> None:
+        if not self._own:
+            check("crb_plan_run", lib().crb_plan_run(self.handle))
+            return
         cur = torch.cuda.current_stream()
         self.stream.wait_stream(cur)
         check("crb_plan_run", lib().crb_plan_run(self.handle))
