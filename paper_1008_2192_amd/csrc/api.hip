@@ -132,6 +132,7 @@ DevFrame make_devframe(const float *img, float *J, uint8_t *mask, char *ws, cons
     f.niter = niter;
     f.flags = flags;
     f.k = 0;
+    derive_detect_consts(f);
     return f;
 }
 

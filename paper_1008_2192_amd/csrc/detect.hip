@@ -79,11 +79,11 @@ struct SEstParams {
 __device__ __forceinline__ SEstParams sest_params(const DevFrame &f) {
     SEstParams p;
     p.gain = f.gain;
-    p.g8 = f.gain * 0.125f;
-    p.inv_gain = 1.0f / f.gain;
+    p.g8 = f.g8;
+    p.inv_gain = f.inv_gain;
     p.sky = f.sky;
-    p.rn2 = f.readnoise * f.readnoise;
-    p.ok = f.gain >= 0x1p-100f && f.gain <= 0x1p100f;
+    p.rn2 = f.rn2f;
+    p.ok = f.est_ok != 0;
     return p;
 }
 
@@ -373,6 +373,10 @@ struct DetectLayout {
     static constexpr int JH = TY + 8, JW = TX + 8, JWP = TX + 9;    // J, apron 4
     static constexpr int SH = TY + 4, SW = TX + 4, SWP = TX + 6;    // S estimate, apron 2
     static constexpr int HW = (SW + 31) / 32;   // words per row of the hot bitmap
+    // the hot bitmap is stored with 4 zero rows above and below and a zero word before
+    // each row (which is also the word after the previous row; one more zero word ends
+    // the array), so that its dilations read it without bounds tests
+    static constexpr int HWP = HW + 1, HR = SH + 8;
     static constexpr int QW = TX / 32;          // words per row of the tile bitmaps
     static constexpr int kTileWords = TY * QW;
     // pixels per round of the binary64 re-evaluation (25 threads each)
@@ -381,7 +385,7 @@ struct DetectLayout {
     // further ones take the same test in their own lanes
     static constexpr int kConMax = TY;
     // work-set pixels a block lists; a larger work set is taken from its bitmap instead
-    static constexpr int kListMax = 16 * TY;
+    static constexpr int kListMax = 8 * TY;
     // LDS budget for the resident blocks per CU (the CU hands out LDS in 1 KiB units):
     // 12 blocks of 16 rows, 6 of 32 rows, 3 of 64 rows (about 24 waves per CU)
     static constexpr int kLdsBudget = TY == 16 ? 15360 : (TY == 32 ? 26624 : 53248);
@@ -419,7 +423,9 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     __shared__ __align__(16) float sJ[L::JH * L::JWP];       // J, clamped extension
     __shared__ __align__(16) float sS[L::SH * L::SWP];      // later: re-evaluation buffer
     __shared__ __align__(16) uint8_t sCode[TY * TX];
-    __shared__ uint32_t sHot[L::SH * L::HW];                // H', apron 2, in-frame
+    __shared__ uint32_t sHotP[L::HR * L::HWP + 1];          // H', apron 2, in-frame
+    // word w of region row r of H' (r in [-4, SH + 4), w in [-1, HW]; zero outside)
+    uint32_t *const sHot = &sHotP[4 * L::HWP + 1];
     __shared__ uint32_t sU[L::kTileWords], sUpre[L::kTileWords + 1];
     // tile cells where S may exceed sigfrac*sigclip; after the work-set build, Q' itself
     __shared__ uint32_t sLow[L::kTileWords];
@@ -430,7 +436,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     // pixels whose contrast test is left to the contrast phase: position, S' interval
     __shared__ uint32_t sConInfo[kConMax];
     __shared__ float sConLo[kConMax], sConHi[kConMax], sConM5[kConMax];
-    static_assert(sizeof(sJ) + sizeof(sS) + sizeof(sCode) + sizeof(sHot) + sizeof(sU) +
+    static_assert(sizeof(sJ) + sizeof(sS) + sizeof(sCode) + sizeof(sHotP) + sizeof(sU) +
                           sizeof(sUpre) + sizeof(sLow) + sizeof(sList) + sizeof(sConInfo) +
                           sizeof(sConLo) + sizeof(sConHi) + sizeof(sConM5) + 7 * 4 + 16 <=
                       L::kLdsBudget,
@@ -455,14 +461,12 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     }
     // iteration 1 reads the input frame and initialises J with the tile's own pixels
     const float *__restrict__ J = (k == 1) ? f.img : f.J;
-    const float sc = f.sigclip, ll = f.sigfrac * f.sigclip;
     // thresholds widened by 2^-20 relative: fl(x) beyond them decides the real x
     // against the binary64 thresholds sigclip and sigfrac * sigclip (exact products)
-    const float sc_lo = sc * (1.0f - 0x1p-20f), sc_hi = sc * (1.0f + 0x1p-20f);
-    const float ll_lo = ll * (1.0f - 0x1p-20f), ll_hi = ll * (1.0f + 0x1p-20f);
+    const float sc_lo = f.sc_lo, sc_hi = f.sc_hi, ll_lo = f.ll_lo, ll_hi = f.ll_hi;
 
-    for (int i = tid; i < L::SH * L::HW; i += NT)
-        sHot[i] = 0u;
+    for (int i = tid; i < L::HR * L::HWP + 1; i += NT)
+        sHotP[i] = 0u;
     for (int i = tid; i < L::kTileWords; i += NT) {
         sU[i] = 0u;
         sLow[i] = 0u;
@@ -626,9 +630,9 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
             bits = (gy >= 0 && gy < H) ? bits & colmask : 0u;
             if (bits) {
                 const int w = c5 >> 5, sh = c5 & 31;
-                atomicOr(&sHot[(r5 + i) * L::HW + w], bits << sh);
+                atomicOr(&sHot[(r5 + i) * L::HWP + w], bits << sh);
                 if (sh > 32 - TTX && (bits >> (32 - sh)))
-                    atomicOr(&sHot[(r5 + i) * L::HW + w + 1], bits >> (32 - sh));
+                    atomicOr(&sHot[(r5 + i) * L::HWP + w + 1], bits >> (32 - sh));
             }
         }
     }
@@ -645,23 +649,18 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
                   "whole quads; the quad bitmap words fit the block's waves");
     constexpr int kQuads = NP * L::SW / 2;
     static_assert(kQuads <= TY * TX / 2, "the quad list fits in the code plane");
-    constexpr int kQuadRounds = (kQuads + NT - 1) / NT;
     uint16_t *const sQuads = reinterpret_cast<uint16_t *>(sCode);   // codes start later
     if (tid < 64 * kQuadWaves) {
         uint32_t m = 0u;
         const int pr = tid / L::HW, w = tid - pr * L::HW;
         if (tid < kQuadWords) {
             uint32_t a = 0u, b = 0u, c = 0u;        // words w - 1, w, w + 1 of the rows
+            const uint32_t *row = &sHot[(2 * pr - 4) * L::HWP + w];
 #pragma unroll
             for (int kk = 0; kk < 10; ++kk) {
-                const int rr = 2 * pr - 4 + kk;
-                const bool in = rr >= 0 && rr < L::SH;
-                const uint32_t *row = &sHot[(in ? rr : 0) * L::HW];
-                const uint32_t ra = row[w > 0 ? w - 1 : 0], rb = row[w],
-                               rc = row[w + 1 < L::HW ? w + 1 : w];
-                a |= (in && w > 0) ? ra : 0u;
-                b |= in ? rb : 0u;
-                c |= (in && w + 1 < L::HW) ? rc : 0u;
+                a |= row[kk * L::HWP - 1];
+                b |= row[kk * L::HWP];
+                c |= row[kk * L::HWP + 1];
             }
             // column 32w + k is needed when a bit lies in columns 32w + k - 4 .. + 4
             const unsigned long long hi = ((unsigned long long)c << 32) | b;
@@ -689,10 +688,9 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     {
         float emax = 0.0f;
         unsigned int ncells = 0u;
-#pragma unroll
-        for (int rd = 0; rd < kQuadRounds; ++rd) {
-            const int it = tid + rd * NT;
-            if (it < nquads) {
+#pragma unroll 1
+        for (int it = tid; it < nquads; it += NT) {
+            {
                 const int q = (int)sQuads[it];
                 const int pr = q / L::SW, cc = q - pr * L::SW, r0 = 2 * pr;
                 float v[6 * 6];
@@ -715,7 +713,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
                         sS[rr * L::SWP + c] = s;
                         emax = fmaxf(emax, err);
                         // H' keeps the cells whose estimate at med5(J) may exceed sigclip
-                        uint32_t *hw = &sHot[rr * L::HW + (c >> 5)];
+                        uint32_t *hw = &sHot[rr * L::HWP + (c >> 5)];
                         const uint32_t hb = 1u << (c & 31);
                         if (!(s + err > sc_lo) && (*hw & hb))
                             atomicAnd(hw, ~hb);
@@ -768,7 +766,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
             unsigned long long x = 0ull;
 #pragma unroll
             for (int dr = 0; dr < 5; ++dr) {
-                const uint32_t *row = &sHot[(r + dr) * L::HW + w];
+                const uint32_t *row = &sHot[(r + dr) * L::HWP + w];
                 x |= (unsigned long long)row[0] | ((unsigned long long)row[1] << 32);
             }
             // bit b of the dilation covers region columns 32w+b .. 32w+b+4, centred on
@@ -789,9 +787,8 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     }
     __syncthreads();
 
-    const double gain = f.gain, sky = f.sky, rn = f.readnoise;
-    const double rn2 = rn * rn, sigclip = f.sigclip, objlim = f.objlim;
-    const double lowlim = (double)f.sigfrac * (double)f.sigclip;
+    const double gain = f.gain_d, sky = f.sky_d, rn2 = f.rn2_d;
+    const double sigclip = f.sigclip_d, objlim = f.objlim_d, lowlim = f.lowlim_d;
     const int total = (int)sQcount;
     // the work set, compacted: thread t takes the t-th, (t+NT)-th, ... pixel of Q' (of
     // the tile, tested against the Q' bitmap, when the list could not hold Q').
@@ -800,8 +797,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     const bool listed_q = total <= kListMax;
     if (!all_exact) {
         const float b2 = 2.02f * emax;
-        const float olim = f.objlim;
-        const float olim_lo = olim * (1.0f - 0x1p-21f), olim_hi = olim * (1.0f + 0x1p-21f);
+        const float olim_lo = f.olim_lo, olim_hi = f.olim_hi;
         unsigned int ncontrast = 0u, nunc = 0u;
         for (int qi = tid; qi < (listed_q ? total : TY * TX); qi += NT) {
             const int pos = listed_q ? (int)sList[qi] : qi;
@@ -845,7 +841,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
                         listed = true;
                     } else {
                         const int t = contrast_by_count_lane(sJ, L::JWP, y0, x0, H, W, r, c,
-                                                             m5[0], sp, lo, hi, 1.0f / olim);
+                                                             m5[0], sp, lo, hi, f.inv_olim);
                         first = t > 0;
                         unc = t < 0;
                         ncontrast += unc ? 0u : 1u;
@@ -871,7 +867,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     // contrast tests of the listed pixels (S' > sigclip certain), one wave per pixel
     const int ncon = min((int)sConCount, kConMax);
     if (ncon) {
-        const float inv_olim = 1.0f / f.objlim;
+        const float inv_olim = f.inv_olim;
         unsigned int ncontrast = 0u, nunc = 0u;
         for (int it = tid >> 6; it < ncon; it += L::NW) {
             const uint32_t info = sConInfo[it];

@@ -81,7 +81,44 @@ struct DevFrame {
     int flags;
     int k;                        // current iteration when a kernel is launched with k = 0
     int pad;
+    // Detection constants, derived from the parameters above by derive_detect_consts (on
+    // the host, in the operations the detection would otherwise repeat per tile): the
+    // FP32 thresholds sigclip and sigfrac * sigclip widened and narrowed by 2^-20
+    // relative, objlim by 2^-21, 1 / objlim; the parameters of the FP32 estimate of S
+    // (gain / 8, 1 / gain, readnoise^2, and whether gain lies in [2^-100, 2^100]); and the
+    // binary64 parameters of the re-evaluation.
+    float sc_lo, sc_hi, ll_lo, ll_hi;
+    float olim_lo, olim_hi, inv_olim;
+    float g8, inv_gain, rn2f;
+    int est_ok;
+    int pad2;
+    double gain_d, sky_d, rn2_d, sigclip_d, objlim_d, lowlim_d;
 };
+
+// Fills the detection constants of f from its parameters (every DevFrame passes through
+// it: make_devframe calls it).  Plain IEEE single and double operations, each rounded
+// once, as the device would evaluate them.
+inline void derive_detect_consts(DevFrame &f) {
+    const float ll = f.sigfrac * f.sigclip;
+    f.sc_lo = f.sigclip * (1.0f - 0x1p-20f);
+    f.sc_hi = f.sigclip * (1.0f + 0x1p-20f);
+    f.ll_lo = ll * (1.0f - 0x1p-20f);
+    f.ll_hi = ll * (1.0f + 0x1p-20f);
+    f.olim_lo = f.objlim * (1.0f - 0x1p-21f);
+    f.olim_hi = f.objlim * (1.0f + 0x1p-21f);
+    f.inv_olim = 1.0f / f.objlim;
+    f.g8 = f.gain * 0.125f;
+    f.inv_gain = 1.0f / f.gain;
+    f.rn2f = f.readnoise * f.readnoise;
+    f.est_ok = (f.gain >= 0x1p-100f && f.gain <= 0x1p100f) ? 1 : 0;
+    f.pad2 = 0;
+    f.gain_d = (double)f.gain;
+    f.sky_d = (double)f.sky;
+    f.rn2_d = (double)f.readnoise * (double)f.readnoise;
+    f.sigclip_d = (double)f.sigclip;
+    f.objlim_d = (double)f.objlim;
+    f.lowlim_d = (double)f.sigfrac * (double)f.sigclip;
+}
 
 struct TileRef {                  // one (frame, tile origin) work item
     int frame, y0, x0, pad;
