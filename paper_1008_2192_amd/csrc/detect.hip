@@ -133,17 +133,27 @@ __device__ __forceinline__ float r_bound(float x, const SEstParams &p) {
 }
 
 // Whether S may exceed thr at a pixel of value c with 4-neighbours up, dn, lf, rt, given
-// a finite R = r_bound(x) for a lower bound x of its med5(J) and E = 2^-19 * 8 v * R with
-// v >= each |value| read and 8 v <= 2^100 (so E >= 2^-19 M R, M as in s_estimate): the
-// estimate s = l4 R as s_estimate forms it, and s + 2^-19 s + E in one FMA.  That sum
-// exceeds the bound s + err of s_estimate, which holds S with four-fold slack, by far more
-// than its own rounding; compared with thr = sigclip less 2^-20 it settles S <= sigclip.
+// Rp = R (1 + 2^-19) rounded, R = r_bound(x) finite for a lower bound x of its med5(J),
+// and E = 2^-19 * 8 v * R with v >= each |value| read and 8 v <= 2^100.
+//   The four clipped sub-pixel terms pair up by their vertical neighbour: with
+//   a = 2c - up, the two terms max(a - lf, 0) + max(a - rt, 0) equal
+//   max(2a - (lf + rt), a - min(lf, rt), 0) (the first argument wins when a is above both
+//   horizontal neighbours, the second when it lies between them, 0 below both), and the
+//   same with b = 2c - dn.  Evaluated as written (two FMAs for a and b, lf + rt, the
+//   minimum, per pair one FMA, one subtraction and a max3, one final addition), each pair
+//   is within 2u (M_a) of its exact value, M_a = 4|c| + 2|up| + |lf| + |rt| (likewise
+//   M_b), and the sum within 3u (M_a + M_b) = 6u M of 4 L+ (u = 2^-24, M as in
+//   s_estimate).
+//   With R's own error (at most 5u relative, as in s_estimate), S <= (l4 + 6u M) R (1+5u),
+//   while fl(l4 Rp + E) >= l4 R (1 + 2^-19 - 2.1u) + E (1 - u) and E >= 32u M R (1 - u):
+//   the test value exceeds S, so comparing it with thr = sigclip less 2^-20 settles
+//   S <= sigclip wherever it fails.
 __device__ __forceinline__ bool s_may_exceed(float c, float up, float dn, float lf, float rt,
-                                             float R, float E, float thr) {
+                                             float Rp, float E, float thr) {
     const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
-    const float l4 = (fmaxf(a - lf, 0.0f) + fmaxf(a - rt, 0.0f)) +
-                     (fmaxf(b - lf, 0.0f) + fmaxf(b - rt, 0.0f));
-    return fmaf(l4 * R, 1.0f + 0x1p-19f, E) > thr;
+    const float s = lf + rt, m = fminf(lf, rt);
+    const float l4 = max3f(fmaf(2.0f, a, -s), a - m, 0.0f) + max3f(fmaf(2.0f, b, -s), b - m, 0.0f);
+    return fmaf(l4, Rp, E) > thr;
 }
 
 // S exactly as the definition evaluates it (binary64, in its operation order), at the
@@ -567,11 +577,12 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
 
     // Over [y0-2, y0+TY+2) x [x0-2, x0+TX+2), in 2 x 5 cell tiles (one per thread and
     // pass).  Dense pass: a lower bound x of med5(J) shared by the tile's ten windows (the
-    // least of the column medians of its 6 x 9 patch: every window holds five of those
-    // columns, each with three values at or above its median, so 15 of its 25 values are
-    // >= x); S does not increase with med5(J), so the estimate at x with its error bound
-    // bounds S from above, and H' = the in-frame cells where that bound exceeds sigclip
-    // (less a margin) holds H.
+    // least over the nine columns of its 6 x 9 patch of the second smallest of patch rows
+    // 1-4: every window holds five of those columns, each including rows 1-4 and so three
+    // values at or above that second smallest, so 15 of its 25 values are >= x); S does
+    // not increase with med5(J), so the estimate at x with its error bound bounds S from
+    // above, and H' = the in-frame cells where that bound exceeds sigclip (less a margin)
+    // holds H.
     constexpr int TTY = 2, TTX = 5, PW = TTX + 4;
     constexpr int NTY = (L::SH + TTY - 1) / TTY, NTX = (L::SW + TTX - 1) / TTX;
     const SEstParams sp = sest_params(f);
@@ -588,15 +599,14 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
 #pragma unroll
             for (int j = 0; j < PW; ++j)
                 v[i * PW + j] = sJ[(r5 + i) * L::JWP + c5 + j];
-        // column medians of rows 0-4 and 1-5: the median of five values is the median of
-        // the fifth, the larger of the two pair minima and the smaller of the two pair
-        // maxima; rows 1-4 form the pairs of both
+        // the second smallest of four values: whichever pair holds the smallest keeps its
+        // larger value as a candidate, the other pair both of its values, so it is the
+        // least of the larger pair minimum and the two pair maxima
         float x = INFINITY;
 #pragma unroll
         for (int j = 0; j < PW; ++j) {
             const float a = v[PW + j], b = v[2 * PW + j], c = v[3 * PW + j], d = v[4 * PW + j];
-            const float lo = fmaxf(fminf(a, b), fminf(c, d)), hi = fminf(fmaxf(a, b), fmaxf(c, d));
-            x = min3f(x, med3f(v[j], lo, hi), med3f(v[5 * PW + j], lo, hi));
+            x = fminf(x, min3f(fmaxf(fminf(a, b), fminf(c, d)), fmaxf(a, b), fmaxf(c, d)));
         }
         const float R = r_bound(x, sp);
         // one error term for the tile's cells: every value their M reads lies in patch
@@ -609,6 +619,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
                 vmax = fmaxf(vmax, fabsf(v[i * PW + j]));
         const bool bound_ok = R < INFINITY && vmax <= 0x1p96f;
         const float E = (8.0f * vmax) * R * 0x1p-19f;
+        const float Rp = fmaf(R, 0x1p-19f, R);
         const int gx0 = x0 - 2 + c5;
         // in-frame columns of the tile's five, as a bit mask
         const uint32_t colmask = (gx0 >= 0 && gx0 + TTX <= W)
@@ -621,7 +632,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
 #pragma unroll
             for (int j = 0; j < TTX; ++j) {
                 const int pc = (i + 2) * PW + (j + 2);
-                bits |= s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], R, E,
+                bits |= s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], Rp, E,
                                      sc_lo) ? 1u << j : 0u;
             }
             // where the analysis of the estimate does not hold at the bound, every cell
@@ -787,8 +798,6 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     }
     __syncthreads();
 
-    const double gain = f.gain_d, sky = f.sky_d, rn2 = f.rn2_d;
-    const double sigclip = f.sigclip_d, objlim = f.objlim_d, lowlim = f.lowlim_d;
     const int total = (int)sQcount;
     // the work set, compacted: thread t takes the t-th, (t+NT)-th, ... pixel of Q' (of
     // the tile, tested against the Q' bitmap, when the list could not hold Q').
@@ -896,6 +905,10 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     // 25 threads compute the S window of a pixel, then one thread its codes
     const int nunc = (int)sUncertain;
     if (nunc) {
+        // the binary64 parameters (read here, on this rare path only)
+        const double gain = f.gain, sky = f.sky, rn = f.readnoise;
+        const double rn2 = rn * rn, sigclip = f.sigclip, objlim = f.objlim;
+        const double lowlim = (double)f.sigfrac * (double)f.sigclip;
         if (tid < 64)
             bitmap_prefix<L::kTileWords>(sU, sUpre);
         __syncthreads();
@@ -1075,7 +1088,9 @@ void k_detect_persistent(const DevFrame *__restrict__ frames, const TileRef *__r
             if (t > t0)
                 __syncthreads();   // the previous tile is done with the LDS
             const TileRef r = tiles[t];
-            const DevFrame f = frames[r.frame];
+            // the frame record is read in place, each field where the tile first needs it,
+            // rather than copied whole into scalar registers at the start of every tile
+            const DevFrame &f = frames[r.frame];
             // the thread index passes through an empty asm statement each round, so that
             // values derived from it are recomputed per tile rather than held in registers
             // across the loop

@@ -84,19 +84,17 @@ struct DevFrame {
     // Detection constants, derived from the parameters above by derive_detect_consts (on
     // the host, in the operations the detection would otherwise repeat per tile): the
     // FP32 thresholds sigclip and sigfrac * sigclip widened and narrowed by 2^-20
-    // relative, objlim by 2^-21, 1 / objlim; the parameters of the FP32 estimate of S
-    // (gain / 8, 1 / gain, readnoise^2, and whether gain lies in [2^-100, 2^100]); and the
-    // binary64 parameters of the re-evaluation.
+    // relative, objlim by 2^-21, 1 / objlim; and the parameters of the FP32 estimate of S
+    // (gain / 8, 1 / gain, readnoise^2, and whether gain lies in [2^-100, 2^100]).
     float sc_lo, sc_hi, ll_lo, ll_hi;
     float olim_lo, olim_hi, inv_olim;
     float g8, inv_gain, rn2f;
     int est_ok;
     int pad2;
-    double gain_d, sky_d, rn2_d, sigclip_d, objlim_d, lowlim_d;
 };
 
 // Fills the detection constants of f from its parameters (every DevFrame passes through
-// it: make_devframe calls it).  Plain IEEE single and double operations, each rounded
+// it: make_devframe calls it).  Plain IEEE single-precision operations, each rounded
 // once, as the device would evaluate them.
 inline void derive_detect_consts(DevFrame &f) {
     const float ll = f.sigfrac * f.sigclip;
@@ -112,12 +110,6 @@ inline void derive_detect_consts(DevFrame &f) {
     f.rn2f = f.readnoise * f.readnoise;
     f.est_ok = (f.gain >= 0x1p-100f && f.gain <= 0x1p100f) ? 1 : 0;
     f.pad2 = 0;
-    f.gain_d = (double)f.gain;
-    f.sky_d = (double)f.sky;
-    f.rn2_d = (double)f.readnoise * (double)f.readnoise;
-    f.sigclip_d = (double)f.sigclip;
-    f.objlim_d = (double)f.objlim;
-    f.lowlim_d = (double)f.sigfrac * (double)f.sigclip;
 }
 
 struct TileRef {                  // one (frame, tile origin) work item
