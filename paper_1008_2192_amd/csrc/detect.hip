@@ -1053,7 +1053,7 @@ template <int TY>
 __global__ __launch_bounds__(8 * TY) __attribute__((amdgpu_waves_per_eu(TY == 16 ? 4 : 6)))
 void k_detect_persistent(const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles,
                          int kiter, int ntiles, unsigned int *__restrict__ tickets) {
-    constexpr int kRun = TY == 64 ? 2 : 4;
+    constexpr int kRun = 2;
     __shared__ int sTile, sEnd;
     int q = (int)(blockIdx.x % kDetectQueues), tried = 0;
     for (;;) {
