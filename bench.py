@@ -272,10 +272,15 @@ def c3_leg(args, dev):
                                                          parse_shape(args.c3_shape))
     batch_out = (items[0]["out_clean"].clone(), items[0]["out_mask"].clone())
     det_ms, det_n = kt["detect"]
+    # a step of this frame is about half a millisecond, so an event around every launch
+    # adds a sixth to it: the record's value is the plan timed without them (the event
+    # run gives the per-kernel averages and the roofline)
+    plain_s = rec["tuned_no_events"]["ms_per_step"] / 1e3
     out = {"workload": "c3: one 4096x4096 FP32 crowded field, 20000 stars (power-law flux), "
                        "1.5% of pixels hit, gain 1.5, read noise 4, niter 4 (forced)",
-           "pixels": px, "value": round(px * 4 / step_s / 1e6, 1),
-           "ms_per_step": round(step_s * 1e3, 3), **rec, "kernel_avg_ms": kavg,
+           "pixels": px, "value": round(px * 4 / plain_s / 1e6, 1),
+           "ms_per_step": round(plain_s * 1e3, 3),
+           "events_ms_per_step": round(step_s * 1e3, 3), **rec, "kernel_avg_ms": kavg,
            "flagged_pixels": int(stats[0]["n_flagged"])}
     out["roofline"] = roofline_record(px, det_ms / det_n / 1e3, work, step_s,
                                       profiled_value("k_detect_c3_counters.md",
@@ -291,7 +296,7 @@ def c3_leg(args, dev):
         out["per_frame"] = {"ms_per_step": round(pf * 1e3, 3),
                             "value": round(px * 4 / pf / 1e6, 1),
                             "identical_to_batch": same,
-                            "batched_speedup": round(pf / step_s, 3)}
+                            "batched_speedup": round(pf / plain_s, 3)}
         if "graph" in out:
             out["per_frame"]["graph_speedup"] = round(pf * 1e3 / out["graph"]["ms_per_step"], 3)
         pft = per_frame_leg(items, px, args.steps, args.warmup, tuning)
