@@ -422,6 +422,13 @@ crb_status crb_debug_detect_exact(const float *J, const crb_frame *params,
  * established (then the detection decides in binary64). */
 crb_status crb_debug_s_estimate(const float *J, const crb_frame *params, float *out_s,
                                 float *out_err);
+/* The detection's dense upper bound of S (Section 5: S = L+ / (2N)) at every pixel of J
+ * (device pointers, H x W each, no overlap): out_u >= S, S being the binary64 value,
+ * from a lower bound of med5(J) shared by 2 x 5 pixel tiles (aligned at the frame's
+ * origin here); out_u = +inf where the bound's analysis does not hold.  The detection
+ * evaluates the other statistics only near the pixels where out_u exceeds sigclip.
+ * Runs on the calling thread's stream. */
+crb_status crb_debug_s_bound(const float *J, const crb_frame *params, float *out_u);
 /* Clamped (2r+1)^2 median filter, r in {1, 2, 3}, by the kernels' networks (3x3 by
  * sorted columns, 5x5 by the network for a 2 x 2 tile of outputs, 7x7 by the
  * single-output one). */

@@ -33,7 +33,7 @@ EXPORTS = ["crb_lacosmic", "crb_lacosmic_noalloc", "crb_lacosmic_batched", "crb_
            "crb_debug_fp64", "crb_work_run", "crb_work_radius", "crb_farm_run",
            "crb_plan_set_counting", "crb_plan_work_counts", "crb_debug_median5_f64",
            "crb_debug_detect_exact", "crb_debug_s_estimate", "crb_plan_set_tuning",
-           "crb_plan_get_tuning", "crb_plan_autotune", "crb_debug_copy_b32"]
+           "crb_plan_get_tuning", "crb_plan_autotune", "crb_debug_copy_b32", "crb_debug_s_bound"]
 CRB_WORK_LACOSMIC = 0
 CRB_WORK_POISSON = 1
 CRB_WORK_WAITER = 2
@@ -135,6 +135,7 @@ def lib():
     L.crb_debug_detect.argtypes = [vp, ctypes.POINTER(Frame), vp]
     L.crb_debug_detect_exact.argtypes = [vp, ctypes.POINTER(Frame), vp]
     L.crb_debug_s_estimate.argtypes = [vp, ctypes.POINTER(Frame), vp, vp]
+    L.crb_debug_s_bound.argtypes = [vp, ctypes.POINTER(Frame), vp]
     L.crb_debug_median.argtypes = [vp, i32, i32, i32, vp]
     L.crb_debug_fp64.argtypes = [vp, vp, i32, vp, vp]
     L.crb_debug_copy_b32.argtypes = [vp, vp, i64]
@@ -150,7 +151,7 @@ def lib():
                  "crb_work_run", "crb_farm_run", "crb_plan_set_counting", "crb_plan_work_counts",
                  "crb_debug_median5_f64", "crb_debug_detect_exact", "crb_debug_s_estimate",
                  "crb_plan_set_tuning", "crb_plan_get_tuning", "crb_plan_autotune",
-                 "crb_debug_copy_b32"):
+                 "crb_debug_copy_b32", "crb_debug_s_bound"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -426,6 +427,19 @@ def debug_s_estimate(J: torch.Tensor, gain, readnoise, sky=0.0, sigclip=4.5, sig
     check("crb_debug_s_estimate", lib().crb_debug_s_estimate(J.data_ptr(), ctypes.byref(p),
                                                              s.data_ptr(), err.data_ptr()))
     return s, err
+
+
+def debug_s_bound(J: torch.Tensor, gain, readnoise, sky=0.0, sigclip=4.5, sigfrac=0.3,
+                  objlim=4.0, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """The detection's dense upper bound of S (crb_debug_s_bound)."""
+    _dev2d(J, torch.float32, "J")
+    H, W = J.shape
+    u = torch.empty((H, W), dtype=torch.float32, device=J.device)
+    p = _params_frame(H, W, gain, readnoise, sky, sigclip, sigfrac, objlim)
+    set_stream(stream)
+    check("crb_debug_s_bound", lib().crb_debug_s_bound(J.data_ptr(), ctypes.byref(p),
+                                                       u.data_ptr()))
+    return u
 
 
 def debug_median(x: torch.Tensor, r: int, stream: Optional[torch.cuda.Stream] = None

@@ -613,6 +613,23 @@ crb_status crb_debug_s_estimate(const float *J, const crb_frame *p, float *out_s
     return st == CRB_OK ? ok() : st;
 }
 
+crb_status crb_debug_s_bound(const float *J, const crb_frame *p, float *out_u) {
+    if (!p || !J || !out_u)
+        return fail(CRB_EINVAL, "null pointer");
+    crb_status st = check_frame_args(p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
+                                     p->sigfrac, p->objlim, 1);
+    if (st != CRB_OK)
+        return st;
+    const size_t bytes = (size_t)p->H * (size_t)p->W * 4;
+    if (ranges_overlap(J, bytes, out_u, bytes))
+        return fail(CRB_EINVAL, "buffers overlap");
+    DevFrame f = make_devframe(J, const_cast<float *>(J), nullptr, nullptr, ws_layout(1, 1),
+                               p->H, p->W, p->gain, p->readnoise, p->sky, p->sigclip,
+                               p->sigfrac, p->objlim, 1, kNoEarlyStop);
+    st = hip_status(launch_debug_s_bound(f, out_u, t_stream), "kernel launch");
+    return st == CRB_OK ? ok() : st;
+}
+
 crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out) {
     if (!in || !out)
         return fail(CRB_EINVAL, "null pointer");

@@ -132,7 +132,7 @@ __device__ __forceinline__ float r_bound(float x, const SEstParams &p) {
     return sane ? p.g8 * __builtin_amdgcn_rsqf(t) : INFINITY;
 }
 
-// Whether S may exceed thr at a pixel of value c with 4-neighbours up, dn, lf, rt, given
+// An upper bound of S at a pixel of value c with 4-neighbours up, dn, lf, rt, given
 // Rp = R (1 + 2^-19) rounded, R = r_bound(x) finite for a lower bound x of its med5(J),
 // and E = 2^-19 * 8 v * R with v >= each |value| read and 8 v <= 2^100.
 //   The four clipped sub-pixel terms pair up by their vertical neighbour: with
@@ -146,14 +146,56 @@ __device__ __forceinline__ float r_bound(float x, const SEstParams &p) {
 //   s_estimate).
 //   With R's own error (at most 5u relative, as in s_estimate), S <= (l4 + 6u M) R (1+5u),
 //   while fl(l4 Rp + E) >= l4 R (1 + 2^-19 - 2.1u) + E (1 - u) and E >= 32u M R (1 - u):
-//   the test value exceeds S, so comparing it with thr = sigclip less 2^-20 settles
-//   S <= sigclip wherever it fails.
-__device__ __forceinline__ bool s_may_exceed(float c, float up, float dn, float lf, float rt,
-                                             float Rp, float E, float thr) {
+//   the returned value exceeds S, so where it is at most sigclip (less 2^-20), S <= sigclip.
+__device__ __forceinline__ float s_upper(float c, float up, float dn, float lf, float rt,
+                                         float Rp, float E) {
     const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
     const float s = lf + rt, m = fminf(lf, rt);
     const float l4 = max3f(fmaf(2.0f, a, -s), a - m, 0.0f) + max3f(fmaf(2.0f, b, -s), b - m, 0.0f);
-    return fmaf(l4, Rp, E) > thr;
+    return fmaf(l4, Rp, E);
+}
+
+// The dense bound of a 2 x 5 cell tile from its 6 x 9 patch of J (patch row i, column j
+// is cell row i - 2, column j - 2; clamped where the patch leaves the frame): u[5 i + j]
+// >= S at cell (i, j) for every cell of the tile, unless the function returns false (R
+// not finite or a value above 2^96 in magnitude: the analysis of the bound does not
+// hold, and every cell must count as a candidate).
+//   x: a lower bound of med5(J) shared by the tile's ten windows, the least over the nine
+//   columns of the second smallest of patch rows 1-4 (every window holds five of those
+//   columns, each including rows 1-4 and so three values at or above that second
+//   smallest, so 15 of its 25 values are >= x).  The second smallest of four values:
+//   whichever pair holds the smallest keeps its larger value as a candidate, the other
+//   pair both of its values, so it is the least of the larger pair minimum and the two
+//   pair maxima.  S does not increase with med5(J), so the estimate at x with its error
+//   bound bounds S from above.
+//   E: one error term for the ten cells: every value their M reads lies in patch rows
+//   1-4, columns 1-7, so M <= 8 vmax.
+__device__ __forceinline__ bool dense_bounds(const float (&v)[6 * 9], const SEstParams &sp,
+                                             float (&u)[10]) {
+    constexpr int PW = 9;
+    float x = INFINITY;
+#pragma unroll
+    for (int j = 0; j < PW; ++j) {
+        const float a = v[PW + j], b = v[2 * PW + j], c = v[3 * PW + j], d = v[4 * PW + j];
+        x = fminf(x, min3f(fmaxf(fminf(a, b), fminf(c, d)), fmaxf(a, b), fmaxf(c, d)));
+    }
+    const float R = r_bound(x, sp);
+    float vmax = 0.0f;
+#pragma unroll
+    for (int i = 1; i <= 4; ++i)
+#pragma unroll
+        for (int j = 1; j <= 7; ++j)
+            vmax = fmaxf(vmax, fabsf(v[i * PW + j]));
+    const float E = (8.0f * vmax) * R * 0x1p-19f;
+    const float Rp = fmaf(R, 0x1p-19f, R);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const int pc = (i + 2) * PW + (j + 2);
+            u[i * 5 + j] = s_upper(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], Rp, E);
+        }
+    return R < INFINITY && vmax <= 0x1p96f;
 }
 
 // S exactly as the definition evaluates it (binary64, in its operation order), at the
@@ -576,14 +618,11 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     }
 
     // Over [y0-2, y0+TY+2) x [x0-2, x0+TX+2), in 2 x 5 cell tiles (one per thread and
-    // pass).  Dense pass: a lower bound x of med5(J) shared by the tile's ten windows (the
-    // least over the nine columns of its 6 x 9 patch of the second smallest of patch rows
-    // 1-4: every window holds five of those columns, each including rows 1-4 and so three
-    // values at or above that second smallest, so 15 of its 25 values are >= x); S does
-    // not increase with med5(J), so the estimate at x with its error bound bounds S from
-    // above, and H' = the in-frame cells where that bound exceeds sigclip (less a margin)
-    // holds H.
+    // pass).  Dense pass: the upper bound of S from a lower bound of med5(J) shared by the
+    // tile's ten windows (dense_bounds); H' = the in-frame cells where that bound exceeds
+    // sigclip (less a margin) holds H.
     constexpr int TTY = 2, TTX = 5, PW = TTX + 4;
+    static_assert(TTY == 2 && TTX == 5, "dense_bounds takes 2 x 5 cell tiles");
     constexpr int NTY = (L::SH + TTY - 1) / TTY, NTX = (L::SW + TTX - 1) / TTX;
     const SEstParams sp = sest_params(f);
 #pragma unroll 1
@@ -593,33 +632,13 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
         const int tx = ti / NTY;
         const int r5 = min((ti - tx * NTY) * TTY, L::SH - TTY);
         const int c5 = min(tx * TTX, L::SW - TTX);
-        float v[(TTY + 4) * PW];
+        float v[(TTY + 4) * PW], u[TTY * TTX];
 #pragma unroll
         for (int i = 0; i < TTY + 4; ++i)
 #pragma unroll
             for (int j = 0; j < PW; ++j)
                 v[i * PW + j] = sJ[(r5 + i) * L::JWP + c5 + j];
-        // the second smallest of four values: whichever pair holds the smallest keeps its
-        // larger value as a candidate, the other pair both of its values, so it is the
-        // least of the larger pair minimum and the two pair maxima
-        float x = INFINITY;
-#pragma unroll
-        for (int j = 0; j < PW; ++j) {
-            const float a = v[PW + j], b = v[2 * PW + j], c = v[3 * PW + j], d = v[4 * PW + j];
-            x = fminf(x, min3f(fmaxf(fminf(a, b), fminf(c, d)), fmaxf(a, b), fmaxf(c, d)));
-        }
-        const float R = r_bound(x, sp);
-        // one error term for the tile's cells: every value their M reads lies in patch
-        // rows 1-4, columns 1-7, so M <= 8 vmax
-        float vmax = 0.0f;
-#pragma unroll
-        for (int i = 1; i <= 4; ++i)
-#pragma unroll
-            for (int j = 1; j <= 7; ++j)
-                vmax = fmaxf(vmax, fabsf(v[i * PW + j]));
-        const bool bound_ok = R < INFINITY && vmax <= 0x1p96f;
-        const float E = (8.0f * vmax) * R * 0x1p-19f;
-        const float Rp = fmaf(R, 0x1p-19f, R);
+        const bool bound_ok = dense_bounds(v, sp, u);
         const int gx0 = x0 - 2 + c5;
         // in-frame columns of the tile's five, as a bit mask
         const uint32_t colmask = (gx0 >= 0 && gx0 + TTX <= W)
@@ -630,11 +649,8 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
         for (int i = 0; i < TTY; ++i) {
             uint32_t bits = 0u;
 #pragma unroll
-            for (int j = 0; j < TTX; ++j) {
-                const int pc = (i + 2) * PW + (j + 2);
-                bits |= s_may_exceed(v[pc], v[pc - PW], v[pc + PW], v[pc - 1], v[pc + 1], Rp, E,
-                                     sc_lo) ? 1u << j : 0u;
-            }
+            for (int j = 0; j < TTX; ++j)
+                bits |= u[i * TTX + j] > sc_lo ? 1u << j : 0u;
             // where the analysis of the estimate does not hold at the bound, every cell
             bits = bound_ok ? bits : (1u << TTX) - 1u;
             const int gy = y0 - 2 + r5 + i;
@@ -1189,9 +1205,40 @@ __global__ __launch_bounds__(kThreads) void k_debug_s_estimate(DevFrame f,
     out_err[t] = err;
 }
 
+// The detection's dense upper bound of S at every pixel of one frame: 2 x 5 cell tiles
+// aligned at the frame's origin, one per thread, each from its clamped 6 x 9 patch;
+// INFINITY where the bound's analysis does not hold.
+__global__ __launch_bounds__(kThreads) void k_debug_s_bound(DevFrame f, float *__restrict__ out_u) {
+    const int H = f.H, W = f.W;
+    const int ntx = (W + 4) / 5, nty = (H + 1) / 2;
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= (long long)ntx * nty)
+        return;
+    const int y0 = (int)(t / ntx) * 2, x0 = (int)(t % ntx) * 5;
+    float v[6 * 9], u[10];
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+        for (int j = 0; j < 9; ++j)
+            v[i * 9 + j] = f.img[(size_t)clampi(y0 - 2 + i, H) * W + clampi(x0 - 2 + j, W)];
+    const bool ok = dense_bounds(v, sest_params(f), u);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 5; ++j)
+            if (y0 + i < H && x0 + j < W)
+                out_u[(size_t)(y0 + i) * W + x0 + j] = ok ? u[i * 5 + j] : INFINITY;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_debug_s_bound(const DevFrame &f, float *out_u, hipStream_t s) {
+    const size_t n = (size_t)((f.W + 4) / 5) * (size_t)((f.H + 1) / 2);
+    k_debug_s_bound<<<(unsigned int)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(f, out_u);
+    return hipGetLastError();
+}
 
 hipError_t launch_debug_s_estimate(const DevFrame &f, float *out_s, float *out_err,
                                    hipStream_t s) {

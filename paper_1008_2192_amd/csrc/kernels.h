@@ -189,6 +189,9 @@ hipError_t launch_debug_s_estimate(const DevFrame &f, float *out_s, float *out_e
                                    hipStream_t s);
 hipError_t launch_debug_median5_f64(const double *in, int H, int W, double *out,
                                    hipStream_t s);
+// The detection's dense upper bound of S at every pixel of one frame (+inf where its
+// analysis does not hold), for parity tests of the bound.
+hipError_t launch_debug_s_bound(const DevFrame &f, float *out_u, hipStream_t s);
 // n FP32 elements copied by 4-byte buffer loads and stores (counter calibration).
 hipError_t launch_debug_copy_b32(const float *src, float *dst, long long n, hipStream_t s);
 hipError_t launch_debug_fp64(const double *x, const double *y, int n, double *out_sqrt,

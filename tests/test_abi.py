@@ -169,8 +169,11 @@ def test_counting_and_debug_entry_validation(L):
     assert L.crb_debug_detect_exact(None, ctypes.byref(fr), a) == -1
     assert L.crb_debug_s_estimate(a, ctypes.byref(fr), None, b) == -1
     assert L.crb_debug_s_estimate(a, ctypes.byref(fr), b, ctypes.c_void_p((1 << 41) + 4)) == -1
+    assert L.crb_debug_s_bound(a, ctypes.byref(fr), None) == -1
+    assert L.crb_debug_s_bound(a, ctypes.byref(fr), ctypes.c_void_p((1 << 40) + 4)) == -1
     fr.gain = 0.0
     assert L.crb_debug_s_estimate(a, ctypes.byref(fr), b, ctypes.c_void_p(1 << 42)) == -1
+    assert L.crb_debug_s_bound(a, ctypes.byref(fr), b) == -1
     assert L.crb_set_option(_lib.CRB_OPT_INCREMENTAL, 2) == -1
     assert L.crb_set_option(_lib.CRB_OPT_INCREMENTAL, 0) == 0
 

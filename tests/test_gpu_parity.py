@@ -178,6 +178,15 @@ def test_s_estimate_error_bound(case):
         f"{int(undecided.sum())} px undecided at sigclip, {int((S > p['sigclip']).sum())} hot")
     assert (gap <= err).all(), case
     assert undecided.sum() <= 2, case
+    # the dense bound the detection takes its candidates from: above S everywhere, and
+    # its candidates hold every pixel of S > sigclip
+    u = _lib.debug_s_bound(torch.from_numpy(img).to(DEV), **p)
+    torch.cuda.synchronize()
+    u = u.cpu().numpy().astype(np.float64)
+    log(f"dense bound case {case}: min (u - S) / (1 + S) = {float(((u - S) / (1 + S)).min()):.3g}, "
+        f"{int((u > p['sigclip']).sum())} candidates for {int((S > p['sigclip']).sum())} hot")
+    assert (u >= S).all(), case
+    assert (u > np.float64(np.float32(p["sigclip"]) * np.float32(1 - 2.0 ** -20)))[S > p["sigclip"]].all()
     codes = _lib.debug_detect(torch.from_numpy(img).to(DEV), **p)
     torch.cuda.synchronize()
     near = dilate(S > p["sigclip"], 2)
