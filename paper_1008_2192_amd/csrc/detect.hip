@@ -87,27 +87,41 @@ __device__ __forceinline__ SEstParams sest_params(const DevFrame &f) {
     return p;
 }
 
+// The sum l4 over the four sub-pixels of max(2c - v1 - v2, 0) (v1 in {up, dn}, v2 in
+// {lf, rt}), which is 4 L+ at a pixel of value c with 4-neighbours up, dn, lf, rt.  The
+// terms pair up by their vertical neighbour: with a = 2c - up, max(a - lf, 0) +
+// max(a - rt, 0) = max(2a - (lf + rt), a - min(lf, rt), 0) (the first argument wins when
+// a is above both horizontal neighbours, the second when it lies between them, 0 below
+// both), and the same with b = 2c - dn.  Evaluated as written (two FMAs for a and b,
+// lf + rt, the minimum, per pair one FMA, one subtraction and a max3, one final
+// addition; 11 operations where the term-by-term sum takes 13), with u = 2^-24 and round
+// to nearest: each pair is within 2u M_a of its exact value, M_a = 4|c| + 2|up| + |lf| +
+// |rt| (likewise M_b), and the sum within 3u (M_a + M_b) = 6u M of 4 L+, M = 4|c| + |up|
+// + |dn| + |lf| + |rt|.
+__device__ __forceinline__ float lplus4(float c, float up, float dn, float lf, float rt) {
+    const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
+    const float s = lf + rt, m = fminf(lf, rt);
+    return max3f(fmaf(2.0f, a, -s), a - m, 0.0f) + max3f(fmaf(2.0f, b, -s), b - m, 0.0f);
+}
+
 // FP32 estimate s of S at a pixel of value c with 4-neighbours up, dn, lf, rt and
 // med5(J) = m5, and a bound err >= |s - S|, S being the binary64 value of the
 // definition (S = L+ / (2N), L+ = a quarter of the sum over the four sub-pixels of
 // max(2c - v1 - v2, 0), N = sqrt(g m + rn^2) / g).  Error analysis, u = 2^-24,
 // round to nearest with FP32 denormals preserved, M = 4|c| + |up| + |dn| + |lf| + |rt|:
-//   each clipped sub-pixel term (one FMA, one subtraction) is within 2u of its
-//     M-part, the four M-parts sum to 2M, and the three additions add 4u M: the
-//     sub-pixel sum l4 is 4 L+ within 8.01 u M;
+//   the sub-pixel sum l4 (lplus4) is 4 L+ within 6.01 u M;
 //   t = g m + rn^2 (positive terms, m itself rounded once) carries at most 3.03 u
 //     relative error, so t^-1/2 at most 1.52 u; the reciprocal square root (v_rsq_f32,
 //     within 1 ulp = 2u), the scaling by g/8 (exact) and the two products add 2u + 2u;
 //   the binary64 evaluation is within 2^-49 (M R + S) of the exact value;
-// so |s - S| <= 8.01 u M R + 5.52 u s with R = g/(8 sqrt t), which err = 2^-19 (M R + s)
-// overstates four-fold (the s-term tolerates a reciprocal square root 14 ulp off).  Outside t in [2^-100, 2^100] and M <= 2^100 (where the
+// so |s - S| <= 6.01 u M R + 5.52 u s with R = g/(8 sqrt t), which err = 2^-19 (M R + s)
+// overstates at least four-fold (the s-term tolerates a reciprocal square root 14 ulp
+// off).  Outside t in [2^-100, 2^100] and M <= 2^100 (where the
 // analysis has no overflow, underflow or domain edge) s = err = +inf, which sends every
 // decision that reads the pixel to the binary64 evaluation.
 __device__ __forceinline__ float s_estimate(float c, float up, float dn, float lf, float rt,
                                             float m5, const SEstParams &p, float &err) {
-    const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
-    const float l4 = (fmaxf(a - lf, 0.0f) + fmaxf(a - rt, 0.0f)) +
-                     (fmaxf(b - lf, 0.0f) + fmaxf(b - rt, 0.0f));
+    const float l4 = lplus4(c, up, dn, lf, rt);
     float m = m5 + p.sky;
     m = (m <= 0.0f) ? 1e-4f : m;
     const float t = fmaf(p.gain, m, p.rn2);
@@ -134,25 +148,14 @@ __device__ __forceinline__ float r_bound(float x, const SEstParams &p) {
 
 // An upper bound of S at a pixel of value c with 4-neighbours up, dn, lf, rt, given
 // Rp = R (1 + 2^-19) rounded, R = r_bound(x) finite for a lower bound x of its med5(J),
-// and E = 2^-19 * 8 v * R with v >= each |value| read and 8 v <= 2^100.
-//   The four clipped sub-pixel terms pair up by their vertical neighbour: with
-//   a = 2c - up, the two terms max(a - lf, 0) + max(a - rt, 0) equal
-//   max(2a - (lf + rt), a - min(lf, rt), 0) (the first argument wins when a is above both
-//   horizontal neighbours, the second when it lies between them, 0 below both), and the
-//   same with b = 2c - dn.  Evaluated as written (two FMAs for a and b, lf + rt, the
-//   minimum, per pair one FMA, one subtraction and a max3, one final addition), each pair
-//   is within 2u (M_a) of its exact value, M_a = 4|c| + 2|up| + |lf| + |rt| (likewise
-//   M_b), and the sum within 3u (M_a + M_b) = 6u M of 4 L+ (u = 2^-24, M as in
-//   s_estimate).
-//   With R's own error (at most 5u relative, as in s_estimate), S <= (l4 + 6u M) R (1+5u),
-//   while fl(l4 Rp + E) >= l4 R (1 + 2^-19 - 2.1u) + E (1 - u) and E >= 32u M R (1 - u):
-//   the returned value exceeds S, so where it is at most sigclip (less 2^-20), S <= sigclip.
+// and E = 2^-19 * 8 v * R with v >= each |value| read and 8 v <= 2^100.  With l4 =
+// lplus4 (within 6u M of 4 L+) and R's own error (at most 5u relative, as in
+// s_estimate), S <= (l4 + 6u M) R (1 + 5u), while fl(l4 Rp + E) >= l4 R (1 + 2^-19 -
+// 2.1u) + E (1 - u) and E >= 32u M R (1 - u): the returned value exceeds S, so where it
+// is at most sigclip (less 2^-20), S <= sigclip.
 __device__ __forceinline__ float s_upper(float c, float up, float dn, float lf, float rt,
                                          float Rp, float E) {
-    const float a = fmaf(2.0f, c, -up), b = fmaf(2.0f, c, -dn);
-    const float s = lf + rt, m = fminf(lf, rt);
-    const float l4 = max3f(fmaf(2.0f, a, -s), a - m, 0.0f) + max3f(fmaf(2.0f, b, -s), b - m, 0.0f);
-    return fmaf(l4, Rp, E);
+    return fmaf(lplus4(c, up, dn, lf, rt), Rp, E);
 }
 
 // The dense bound of a 2 x 5 cell tile from its 6 x 9 patch of J (patch row i, column j
@@ -715,42 +718,42 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     {
         float emax = 0.0f;
         unsigned int ncells = 0u;
+        const bool counting = (f.flags & kCountWork) != 0;
 #pragma unroll 1
         for (int it = tid; it < nquads; it += NT) {
-            {
-                const int q = (int)sQuads[it];
-                const int pr = q / L::SW, cc = q - pr * L::SW, r0 = 2 * pr;
-                float v[6 * 6];
+            const int q = (int)sQuads[it];
+            const int pr = q / L::SW, cc = q - pr * L::SW, r0 = 2 * pr;
+            float v[6 * 6];
 #pragma unroll
-                for (int i = 0; i < 6; ++i)
+            for (int i = 0; i < 6; ++i)
 #pragma unroll
-                    for (int j = 0; j < 6; ++j)
-                        v[i * 6 + j] = sJ[(r0 + i) * L::JWP + cc + j];
-                float m5[4];
-                med5_t2x2(v, m5);
+                for (int j = 0; j < 6; ++j)
+                    v[i * 6 + j] = sJ[(r0 + i) * L::JWP + cc + j];
+            float m5[4];
+            med5_t2x2(v, m5);
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < 2; ++i) {
 #pragma unroll
-                    for (int j = 0; j < 2; ++j) {
-                        const int pc = (i + 2) * 6 + (j + 2);
-                        float err;
-                        const float s = s_estimate(v[pc], v[pc - 6], v[pc + 6], v[pc - 1],
-                                                   v[pc + 1], m5[i * 2 + j], sp, err);
-                        const int rr = r0 + i, c = cc + j;
-                        sS[rr * L::SWP + c] = s;
-                        emax = fmaxf(emax, err);
-                        // H' keeps the cells whose estimate at med5(J) may exceed sigclip
-                        uint32_t *hw = &sHot[rr * L::HWP + (c >> 5)];
-                        const uint32_t hb = 1u << (c & 31);
-                        if (!(s + err > sc_lo) && (*hw & hb))
-                            atomicAnd(hw, ~hb);
-                        const int cy = rr - 2, cx = c - 2;
-                        const bool tile_cell = cy >= 0 && cy < TY && cx >= 0 && cx < TX;
+                for (int j = 0; j < 2; ++j) {
+                    const int pc = (i + 2) * 6 + (j + 2);
+                    float err;
+                    const float s = s_estimate(v[pc], v[pc - 6], v[pc + 6], v[pc - 1],
+                                               v[pc + 1], m5[i * 2 + j], sp, err);
+                    const int rr = r0 + i, c = cc + j;
+                    sS[rr * L::SWP + c] = s;
+                    emax = fmaxf(emax, err);
+                    // H' keeps the cells whose estimate at med5(J) may exceed sigclip
+                    uint32_t *hw = &sHot[rr * L::HWP + (c >> 5)];
+                    const uint32_t hb = 1u << (c & 31);
+                    if (!(s + err > sc_lo) && (*hw & hb))
+                        atomicAnd(hw, ~hb);
+                    const int cy = rr - 2, cx = c - 2;
+                    const bool tile_cell = cy >= 0 && cy < TY && cx >= 0 && cx < TX;
+                    if (counting)
                         ncells += tile_cell ? 1u : 0u;
-                        // S may exceed sigfrac * sigclip here (the cell's own bound)
-                        if (tile_cell && s + err > ll_lo)
-                            atomicOr(&sLow[cy * L::QW + (cx >> 5)], 1u << (cx & 31));
-                    }
+                    // S may exceed sigfrac * sigclip here (the cell's own bound)
+                    if (tile_cell && s + err > ll_lo)
+                        atomicOr(&sLow[cy * L::QW + (cx >> 5)], 1u << (cx & 31));
                 }
             }
         }
@@ -759,7 +762,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
         emax = __uint_as_float(__ockl_wfred_max_u32(__float_as_uint(emax)));
         if (lane == 0)
             atomicMax(&sErrBits, __float_as_uint(emax));
-        if (f.flags & kCountWork) {
+        if (counting) {
             ncells = __ockl_wfred_add_u32(ncells);
             if (lane == 0 && ncells)
                 atomicAdd(&sExactCells, ncells);
