@@ -283,6 +283,35 @@ def test_end_to_end_small(early_stop):
         compare_end_to_end(f, clean, mask, r)
 
 
+@pytest.mark.parametrize("tile_h", [16, 32, 64])
+def test_crowded_tiles_overflow_lists(tile_h):
+    """A frame with 15% of its pixels hit: tiles hold more work-set pixels than the
+    block's list (8 rows' worth) and more contrast pixels than its contrast list, so
+    the bitmap and in-lane fallbacks run; codes and four iterations equal the oracle's
+    under each detection tile height."""
+    f = synth.render(128, 192, 77, sky_e=100.0, gain=2.0, readnoise=5.0, n_stars=40,
+                     star_fwhm=2.0, star_flux="lognormal", hit_coverage=0.15, hit_len=(1, 8),
+                     hit_amp=(200.0, 5000.0))
+    p = fparams(f)
+    tr = ref.iterate(f.img, np.zeros(f.img.shape, np.uint8), trace=True, **p)
+    near = dilate(tr["s"] > p["sigclip"], 2)
+    work = near & (tr["s"] > np.float64(np.float32(p["sigfrac"])) * p["sigclip"])
+    most = max(int(work[y:y + tile_h, x:x + 64].sum())
+               for y in range(0, 128, tile_h) for x in range(0, 192, 64))
+    assert most > 8 * tile_h, most          # the list overflows in some tile
+    try:
+        _lib.set_single_tuning(tile_h, 0, 0)
+        img = torch.from_numpy(f.img).to(DEV)
+        codes = _lib.debug_detect(img, **p)
+        clean, mask = _lib.lacosmic(img, niter=4, early_stop=False, **p)
+        torch.cuda.synchronize()
+    finally:
+        _lib.set_single_tuning(32, 0, 0)
+    check_codes(codes.cpu().numpy(), expected_codes(tr, p), near, tr, f"crowded t{tile_h}")
+    r = ref.lacosmic(f.img, niter=4, early_stop=False, **p)
+    compare_end_to_end(f, clean, mask, r)
+
+
 EXTREMES = [
     dict(sigclip=1.5),                       # many hot pixels: a dense work set
     dict(sigclip=50.0),                      # none
