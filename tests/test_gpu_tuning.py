@@ -4,7 +4,8 @@ The shapes: detection tiles of 16, 32 or 64 rows, launched one block per tile or
 persistent blocks taking tiles from ticket counters; grow and replacement as three
 launches with first-iteration strips of 8, 16 or 32 rows, or fused into one launch per
 iteration.  Each shape runs a batch of frames with ragged sizes (narrower and wider than
-a strip, widths that are and are not multiples of 16, single rows and columns) and must
+a strip, widths that are and are not multiples of 16, single rows and columns, and a
+frame crowded enough to overflow the detection's lists) and must
 reproduce the default shape's masks, cleaned images and counts exactly; the default is
 checked against the FP64 oracle.  Also: incremental detection under each tile height,
 graph plans re-captured after a change of shape, the single-frame options, the
@@ -44,6 +45,10 @@ def batch_frames():
     for (H, W, seed) in [(33, 97, 31), (1, 40, 32), (40, 1, 33), (70, 130, 35), (97, 65, 38),
                          (150, 2100, 39), (129, 1000, 40), (64, 1984, 41)]:
         out.append(synth.c1_density_frame(H, W, seed, 1.0, 5.0))
+    # 15% of the pixels hit: tiles overflow the work and contrast lists at every height
+    out.append(synth.render(128, 192, 77, sky_e=100.0, gain=2.0, readnoise=5.0, n_stars=40,
+                            star_fwhm=2.0, star_flux="lognormal", hit_coverage=0.15,
+                            hit_len=(1, 8), hit_amp=(200.0, 5000.0)))
     return out
 
 
