@@ -163,25 +163,24 @@ __device__ __forceinline__ float s_upper(float c, float up, float dn, float lf, 
 // >= S at cell (i, j) for every cell of the tile, unless the function returns false (R
 // not finite or a value above 2^96 in magnitude: the analysis of the bound does not
 // hold, and every cell must count as a candidate).
-//   x: a lower bound of med5(J) shared by the tile's ten windows, the least over the nine
-//   columns of the second smallest of patch rows 1-4 (every window holds five of those
-//   columns, each including rows 1-4 and so three values at or above that second
-//   smallest, so 15 of its 25 values are >= x).  The second smallest of four values:
-//   whichever pair holds the smallest keeps its larger value as a candidate, the other
-//   pair both of its values, so it is the least of the larger pair minimum and the two
-//   pair maxima.  S does not increase with med5(J), so the estimate at x with its error
-//   bound bounds S from above.
+//   x: a lower bound of med5(J) shared by the tile's ten windows, the least value of
+//   patch rows 1-4 (every window holds those four rows of its five columns, so 20 of its
+//   25 values are >= x; 18 three-input minima).  S does not increase with med5(J), so
+//   the estimate at x with its error bound bounds S from above.  (The least over the
+//   columns of each column's second smallest in rows 1-4 is a tighter bound, with 15
+//   values >= it, but costs 63 operations; with the least value H' grows by about 3%
+//   and the region of exact med5(J) by about 7%.)
 //   E: one error term for the ten cells: every value their M reads lies in patch rows
 //   1-4, columns 1-7, so M <= 8 vmax.
 __device__ __forceinline__ bool dense_bounds(const float (&v)[6 * 9], const SEstParams &sp,
                                              float (&u)[10]) {
-    constexpr int PW = 9;
-    float x = INFINITY;
+    constexpr int PW = 9, NV = 4 * PW;
+    float x = v[PW];
 #pragma unroll
-    for (int j = 0; j < PW; ++j) {
-        const float a = v[PW + j], b = v[2 * PW + j], c = v[3 * PW + j], d = v[4 * PW + j];
-        x = fminf(x, min3f(fmaxf(fminf(a, b), fminf(c, d)), fmaxf(a, b), fmaxf(c, d)));
-    }
+    for (int k = 1; k + 1 < NV; k += 2)
+        x = min3f(x, v[PW + k], v[PW + k + 1]);
+    if (NV % 2 == 0)
+        x = fminf(x, v[PW + NV - 1]);
     const float R = r_bound(x, sp);
     float vmax = 0.0f;
 #pragma unroll
@@ -731,30 +730,35 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
                     v[i * 6 + j] = sJ[(r0 + i) * L::JWP + cc + j];
             float m5[4];
             med5_t2x2(v, m5);
+            // a quad's two columns (cc even) share their word of each bitmap, and lie both
+            // inside the tile's columns or both outside
+            const int cx = cc - 2;
+            const bool tile_cols = cx >= 0 && cx < TX;
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
+                const int rr = r0 + i, cy = rr - 2;
+                const bool tile_row = tile_cols && cy >= 0 && cy < TY;
+                uint32_t drop = 0u, low = 0u;
 #pragma unroll
                 for (int j = 0; j < 2; ++j) {
                     const int pc = (i + 2) * 6 + (j + 2);
                     float err;
                     const float s = s_estimate(v[pc], v[pc - 6], v[pc + 6], v[pc - 1],
                                                v[pc + 1], m5[i * 2 + j], sp, err);
-                    const int rr = r0 + i, c = cc + j;
-                    sS[rr * L::SWP + c] = s;
+                    sS[rr * L::SWP + cc + j] = s;
                     emax = fmaxf(emax, err);
                     // H' keeps the cells whose estimate at med5(J) may exceed sigclip
-                    uint32_t *hw = &sHot[rr * L::HWP + (c >> 5)];
-                    const uint32_t hb = 1u << (c & 31);
-                    if (!(s + err > sc_lo) && (*hw & hb))
-                        atomicAnd(hw, ~hb);
-                    const int cy = rr - 2, cx = c - 2;
-                    const bool tile_cell = cy >= 0 && cy < TY && cx >= 0 && cx < TX;
-                    if (counting)
-                        ncells += tile_cell ? 1u : 0u;
+                    drop |= !(s + err > sc_lo) ? 1u << ((cc + j) & 31) : 0u;
                     // S may exceed sigfrac * sigclip here (the cell's own bound)
-                    if (tile_cell && s + err > ll_lo)
-                        atomicOr(&sLow[cy * L::QW + (cx >> 5)], 1u << (cx & 31));
+                    low |= s + err > ll_lo ? 1u << ((cx + j) & 31) : 0u;
                 }
+                uint32_t *hw = &sHot[rr * L::HWP + (cc >> 5)];
+                if (drop & *hw)
+                    atomicAnd(hw, ~drop);
+                if (tile_row && low)
+                    atomicOr(&sLow[cy * L::QW + (cx >> 5)], low);
+                if (counting)
+                    ncells += tile_row ? 2u : 0u;
             }
         }
         // non-negative floats order as their bit patterns: the device library's

@@ -2,9 +2,8 @@
 
 Algorithmic work is counted with every plane computed once (the halo recomputation
 of a tiled execution is overhead, not algorithm):
-  * dense, per image pixel: a lower bound of med5(J) (the second smallest of the four
-    middle rows of each column, six operations shared by a cell's two rows, and the least
-    of them over each 2 x 5 cell's nine columns); L+; N at that bound
+  * dense, per image pixel: a lower bound of med5(J) (the least of the four middle rows
+    of each 2 x 5 cell's nine columns, 18 three-input minima per cell); L+; N at that bound
     (once per cell) and the upper bound of S it gives; the test of that bound against
     sigclip, which marks the pixels near which the other statistics can matter;
   * per pixel whose med5(J) is selected exactly (the cells within 4 of such a mark,
@@ -44,9 +43,9 @@ NOISE_OPS = 1 + 1 + 1 + 1 + 1 + 1         # +sky, floor, g*m, +rn^2, sqrt, /g
 S_OPS = 2                                 # 2N, L+/(2N)
 HOT_OPS = 1                               # S > sigclip
 MED3_AT_OPS = 3 * 3 + 3 + 1               # one med3(J) value from its 3 x 3 window
-# lower bound of med5(J): 6 min/max operations per column for a pair of rows (the second
-# smallest of its four middle values), then the least of the 9 columns per 2 x 5 cell
-BOUND_OPS = 6 / 2 + 8 / 10
+# lower bound of med5(J): the least of the 36 values of a 2 x 5 cell's four middle rows
+# (18 three-input minima per cell)
+BOUND_OPS = 18 / 10
 BOUND_NOISE_OPS = NOISE_OPS / 10          # N at the bound, once per 2 x 5 cell
 # per work-set pixel, besides med5(S): S - med5(S), > sigclip, > sigfrac*sigclip
 WORK_OPS = 3
