@@ -629,10 +629,23 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
     const SEstParams sp = sest_params(f);
 #pragma unroll 1
     for (int ti = tid; ti < NTY * NTX; ti += NT) {
-        // column-major over the 2 x 5 tiles: with the J pitch this spreads a wave's patch
-        // loads over the LDS banks
-        const int tx = ti / NTY;
-        const int r5 = min((ti - tx * NTY) * TTY, L::SH - TTY);
+        // column-major over the 2 x 5 tiles in groups of 16 row pairs, then the remaining
+        // row pairs: a row pair's loads sit 2 * 73 = 18 banks (mod 32) after the previous
+        // one's, so the 16 row pairs of a column tile take 16 distinct banks of one parity
+        // and a half-wave's two column tiles (5 columns apart) the two parities; the
+        // patch loads of a whole group are free of bank conflicts
+        constexpr int NFULL = (NTY / 16) * 16, NREM = NTY - NFULL;
+        int tx, k;
+        if (ti < NFULL * NTX) {
+            const int g = ti / (16 * NTX), e = ti - g * (16 * NTX);
+            tx = e >> 4;
+            k = 16 * g + (e & 15);
+        } else {
+            const int e = ti - NFULL * NTX;
+            tx = NREM > 0 ? e / (NREM > 0 ? NREM : 1) : 0;
+            k = NFULL + (e - tx * NREM);
+        }
+        const int r5 = min(k * TTY, L::SH - TTY);
         const int c5 = min(tx * TTX, L::SW - TTX);
         float v[(TTY + 4) * PW], u[TTY * TTX];
 #pragma unroll
