@@ -634,7 +634,9 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
         // one's, so the 16 row pairs of a column tile take 16 distinct banks of one parity
         // and a half-wave's two column tiles (5 columns apart) the two parities; the
         // patch loads of a whole group are free of bank conflicts
-        constexpr int NFULL = (NTY / 16) * 16, NREM = NTY - NFULL;
+        static_assert(2 * L::JWP % 32 == 18, "the bank spread assumes a J pitch of 9 mod 32");
+        constexpr int NFULL = (NTY / 16) * 16;
+        constexpr int NREM = NTY > NFULL ? NTY - NFULL : 1;     // (unused when 0)
         int tx, k;
         if (ti < NFULL * NTX) {
             const int g = ti / (16 * NTX), e = ti - g * (16 * NTX);
@@ -642,7 +644,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
             k = 16 * g + (e & 15);
         } else {
             const int e = ti - NFULL * NTX;
-            tx = NREM > 0 ? e / (NREM > 0 ? NREM : 1) : 0;
+            tx = e / NREM;
             k = NFULL + (e - tx * NREM);
         }
         const int r5 = min(k * TTY, L::SH - TTY);
