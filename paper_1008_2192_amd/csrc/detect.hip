@@ -275,16 +275,22 @@ __device__ __forceinline__ bool contrast_exact(const float *sJ, int jp, int y0, 
     return n >= 25;
 }
 
-// The switching values of the contrast test below, from med3 (m3) and med5(J) (m5) at
-// the pixel: a window value x > t_sure makes the test hold for every S' >= lo, one with
-// x >= t_maybe lets it hold for some S' <= hi.
-__device__ __forceinline__ void contrast_thresholds(float m3, float m5, const SEstParams &p,
-                                                    float lo, float hi, float inv_olim,
-                                                    float &t_sure, float &t_maybe) {
-    float m = m5 + p.sky;
-    m = (m <= 0.0f) ? 1e-4f : m;
-    const float t = fmaf(p.gain, m, p.rn2);
-    const float N = t * __builtin_amdgcn_rsqf(t) * p.inv_gain;
+// N at a pixel from its FP32 estimate s = l4 R of S (s_estimate; R = (g/8) rsq(t), and l4
+// the pixel's L+ sum formed as the estimate formed it): N = 1 / (8 R) = l4 / (8 s).  R is
+// within 4.52u of g / (8 sqrt(t)) for the definition's t (t to 3.03u, so its -1/2 power
+// to 1.52u; the reciprocal square root to 1 ulp = 2u; the product by g/8 to u), s adds
+// u and the division u: N is within 6.52u of the definition's (u = 2^-24), for any
+// s > 0 with a finite error bound.
+__device__ __forceinline__ float noise_from_estimate(float l4, float s) {
+    return l4 / (8.0f * s);
+}
+
+// The switching values of the contrast test below, from med3 (m3) and N at the pixel:
+// a window value x > t_sure makes the test hold for every S' >= lo, one with x >= t_maybe
+// lets it hold for some S' <= hi.
+__device__ __forceinline__ void contrast_thresholds(float m3, float N, float lo, float hi,
+                                                    float inv_olim, float &t_sure,
+                                                    float &t_maybe) {
     const float klo = N * lo * inv_olim, khi = N * hi * inv_olim;
     t_sure = (m3 - klo) + fmaf(0x1p-19f, fabsf(m3) + klo, 0x1p-126f);
     t_maybe = (m3 - khi) - fmaf(0x1p-19f, fabsf(m3) + khi, 0x1p-126f);
@@ -303,22 +309,20 @@ __device__ __forceinline__ void contrast_thresholds(float m3, float m5, const SE
 //   widened or narrowed by 2^-21 relative decides this for the whole interval (the
 //   caller does, before listing the pixel).
 //   Otherwise the test holds at x iff m3 - x < K (1 + e), K = N S'/objlim, |e| <=
-//   4 * 2^-53.  K from N in FP32 (within 8u: t = g m + rn^2 to 3.03u, its reciprocal
-//   square root to 1 ulp, two products) and two more products is within 11u, so x above
-//   T = m3 - K up to a band of 2^-19 (|m3| + K) + 2^-126 (three-fold the roundings)
-//   decides the test.  The test is larger for larger S', so lo bounds its certain
-//   holding and hi its possible holding.
-// m5 is med5(J) at the pixel; lane l < 49 takes the med3 value of window cell
-// (l / 7 - 3, l % 7 - 3), and ballots count them.
+//   4 * 2^-53.  K from N in FP32 (within 8u: noise_from_estimate gives 6.52u) and two
+//   more products is within 11u, so x above T = m3 - K up to a band of 2^-19 (|m3| + K)
+//   + 2^-126 (three-fold the roundings) decides the test.  The test is larger for larger
+//   S', so lo bounds its certain holding and hi its possible holding.
+// N is the noise at the pixel (noise_from_estimate); lane l < 49 takes the med3 value of
+// window cell (l / 7 - 3, l % 7 - 3), and ballots count them.
 __device__ __forceinline__ int contrast_by_count(const float *sJ, int jp, int y0, int x0,
-                                                 int H, int W, int r, int c, float m5,
-                                                 const SEstParams &p, float lo, float hi,
-                                                 float inv_olim, int lane) {
+                                                 int H, int W, int r, int c, float N, float lo,
+                                                 float hi, float inv_olim, int lane) {
     const int l49 = lane < 49 ? lane : 24;
     const float x = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, l49 / 7 - 3, l49 % 7 - 3), jp);
     const float m3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 24));
     float t_sure, t_maybe;
-    contrast_thresholds(m3, m5, p, lo, hi, inv_olim, t_sure, t_maybe);
+    contrast_thresholds(m3, N, lo, hi, inv_olim, t_sure, t_maybe);
     const int sure = __popcll(__ballot(lane < 49 && x > t_sure));
     const int maybe = __popcll(__ballot(lane < 49 && x >= t_maybe));
     return sure >= 25 ? 1 : (maybe < 25 ? 0 : -1);
@@ -327,12 +331,11 @@ __device__ __forceinline__ int contrast_by_count(const float *sJ, int jp, int y0
 // The same test by one thread (for pixels beyond the contrast list): the 49 med3 values
 // one after another.
 __device__ __forceinline__ int contrast_by_count_lane(const float *sJ, int jp, int y0, int x0,
-                                                      int H, int W, int r, int c, float m5,
-                                                      const SEstParams &p, float lo, float hi,
-                                                      float inv_olim) {
+                                                      int H, int W, int r, int c, float N,
+                                                      float lo, float hi, float inv_olim) {
     const float m3 = med3_at(med3_cell(sJ, jp, y0, x0, H, W, r, c, 0, 0), jp);
     float t_sure, t_maybe;
-    contrast_thresholds(m3, m5, p, lo, hi, inv_olim, t_sure, t_maybe);
+    contrast_thresholds(m3, N, lo, hi, inv_olim, t_sure, t_maybe);
     int sure = 0, maybe = 0;
 #pragma unroll 1
     for (int i = 0; i < 7; ++i) {
@@ -487,12 +490,12 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
         sConCount;
     double *const sX = reinterpret_cast<double *>(sS);
     __shared__ uint16_t sList[kListMax];                    // work set Q' (up to kListMax)
-    // pixels whose contrast test is left to the contrast phase: position, S' interval
+    // pixels whose contrast test is left to the contrast phase: position, S' interval, N
     __shared__ uint32_t sConInfo[kConMax];
-    __shared__ float sConLo[kConMax], sConHi[kConMax], sConM5[kConMax];
+    __shared__ float sConLo[kConMax], sConHi[kConMax], sConN[kConMax];
     static_assert(sizeof(sJ) + sizeof(sS) + sizeof(sCode) + sizeof(sHotP) + sizeof(sU) +
                           sizeof(sUpre) + sizeof(sLow) + sizeof(sList) + sizeof(sConInfo) +
-                          sizeof(sConLo) + sizeof(sConHi) + sizeof(sConM5) + 7 * 4 + 16 <=
+                          sizeof(sConLo) + sizeof(sConHi) + sizeof(sConN) + 7 * 4 + 16 <=
                       L::kLdsBudget,
                   "the LDS of a detection block must let its resident blocks share a CU");
 
@@ -872,23 +875,19 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
                     unc = true;
                 } else {
                     const unsigned int slot = atomicAdd(&sConCount, 1u);
-                    // med5(J) at the pixel, for N
-                    float w5[25], m5[1];
-#pragma unroll
-                    for (int i = 0; i < 5; ++i)
-#pragma unroll
-                        for (int j = 0; j < 5; ++j)
-                            w5[i * 5 + j] = sJ[(r + 2 + i) * L::JWP + c + 2 + j];
-                    med5_t1x1(w5, m5);
+                    // N from the pixel's estimate (w[12], positive here) and its L+ sum
+                    const float *pj = &sJ[(r + 4) * L::JWP + c + 4];
+                    const float nz = noise_from_estimate(
+                        lplus4(pj[0], pj[-L::JWP], pj[L::JWP], pj[-1], pj[1]), w[12]);
                     if (slot < (unsigned int)kConMax) {
                         sConInfo[slot] = (uint32_t)pos | (l1 ? 1u << 16 : 0u);
                         sConLo[slot] = lo;
                         sConHi[slot] = hi;
-                        sConM5[slot] = m5[0];
+                        sConN[slot] = nz;
                         listed = true;
                     } else {
                         const int t = contrast_by_count_lane(sJ, L::JWP, y0, x0, H, W, r, c,
-                                                             m5[0], sp, lo, hi, f.inv_olim);
+                                                             nz, lo, hi, f.inv_olim);
                         first = t > 0;
                         unc = t < 0;
                         ncontrast += unc ? 0u : 1u;
@@ -920,7 +919,7 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
             const uint32_t info = sConInfo[it];
             const int pos = (int)(info & 0xFFFFu);
             const int r = pos / TX, c = pos - r * TX;
-            const int t = contrast_by_count(sJ, L::JWP, y0, x0, H, W, r, c, sConM5[it], sp,
+            const int t = contrast_by_count(sJ, L::JWP, y0, x0, H, W, r, c, sConN[it],
                                             sConLo[it], sConHi[it], inv_olim, lane);
             if (lane == 0) {
                 if (t < 0) {

@@ -10,9 +10,10 @@ of a tiled execution is overhead, not algorithm):
     counted by the kernel on the tile's own pixels): the med5 network, N and S;
   * per work-set pixel (within 2 of an S > sigclip pixel, S > sigfrac * sigclip):
     med5 of S, S' and the two threshold compares;
-  * per contrast test (S' > sigclip): med5(J) at the pixel (single-output network) and
-    N from it, the 49 med3(J) values of the med7 window (13 operations each: three
-    sorted columns of three, then three column extremes and their median), and the test
+  * per contrast test (S' > sigclip): N from the pixel's estimate of S and its L+ sum
+    (N = L+ / (2 S): the pixel's med5(J) was selected exactly and counted above), the 49
+    med3(J) values of the med7 window (13 operations each: three sorted columns of three,
+    then three column extremes and their median), and the test
     S'/F^ > objlim, decided by comparing those values with the test's switching value
     and counting them (the test holds at med7 iff it holds at 25 or more of them), which
     is less work than selecting med7.
@@ -49,10 +50,10 @@ BOUND_OPS = 18 / 10
 BOUND_NOISE_OPS = NOISE_OPS / 10          # N at the bound, once per 2 x 5 cell
 # per work-set pixel, besides med5(S): S - med5(S), > sigclip, > sigfrac*sigclip
 WORK_OPS = 3
-# per contrast test: N (6); the floor test S'/0.01 > objlim, N S'/objlim, the switching
-# value and its band (6); two comparisons and two counts per window value (4 x 49); the
-# two count tests (2)
-CONTRAST_OPS = NOISE_OPS + 6 + 4 * 49 + 2
+# per contrast test: N as L+ / (2 S) from the pixel's S (2); the floor test S'/0.01 >
+# objlim, N S'/objlim, the switching value and its band (6); two comparisons and two
+# counts per window value (4 x 49); the two count tests (2)
+CONTRAST_OPS = 2 + 6 + 4 * 49 + 2
 
 
 @functools.lru_cache(maxsize=None)
@@ -80,8 +81,7 @@ def detect_ops() -> dict:
     return dict(dense=dense,
                 per_exact_pixel=network_ops_per_output("med5_t2x2") + NOISE_OPS + S_OPS,
                 per_work_pixel=network_ops_per_output("med5_t1x1") + WORK_OPS,
-                per_contrast=CONTRAST_OPS + 49 * MED3_AT_OPS +
-                network_ops_per_output("med5_t1x1"))
+                per_contrast=CONTRAST_OPS + 49 * MED3_AT_OPS)
 
 
 def detect_ops_per_launch(pixels: int, exact_pixels: float, work_pixels: float,
