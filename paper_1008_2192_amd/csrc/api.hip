@@ -234,7 +234,7 @@ static crb_status enqueue_single(const DevFrame &f, const LaunchCfg &cfg, hipStr
     for (int k = 1; e == hipSuccess && k <= f.niter; ++k) {
         e = launch_detect(nullptr, nullptr, 0, f, k, cfg, nullptr, s);
         if (e == hipSuccess)
-            e = launch_grow(nullptr, nullptr, 0, f, k, cfg, s);
+            e = launch_grow(nullptr, nullptr, 0, f, k, (f.flags & kFreshMask) != 0, cfg, s);
         if (e == hipSuccess && !fused)
             e = launch_replace(nullptr, 1, nullptr, f, k, replace_grid(npix), s);
     }
@@ -775,7 +775,8 @@ static crb_status plan_enqueue(crb_plan *p) {
                 (e = launch_detect(nullptr, nullptr, 0, f, k, cfg, nullptr, s)) == hipSuccess &&
                 (e = tmark_end(p)) == hipSuccess &&
                 (e = tmark_begin(p, kKindGrow)) == hipSuccess &&
-                (e = launch_grow(nullptr, nullptr, 0, f, k, cfg, s)) == hipSuccess &&
+                (e = launch_grow(nullptr, nullptr, 0, f, k, (f.flags & kFreshMask) != 0, cfg,
+                                 s)) == hipSuccess &&
                 (e = tmark_end(p)) == hipSuccess && !cfg.fused &&
                 (e = tmark_begin(p, kKindReplace)) == hipSuccess &&
                 (e = launch_replace(nullptr, 1, nullptr, f, k, replace_grid(npix), s)) ==
@@ -799,7 +800,8 @@ static crb_status plan_enqueue(crb_plan *p) {
                 hipSuccess &&
             (e = tmark_end(p)) == hipSuccess &&
             (e = tmark_begin(p, kKindGrow)) == hipSuccess &&
-            (e = launch_grow(p->d_frames, p->d_tgrow, p->ntgrow, none, k, cfg, s)) ==
+            // every frame of a plan carries kFreshMask
+            (e = launch_grow(p->d_frames, p->d_tgrow, p->ntgrow, none, k, true, cfg, s)) ==
                 hipSuccess &&
             (e = tmark_end(p)) == hipSuccess && !cfg.fused &&
             (e = tmark_begin(p, kKindReplace)) == hipSuccess &&

@@ -148,9 +148,12 @@ inline int detect_tiles(int H, int W, int tile_h) {
 }
 // Two-stage grow, new-flag count, cumulative mask and flagged list; with cfg.fused (and
 // no debug G2 plane) also the replacement, in one launch (then no list prefix and
-// replacement launch follow).  d_tiles lists 32-row strips of kGrowTX columns.
+// replacement launch follow).  d_tiles lists 32-row strips of kGrowTX columns.  fresh:
+// every frame of the launch carries kFreshMask (then iteration 1 reads no mask rows; the
+// frames without it are tested at run time either way).
 hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
-                       const DevFrame &single, int k, const LaunchCfg &cfg, hipStream_t s);
+                       const DevFrame &single, int k, bool fresh, const LaunchCfg &cfg,
+                       hipStream_t s);
 // Offsets of each frame's flagged list in one flat index space (batched path):
 // d_prefix[i] = sum of the list lengths of frames before i; d_prefix[n] = total.
 hipError_t launch_list_prefix(const DevFrame *d_frames, int nframes, int k,

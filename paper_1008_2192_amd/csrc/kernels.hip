@@ -159,12 +159,15 @@ __device__ __forceinline__ bool strip_near_first(const DevFrame &f, int y0, int 
 // One wave's strip: rows y0 .. y0+TYG-1 of the 992-pixel column group at x0.  With
 // ALIGNED (the width a multiple of 16) every load is branch-free and the code and mask
 // rows are fetched kAhead rows before their use, so several are in flight at once.
-template <int TYG, bool ALIGNED>
+// FRESH: known to be iteration 1 on a mask that detection has just cleared, whose rows
+// are then not read at all; other strips test for a fresh mask at run time and still
+// load the mask rows (so that the one variant keeps its registers unspilled).
+template <int TYG, bool ALIGNED, bool FRESH>
 __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, int k, int lane) {
     constexpr int kAhead = 4;
     const int H = f.H, W = f.W;
     // iteration 1 on a mask that detection has just cleared: nothing to read
-    const bool fresh = k == 1 && (f.flags & kFreshMask);
+    const bool fresh = FRESH || (k == 1 && (f.flags & kFreshMask));
     const int px = x0 - 16 + 16 * lane;                // first pixel of this lane's group
     const bool owner = lane >= 1 && lane <= kGrowTX / 16 && px < W;
     // from iteration 2 on the list already holds M_{k-1} and takes only the new flags
@@ -185,7 +188,8 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
 #pragma unroll
         for (int t = 0; t < kAhead; ++t) {
             cring[t] = load16_aligned(f.codes, y0 - 2 + t, px, H, W);
-            mring[t] = load16_aligned(f.mask, y0 + t, px, H, W);
+            if constexpr (!FRESH)
+                mring[t] = load16_aligned(f.mask, y0 + t, px, H, W);
         }
     }
 #pragma unroll
@@ -219,7 +223,9 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
             for (int q = 0; q < 4; ++q)
                 g2.d[q] = (hG0.d[q] | hG1.d[q] | hG2.d[q]) & lo2.d[q];
             Px16 mp;
-            if constexpr (ALIGNED) {
+            if constexpr (ALIGNED && FRESH) {
+                mp = Px16{};
+            } else if constexpr (ALIGNED) {
                 mp = mring[r % kAhead];
                 if (r + kAhead < TYG)
                     mring[r % kAhead] = load16_aligned(f.mask, y0 + r + kAhead, px, H, W);
@@ -288,7 +294,10 @@ __device__ __forceinline__ void grow_strip(const DevFrame &f, int y0, int x0, in
     }
 }
 
-template <int TYG>
+// FRESH: iteration 1, and every frame of the launch has a mask that detection has just
+// cleared (a kernel of its own: with both aligned variants in one kernel the 32-row
+// strip spills).
+template <int TYG, bool FRESH>
 // 3 waves per SIMD: at most 168 VGPRs (the 32-row strip needs about that many)
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void k_grow(
     const DevFrame *__restrict__ frames, const TileRef *__restrict__ tiles, DevFrame single,
@@ -321,9 +330,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     if (frame_skips(f, k))
         return;
     if ((f.W & 15) == 0)
-        grow_strip<TYG, true>(f, y0, x0, k, lane);
+        grow_strip<TYG, true, FRESH>(f, y0, x0, k, lane);
     else
-        grow_strip<TYG, false>(f, y0, x0, k, lane);
+        grow_strip<TYG, false, false>(f, y0, x0, k, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -927,7 +936,8 @@ static int grow_height(bool batch, const DevFrame &single, int k, const LaunchCf
 }
 
 hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int ntiles,
-                       const DevFrame &single, int k, const LaunchCfg &cfg, hipStream_t s) {
+                       const DevFrame &single, int k, bool fresh, const LaunchCfg &cfg,
+                       hipStream_t s) {
     constexpr int wpb = kThreads / 64;
     if (d_tiles && ntiles <= 0)
         return hipSuccess;
@@ -945,15 +955,25 @@ hipError_t launch_grow(const DevFrame *d_frames, const TileRef *d_tiles, int nti
     if (fused) {
         k_grow_replace<kGrowTYSmall><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
     } else {
+        fresh = fresh && k == 1;
         switch (ty) {
         case 8:
-            k_grow<8><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            if (fresh)
+                k_grow<8, true><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            else
+                k_grow<8, false><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
             break;
         case 16:
-            k_grow<16><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            if (fresh)
+                k_grow<16, true><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            else
+                k_grow<16, false><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
             break;
         case 32:
-            k_grow<32><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            if (fresh)
+                k_grow<32, true><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
+            else
+                k_grow<32, false><<<grid, kThreads, 0, s>>>(d_frames, d_tiles, single, k, n);
             break;
         default:
             return hipErrorInvalidValue;

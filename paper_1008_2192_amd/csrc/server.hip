@@ -395,7 +395,7 @@ static crb_status launch_round(crb_server *s) {
     if (e == hipSuccess)
         e = launch_detect(dfr, dtd, (int)ntd, none, 0, cfg, nullptr, s->compute);
     if (e == hipSuccess)
-        e = launch_grow(dfr, dtg, (int)ntg, none, 0, cfg, s->compute);
+        e = launch_grow(dfr, dtg, (int)ntg, none, 0, false, cfg, s->compute);
     if (e == hipSuccess)
         e = launch_list_prefix(dfr, n, 0, dpre, s->compute);
     if (e == hipSuccess)
