@@ -736,47 +736,77 @@ __device__ __forceinline__ void detect_tile(const DevFrame &f, int y0, int x0, i
         float emax = 0.0f;
         unsigned int ncells = 0u;
         const bool counting = (f.flags & kCountWork) != 0;
+        // The cells (rr, cc) and (rr, cc + 1) of a quad row (cc even), given their
+        // med5(J) and their 4-neighbours (u above, d below, l left of the first cell, r
+        // right of the second): the S estimates, the block's error bound, and one H' word
+        // and one low word updated per row.  A quad's two columns share their word of
+        // each bitmap and lie both inside the tile's columns or both outside.
+        auto exact_row = [&](int rr, int cc, float u0, float u1, float l, float c0, float c1,
+                             float r, float d0, float d1, float m0, float m1) {
+            const int cx = cc - 2, cy = rr - 2;
+            const bool tile_row = cx >= 0 && cx < TX && cy >= 0 && cy < TY;
+            float e0, e1;
+            const float s0 = s_estimate(c0, u0, d0, l, c1, m0, sp, e0);
+            const float s1 = s_estimate(c1, u1, d1, c0, r, m1, sp, e1);
+            sS[rr * L::SWP + cc] = s0;
+            sS[rr * L::SWP + cc + 1] = s1;
+            emax = fmaxf(emax, fmaxf(e0, e1));
+            // H' keeps the cells whose estimate at med5(J) may exceed sigclip
+            const uint32_t drop = (!(s0 + e0 > sc_lo) ? 1u << (cc & 31) : 0u) |
+                                  (!(s1 + e1 > sc_lo) ? 1u << ((cc + 1) & 31) : 0u);
+            // S may exceed sigfrac * sigclip here (the cell's own bound)
+            const uint32_t low = (s0 + e0 > ll_lo ? 1u << (cx & 31) : 0u) |
+                                 (s1 + e1 > ll_lo ? 1u << ((cx + 1) & 31) : 0u);
+            uint32_t *hw = &sHot[rr * L::HWP + (cc >> 5)];
+            if (drop & *hw)
+                atomicAnd(hw, ~drop);
+            if (tile_row && low)
+                atomicOr(&sLow[cy * L::QW + (cx >> 5)], low);
+            if (counting)
+                ncells += tile_row ? 2u : 0u;
+        };
+        // Wave w takes the list's entries 64 w, 64 w + 256, ...: one quad per lane (the
+        // 2 x 2 network) while more than 32 remain, and a last run of at most 32 quads
+        // two lanes per quad, one row each (the 1 x 2 network and two estimates, about
+        // 60% of a quad's instructions), as most tiles end their list with such a run.
 #pragma unroll 1
-        for (int it = tid; it < nquads; it += NT) {
-            const int q = (int)sQuads[it];
-            const int pr = q / L::SW, cc = q - pr * L::SW, r0 = 2 * pr;
-            float v[6 * 6];
+        for (int q0 = tid - lane; q0 < nquads; q0 += NT) {
+            const int left = nquads - q0;                 // uniform in the wave
+            if (left > 32) {
+                if (lane < left) {
+                    const int q = (int)sQuads[q0 + lane];
+                    const int pr = q / L::SW, cc = q - pr * L::SW, r0 = 2 * pr;
+                    float v[6 * 6];
 #pragma unroll
-            for (int i = 0; i < 6; ++i)
+                    for (int i = 0; i < 6; ++i)
 #pragma unroll
-                for (int j = 0; j < 6; ++j)
-                    v[i * 6 + j] = sJ[(r0 + i) * L::JWP + cc + j];
-            float m5[4];
-            med5_t2x2(v, m5);
-            // a quad's two columns (cc even) share their word of each bitmap, and lie both
-            // inside the tile's columns or both outside
-            const int cx = cc - 2;
-            const bool tile_cols = cx >= 0 && cx < TX;
+                        for (int j = 0; j < 6; ++j)
+                            v[i * 6 + j] = sJ[(r0 + i) * L::JWP + cc + j];
+                    float m5[4];
+                    med5_t2x2(v, m5);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int rr = r0 + i, cy = rr - 2;
-                const bool tile_row = tile_cols && cy >= 0 && cy < TY;
-                uint32_t drop = 0u, low = 0u;
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    const int pc = (i + 2) * 6 + (j + 2);
-                    float err;
-                    const float s = s_estimate(v[pc], v[pc - 6], v[pc + 6], v[pc - 1],
-                                               v[pc + 1], m5[i * 2 + j], sp, err);
-                    sS[rr * L::SWP + cc + j] = s;
-                    emax = fmaxf(emax, err);
-                    // H' keeps the cells whose estimate at med5(J) may exceed sigclip
-                    drop |= !(s + err > sc_lo) ? 1u << ((cc + j) & 31) : 0u;
-                    // S may exceed sigfrac * sigclip here (the cell's own bound)
-                    low |= s + err > ll_lo ? 1u << ((cx + j) & 31) : 0u;
+                    for (int i = 0; i < 2; ++i) {
+                        constexpr int P = 6;
+                        const int pc = (i + 2) * P + 2;
+                        exact_row(r0 + i, cc, v[pc - P], v[pc + 1 - P], v[pc - 1], v[pc],
+                                  v[pc + 1], v[pc + 2], v[pc + P], v[pc + 1 + P], m5[2 * i],
+                                  m5[2 * i + 1]);
+                    }
                 }
-                uint32_t *hw = &sHot[rr * L::HWP + (cc >> 5)];
-                if (drop & *hw)
-                    atomicAnd(hw, ~drop);
-                if (tile_row && low)
-                    atomicOr(&sLow[cy * L::QW + (cx >> 5)], low);
-                if (counting)
-                    ncells += tile_row ? 2u : 0u;
+            } else if (lane < 2 * left) {
+                const int q = (int)sQuads[q0 + (lane >> 1)];
+                const int pr = q / L::SW, cc = q - pr * L::SW, rr = 2 * pr + (lane & 1);
+                float v[5 * 6];
+#pragma unroll
+                for (int i = 0; i < 5; ++i)
+#pragma unroll
+                    for (int j = 0; j < 6; ++j)
+                        v[i * 6 + j] = sJ[(rr + i) * L::JWP + cc + j];
+                float m5[2];
+                med5_t1x2(v, m5);
+                constexpr int P = 6, pc = 2 * P + 2;
+                exact_row(rr, cc, v[pc - P], v[pc + 1 - P], v[pc - 1], v[pc], v[pc + 1],
+                          v[pc + 2], v[pc + P], v[pc + 1 + P], m5[0], m5[1]);
             }
         }
         // non-negative floats order as their bit patterns: the device library's

@@ -408,7 +408,8 @@ def emit_sort_function(name: str, n: int) -> str:
 
 
 # tile shapes used by the kernels: (function name, k, ty, tx)
-TILES = [("med5_t2x2", 5, 2, 2), ("med5_t1x1", 5, 1, 1), ("med7_t1x1", 7, 1, 1)]
+TILES = [("med5_t2x2", 5, 2, 2), ("med5_t1x2", 5, 1, 2), ("med5_t1x1", 5, 1, 1),
+         ("med7_t1x1", 7, 1, 1)]
 
 
 def generate(path: str, verify: bool = True) -> None:
