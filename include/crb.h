@@ -430,8 +430,8 @@ crb_status crb_debug_s_estimate(const float *J, const crb_frame *params, float *
  * Runs on the calling thread's stream. */
 crb_status crb_debug_s_bound(const float *J, const crb_frame *params, float *out_u);
 /* Clamped (2r+1)^2 median filter, r in {1, 2, 3}, by the kernels' networks (3x3 by
- * sorted columns, 5x5 by the network for a 2 x 2 tile of outputs, 7x7 by the
- * single-output one). */
+ * sorted columns, 5x5 by the network for a 2 x 2 tile of outputs on even pairs of rows
+ * and the one for a row of two outputs on odd pairs, 7x7 by the single-output one). */
 crb_status crb_debug_median(const float *in, int32_t H, int32_t W, int32_t r, float *out);
 /* Clamped 5x5 median filter of binary64 values by the single-output network that the
  * detection applies to its FP32 estimates of S (here on binary64 inputs). */

@@ -1173,7 +1173,8 @@ void k_detect_persistent(const DevFrame *__restrict__ frames, const TileRef *__r
 // ---------------------------------------------------------------------------
 
 // Output tile of one thread of k_debug_median: the shapes the kernels use (med3 in runs,
-// med5 in 2 x 2 quads, med7 single).
+// med5 in 2 x 2 quads, by the quad network on even tile rows and the one-row network on
+// odd ones, med7 single).
 __host__ __device__ constexpr int debug_median_ty(int r) { return r == 2 ? 2 : 1; }
 __host__ __device__ constexpr int debug_median_tx(int r) { return r == 1 ? kRun3 : (r == 2 ? 2 : 1); }
 
@@ -1203,7 +1204,23 @@ __global__ __launch_bounds__(kThreads) void k_debug_median(const float *__restri
         }
         med3_run<kRun3>(a, b, c, o);
     } else if constexpr (R == 2) {
-        med5_t2x2(v, o);
+        if (((t / ntx) & 1) == 0) {
+            med5_t2x2(v, o);
+        } else {
+            // odd tile rows: the one-row network (two outputs) on each of the two rows
+            float a[5 * PW], b[5 * PW], oa[2], ob[2];
+#pragma unroll
+            for (int i = 0; i < 5 * PW; ++i) {
+                a[i] = v[i];
+                b[i] = v[PW + i];
+            }
+            med5_t1x2(a, oa);
+            med5_t1x2(b, ob);
+            o[0] = oa[0];
+            o[1] = oa[1];
+            o[2] = ob[0];
+            o[3] = ob[1];
+        }
     } else {
         med7_t1x1(v, o);
     }
