@@ -379,11 +379,31 @@ __device__ __forceinline__ void replace_from_window(const DevFrame &f, int y, in
     }
 }
 
+// Values off .. off + 4 (off in 0..3) of the 8-value block (lo, hi): shifted by 2 when
+// bit 1 of off is set, then by 1 when bit 0 is (selects of named values: an array here
+// would be indexed through scratch memory).
+__device__ __forceinline__ void window_row(float4 lo, float4 hi, int off, float &o0, float &o1,
+                                           float &o2, float &o3, float &o4) {
+    const bool s2 = (off & 2) != 0, s1 = (off & 1) != 0;
+    const float h0 = s2 ? lo.z : lo.x, h1 = s2 ? lo.w : lo.y, h2 = s2 ? hi.x : lo.z;
+    const float h3 = s2 ? hi.y : lo.w, h4 = s2 ? hi.z : hi.x, h5 = s2 ? hi.w : hi.y;
+    o0 = s1 ? h1 : h0;
+    o1 = s1 ? h2 : h1;
+    o2 = s1 ? h3 : h2;
+    o3 = s1 ? h4 : h3;
+    o4 = s1 ? h5 : h4;
+}
+
 // Unflagged pixels are never written and flagged ones are never used as values, so
-// the update in place is correct within the launch.  All 25 mask bytes and all 25 J
-// values of the window are loaded unconditionally (clamped addresses are always
-// valid), so the 50 loads are in flight together; a flagged neighbour's J may be
-// rewritten meanwhile by another thread, and that value is discarded.
+// the update in place is correct within the launch.  All mask bytes and J values of the
+// window are loaded unconditionally (clamped addresses are always valid), so the loads
+// are in flight together; a flagged neighbour's J may be rewritten meanwhile by another
+// thread, and that value is discarded.  A pixel at least 2 columns from either edge
+// whose window rows lie within the frame buffer as 8-pixel blocks takes each window row
+// as the 8 values and 8 mask bytes at the 4-pixel boundary at or below x - 2 (two
+// 16-byte and two 4-byte loads, not five of each): the pixels of a wave lie far apart,
+// and every load instruction costs the cache an access per distinct line it meets.
+// Other pixels load the 25 clamped positions one by one.
 __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p, int k) {
     const int W = f.W, H = f.H;
     const int y = (int)(p / (uint32_t)W), x = (int)(p - (uint32_t)y * (uint32_t)W);
@@ -402,21 +422,53 @@ __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p, int k
             return;
     }
     float v[25];
-    uint8_t mk[25];
-#pragma unroll
-    for (int dy = -2; dy <= 2; ++dy) {
-        const size_t row = (size_t)clampi(y + dy, H) * W;
-#pragma unroll
-        for (int dx = -2; dx <= 2; ++dx) {
-            const size_t q = row + clampi(x + dx, W);
-            mk[(dy + 2) * 5 + dx + 2] = f.mask[q];
-            v[(dy + 2) * 5 + dx + 2] = f.J[q];
-        }
-    }
     uint32_t fl = 0u;
+    // the last window row's block ends within the frame: so do the others (rows clamped)
+    const size_t lastblk = (((size_t)min(y + 2, H - 1) * W + (size_t)(x - 2)) & ~(size_t)3) + 8;
+    const bool blocks = x >= 2 && x + 2 < W && lastblk <= (size_t)H * (size_t)W &&
+                        ((uintptr_t)f.J & 15u) == 0u && ((uintptr_t)f.mask & 3u) == 0u;
+    if (blocks) {
+        float4 jb[5][2];
+        uint32_t mb[5][2];
+        int off[5];
 #pragma unroll
-    for (int j = 0; j < 25; ++j)
-        fl |= mk[j] != 0 ? 1u << j : 0u;
+        for (int i = 0; i < 5; ++i) {
+            const size_t s0 = (size_t)clampi(y + i - 2, H) * W + (size_t)(x - 2);
+            const size_t a = s0 & ~(size_t)3;
+            off[i] = (int)(s0 - a);
+            const float4 *jp = reinterpret_cast<const float4 *>(f.J + a);
+            const uint32_t *mp = reinterpret_cast<const uint32_t *>(f.mask + a);
+            jb[i][0] = jp[0];
+            jb[i][1] = jp[1];
+            mb[i][0] = mp[0];
+            mb[i][1] = mp[1];
+        }
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+            window_row(jb[i][0], jb[i][1], off[i], v[i * 5], v[i * 5 + 1], v[i * 5 + 2],
+                       v[i * 5 + 3], v[i * 5 + 4]);
+            const unsigned long long m =
+                (((unsigned long long)mb[i][1] << 32) | mb[i][0]) >> (8 * off[i]);
+#pragma unroll
+            for (int j = 0; j < 5; ++j)
+                fl |= ((m >> (8 * j)) & 0xFFull) != 0ull ? 1u << (i * 5 + j) : 0u;
+        }
+    } else {
+        uint8_t mk[25];
+#pragma unroll
+        for (int dy = -2; dy <= 2; ++dy) {
+            const size_t row = (size_t)clampi(y + dy, H) * W;
+#pragma unroll
+            for (int dx = -2; dx <= 2; ++dx) {
+                const size_t q = row + clampi(x + dx, W);
+                mk[(dy + 2) * 5 + dx + 2] = f.mask[q];
+                v[(dy + 2) * 5 + dx + 2] = f.J[q];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 25; ++j)
+            fl |= mk[j] != 0 ? 1u << j : 0u;
+    }
     replace_from_window(f, y, x, v, fl, k);
 }
 __global__ __launch_bounds__(kThreads) void k_list_prefix(const DevFrame *__restrict__ frames,
