@@ -394,6 +394,40 @@ __device__ __forceinline__ void window_row(float4 lo, float4 hi, int off, float 
     o4 = s1 ? h5 : h4;
 }
 
+// Whether the 5x5 window of (y, x) can be read as aligned 8-pixel blocks, one per
+// window row: at least 2 columns from either edge, the last window row's block (rows are
+// clamped, so the lowest is the last) ends within the frame buffer, and J starts on a
+// 16-byte boundary.
+__device__ __forceinline__ bool window_blocks_ok(const DevFrame &f, int y, int x) {
+    const int W = f.W, H = f.H;
+    const size_t last = (((size_t)min(y + 2, H - 1) * W + (size_t)(x - 2)) & ~(size_t)3) + 8;
+    return x >= 2 && x + 2 < W && last <= (size_t)H * (size_t)W && ((uintptr_t)f.J & 15u) == 0u;
+}
+
+// First pixel of window row i (0..4) of (y, x), and of its aligned 8-pixel block.
+__device__ __forceinline__ size_t window_row_start(const DevFrame &f, int y, int x, int i) {
+    return (size_t)clampi(y + i - 2, f.H) * f.W + (size_t)(x - 2);
+}
+
+// J over the window of (y, x) (window_blocks_ok): two 16-byte loads a row.
+__device__ __forceinline__ void load_window_j_blocks(const DevFrame &f, int y, int x,
+                                                     float (&v)[25]) {
+    float4 jb[5][2];
+    int off[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const size_t s0 = window_row_start(f, y, x, i), a = s0 & ~(size_t)3;
+        off[i] = (int)(s0 - a);
+        const float4 *jp = reinterpret_cast<const float4 *>(f.J + a);
+        jb[i][0] = jp[0];
+        jb[i][1] = jp[1];
+    }
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        window_row(jb[i][0], jb[i][1], off[i], v[i * 5], v[i * 5 + 1], v[i * 5 + 2],
+                   v[i * 5 + 3], v[i * 5 + 4]);
+}
+
 // Unflagged pixels are never written and flagged ones are never used as values, so
 // the update in place is correct within the launch.  All mask bytes and J values of the
 // window are loaded unconditionally (clamped addresses are always valid), so the loads
@@ -423,30 +457,21 @@ __device__ __forceinline__ void replace_one(const DevFrame &f, uint32_t p, int k
     }
     float v[25];
     uint32_t fl = 0u;
-    // the last window row's block ends within the frame: so do the others (rows clamped)
-    const size_t lastblk = (((size_t)min(y + 2, H - 1) * W + (size_t)(x - 2)) & ~(size_t)3) + 8;
-    const bool blocks = x >= 2 && x + 2 < W && lastblk <= (size_t)H * (size_t)W &&
-                        ((uintptr_t)f.J & 15u) == 0u && ((uintptr_t)f.mask & 3u) == 0u;
-    if (blocks) {
-        float4 jb[5][2];
+    if (window_blocks_ok(f, y, x) && ((uintptr_t)f.mask & 3u) == 0u) {
+        // the mask bytes by the same blocks: one 8-byte load a row
         uint32_t mb[5][2];
         int off[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
-            const size_t s0 = (size_t)clampi(y + i - 2, H) * W + (size_t)(x - 2);
-            const size_t a = s0 & ~(size_t)3;
+            const size_t s0 = window_row_start(f, y, x, i), a = s0 & ~(size_t)3;
             off[i] = (int)(s0 - a);
-            const float4 *jp = reinterpret_cast<const float4 *>(f.J + a);
             const uint32_t *mp = reinterpret_cast<const uint32_t *>(f.mask + a);
-            jb[i][0] = jp[0];
-            jb[i][1] = jp[1];
             mb[i][0] = mp[0];
             mb[i][1] = mp[1];
         }
+        load_window_j_blocks(f, y, x, v);
 #pragma unroll
         for (int i = 0; i < 5; ++i) {
-            window_row(jb[i][0], jb[i][1], off[i], v[i * 5], v[i * 5 + 1], v[i * 5 + 2],
-                       v[i * 5 + 3], v[i * 5 + 4]);
             const unsigned long long m =
                 (((unsigned long long)mb[i][1] << 32) | mb[i][0]) >> (8 * off[i]);
 #pragma unroll
