@@ -395,16 +395,19 @@ __device__ __forceinline__ void window_row(float4 lo, float4 hi, int off, float 
 }
 
 // Whether the 5x5 window of (y, x) can be read as aligned 8-pixel blocks, one per
-// window row: at least 2 columns from either edge, the last window row's block (rows are
-// clamped, so the lowest is the last) ends within the frame buffer, and J starts on a
-// 16-byte boundary.
+// window row: at least 2 columns from either edge, the block of the bottom window row
+// (the largest index: rows are clamped into the frame) ends within the frame buffer, and
+// J starts on a 16-byte boundary.
 __device__ __forceinline__ bool window_blocks_ok(const DevFrame &f, int y, int x) {
     const int W = f.W, H = f.H;
+    if (x < 2 || x + 2 >= W || ((uintptr_t)f.J & 15u) != 0u)
+        return false;
     const size_t last = (((size_t)min(y + 2, H - 1) * W + (size_t)(x - 2)) & ~(size_t)3) + 8;
-    return x >= 2 && x + 2 < W && last <= (size_t)H * (size_t)W && ((uintptr_t)f.J & 15u) == 0u;
+    return last <= (size_t)H * (size_t)W;
 }
 
-// First pixel of window row i (0..4) of (y, x), and of its aligned 8-pixel block.
+// Index of the first pixel (column x - 2) of window row i (0..4) of (y, x); that row's
+// block starts at the multiple of 4 at or below it.
 __device__ __forceinline__ size_t window_row_start(const DevFrame &f, int y, int x, int i) {
     return (size_t)clampi(y + i - 2, f.H) * f.W + (size_t)(x - 2);
 }
